@@ -1,0 +1,202 @@
+#!/usr/bin/env python3
+"""Benchmark of the EDAA hot path on one MI355X.
+
+Workload (one "step"): the batched ensemble on the Urban-shaped synthetic scene
+-- L = 162 bands, N = 307 x 307 = 94249 pixels, p = 6, M = 50 runs (10 seeds x
+gamma in {0.25, 0.5, 1, 2, 4}), T = 100 outer iterations, K1 = K2 = 5 --
+including the per-pixel normalisation of the raw scene, B0/A0 initialisation,
+step sizes, the 100 x (1 + 5) passes over X, the closing pass, coherence and
+the Algorithm 2 selection.  Inputs are resident in device memory before the
+timed region starts.
+
+Printed: one JSON line with run-iterations/s (M * T per step), the
+algorithmic HBM rate, the roofline of the dominant kernel (the B-pass, timed
+with HIP events recorded around each of its launches on its launch stream),
+the plain path (single runs on the same data, at equal final loss) and the
+float64 oracle timed on this host's cores on a bounded sample.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+FP32_VECTOR_FMA_TFLOPS = 78.6     # 256 CU x 64 FMA lanes x 2 flop x 2.4 GHz (no packed FP32)
+HBM_GBS = 8000.0
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(Xraw, p, seed, gamma, T_sample):
+    """The float64 oracle as it stands, on the same scene, for T_sample outer
+    iterations of one run; returns run-iterations/s and the threads used."""
+    import numpy as np
+    from oracle import edaa as O
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    except Exception:
+        threads = 1
+    X, _ = O.normalize_pixels(Xraw.astype(np.float64))
+    t0 = time.perf_counter()
+    O.edaa_fit(X, p, T=T_sample, gamma=gamma, seed=seed)
+    dt = time.perf_counter() - t0
+    return T_sample / dt, threads, dt
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--plain-runs", type=int, default=5, help="single runs timed for the plain path (0: skip)")
+    ap.add_argument("--cpu-sample-T", type=int, default=3, help="oracle outer iterations timed (0: skip)")
+    ap.add_argument("--n-seeds", type=int, default=10)
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(run it with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2209_11002_amd import api, synth
+
+    dev = torch.device("cuda:0")
+    scene, cfg = synth.urban_ensemble(n_seeds=args.n_seeds)
+    L, N = scene.X.shape
+    p, T, K1, K2 = 6, cfg["T"], cfg["K1"], cfg["K2"]
+    seeds, gammas = cfg["seeds"], cfg["gammas"]
+    M = len(seeds)
+    log(f"scene L={L} N={N} p={p} M={M} T={T}")
+    Xraw = torch.from_numpy(scene.X).to(dev)
+    out = dict(A=torch.empty((M, p, N), device=dev), B=torch.empty((M, N, p), device=dev),
+               E=torch.empty((M, L, p), device=dev))
+
+    def step(graph=False, time_passes=False):
+        Xn = api.normalize_pixels(Xraw)
+        return api.ensemble(Xn, p, seeds, gammas, T=T, K1=K1, K2=K2, graph=graph, out=out,
+                            time_passes=time_passes)
+
+    for w in range(args.warmup):
+        step(time_passes=True)
+        step(graph=True)
+        log(f"warmup {w + 1}/{args.warmup} done")
+    torch.cuda.synchronize()
+
+    # Timed region: eager launches, with HIP events recorded around every pass
+    # launch on the library's stream (events inside a replayed graph carry no
+    # timestamps on this runtime).
+
+    b_ms, b_n, a_ms, a_n = 0.0, 0, 0.0, 0
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        r = step(time_passes=True)
+        n, ms = api.pass_times(dev, 1)
+        b_n += n
+        b_ms += ms
+        n, ms = api.pass_times(dev, 0)
+        a_n += n
+        a_ms += ms
+        log(f"step {k + 1}/{args.steps} done")
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ms_per_step = 1e3 * dt / args.steps
+    value = M * T * args.steps / dt
+
+    # the same steps replayed from the captured HIP graph (no events)
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        rg = step(graph=True)
+    torch.cuda.synchronize()
+    gdt = time.perf_counter() - t0
+    value_graph = M * T * args.steps / gdt
+    assert np.array_equal(rg["loss"], r["loss"]), "graph replay differs from eager launches"
+    log(f"graph replay: {value_graph:.1f} run-it/s")
+
+    # algorithmic bytes and flops (float32 state, X read once per pass)
+    Q = M * p
+    xb = L * N * 4
+    bpass_bytes = xb + 2 * Q * N * 4
+    bpass_flops = 4.0 * L * N * Q
+    apass_bytes = xb + 2 * Q * N * 4
+    step_bytes = (2 * xb                       # normalisation
+                  + xb + 2 * Q * N * 4         # A0 fill + init pass (writes B)
+                  + T * (apass_bytes + K2 * bpass_bytes)
+                  + xb + Q * N * 4             # closing pass
+                  + 2 * Q * N * 4)             # B output
+    b_avg_s = b_ms / max(b_n, 1) / 1e3
+    a_avg_s = a_ms / max(a_n, 1) / 1e3
+    achieved = bpass_flops / b_avg_s / 1e12
+    roofline = dict(bound="alu", achieved=round(achieved, 3), peak=FP32_VECTOR_FMA_TFLOPS, unit="TFLOP/s",
+                    frac=round(achieved / FP32_VECTOR_FMA_TFLOPS, 4), traffic=None,
+                    kernel="k_bpass (B-pass)", avg_launch_us=round(b_avg_s * 1e6, 2),
+                    algorithmic_bytes_per_launch=bpass_bytes, flops_per_launch=bpass_flops,
+                    achieved_gbs=round(bpass_bytes / b_avg_s / 1e9, 1),
+                    apass_avg_launch_us=round(a_avg_s * 1e6, 2))
+    final_loss_batched = r["loss"][:, -1].copy()
+    log(f"batched: {value:.1f} run-it/s, {ms_per_step:.1f} ms/step, B-pass {b_avg_s * 1e6:.1f} us")
+
+    plain = None
+    if args.plain_runs > 0:
+        Xn = api.normalize_pixels(Xraw)
+        api.fit(Xn, p, T=T, gamma=gammas[0], seed=seeds[0], graph=True)   # capture
+        torch.cuda.synchronize()
+        losses = []
+        t0 = time.perf_counter()
+        for m in range(args.plain_runs):
+            rr = api.fit(Xn, p, T=T, K1=K1, K2=K2, gamma=gammas[m], seed=seeds[m], graph=True)
+            losses.append(rr["loss"][-1])
+        torch.cuda.synchronize()
+        pdt = time.perf_counter() - t0
+        pval = args.plain_runs * T / pdt
+        rel = float(np.max(np.abs(np.array(losses) - final_loss_batched[:args.plain_runs])
+                           / final_loss_batched[:args.plain_runs]))
+        plain = dict(value=round(pval, 2), unit="run-iterations/s", runs=args.plain_runs,
+                     batched_speedup=round(value / pval, 2), final_loss_max_rel_diff=rel)
+        log(f"plain: {pval:.1f} run-it/s (speedup {value / pval:.2f}x, final-loss rel diff {rel:.2e})")
+
+    cpu = None
+    if args.cpu_sample_T > 0:
+        log("timing the float64 oracle on the host")
+        v, threads, cdt = cpu_baseline(scene.X, p, seeds[0], gammas[0], args.cpu_sample_T)
+        cpu = dict(value=round(v, 4), unit="run-iterations/s", cores=threads, kind="oracle",
+                   sample=f"1 run x {args.cpu_sample_T} outer iterations (K1=K2=5) of the float64 oracle "
+                          f"on the full {L}x{N} scene, {cdt:.1f} s")
+        log(f"oracle: {v:.4f} run-it/s on {threads} threads")
+
+    line = {
+        "metric": "EDAA run-iterations/sec + HBM GB/s; batched vs plain at equal loss",
+        "value": round(value, 2),
+        "unit": "run-iterations/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"batched EDAA ensemble, Urban-shaped synthetic scene L={L} N={N} (307x307) "
+                               f"p={p}, M={M} runs (seeds x gamma 0.25..4), T={T}, K1={K1}, K2={K2}, "
+                               f"Dirichlet(0.7) abundances, noise sigma 0.02",
+                   "L": L, "N": N, "p": p, "M": M, "T": T, "K1": K1, "K2": K2},
+        "hbm_gbs": round(step_bytes / (ms_per_step / 1e3) / 1e9, 1),
+        "value_graph_replay": round(value_graph, 2),
+        "roofline": roofline,
+        "plain": plain,
+        "cpu_baseline": cpu,
+        "selected_run": int(r["selected"]),
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

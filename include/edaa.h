@@ -1,0 +1,206 @@
+/*
+ * edaa.h -- C ABI of the MI355X (gfx950) library for Entropic Descent
+ * Archetypal Analysis (EDAA, arXiv 2209.11002).
+ *
+ * The library minimises the archetypal-analysis objective
+ *      1/2 || X - X B A ||_F^2
+ * over A (p x N, every column on the simplex Delta_p) and B (N x p, every
+ * column on Delta_N) with the alternating entropic (mirror) steps of the
+ * paper's Algorithm 1, runs ensembles of seeded runs and selects one with the
+ * paper's Algorithm 2.
+ *
+ * Conventions shared by every call
+ *   - Arrays are row-major C arrays.  X is [L][N] (one pixel per column,
+ *     element (l, i) at l*N + i), A is [p][N], B is [N][p], E = X B is [L][p].
+ *     Ensemble outputs stack runs first: A_all [M][p][N], B_all [M][N][p],
+ *     E_all [M][L][p].
+ *   - Pointers documented "device" are device memory of the context's GPU;
+ *     "host" pointers are ordinary host memory.  The caller allocates and owns
+ *     every input and output; the context owns (and reuses) its workspace.
+ *   - Work is enqueued on the stream given to edaa_create.  A call that fills
+ *     a host array synchronises that stream before it returns.
+ *   - A context is not thread safe: use one context per host thread/stream.
+ *   - Errors: every call validates its arguments before enqueuing anything
+ *     and returns EDAA_EINVAL (nothing enqueued) on a bad one; the message is
+ *     available from edaa_last_error() on the calling thread.  A HIP runtime
+ *     failure returns EDAA_EDEVICE and poisons the context (later calls on it
+ *     return EDAA_EDEVICE).
+ *   - Sizes: 1 <= p <= 16, p <= N, 1 <= L <= 512, N < 2^31 / (M p).
+ */
+#ifndef EDAA_H
+#define EDAA_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct edaa_ctx edaa_ctx;
+
+typedef enum {
+    EDAA_OK = 0,
+    EDAA_EINVAL = -1,        /* invalid argument; nothing was enqueued          */
+    EDAA_ENOMEM = -2,        /* device workspace could not be allocated         */
+    EDAA_EDEVICE = -3,       /* HIP runtime error; the context is poisoned      */
+    EDAA_ENUMERIC = -4,      /* non-finite result (every run of an ensemble)    */
+    EDAA_EUNSUPPORTED = -5   /* valid request outside what the library supports */
+} edaa_status;
+
+enum { EDAA_X_F32 = 0, EDAA_X_BF16 = 1 };                   /* storage type of X      */
+enum { EDAA_COHERENCE_COSINE = 0, EDAA_COHERENCE_RAW = 1 }; /* reading of eq. coherence */
+enum {
+    EDAA_FLAG_GRAPH = 1,     /* record the whole run sequence in a HIP graph once
+                                per (shape, buffers) and replay it afterwards */
+    EDAA_FLAG_TIME_PASSES = 2 /* record HIP events around every A-pass, B-pass
+                                and closing-pass launch (eager launches only;
+                                see edaa_pass_times) */
+};
+
+/* Parameters of Algorithm 1 / Algorithm 2.  edaa_default_params fills the
+ * paper's values: T = 100, K1 = K2 = 5 (Section "Implementation details",
+ * paragraph "Hyperparameters"), gamma = 1 (an element of the set S of
+ * eq. eta0A), init_scale = 0.1 (eq. initB0), select_threshold = 1.05
+ * (Algorithm 2). */
+typedef struct {
+    int T, K1, K2;           /* outer iterations, A-steps and B-steps per outer  */
+    double gamma;            /* eta1 = gamma / sigma_max^2(X B0), eq. eta0A      */
+    double eta1, eta2;       /* > 0: explicit step sizes (resume, tests);
+                                0: the paper's rule (eq. eta0A, eq. eta0B)       */
+    double init_scale;       /* B0 = column softmax(init_scale * U), eq. initB0  */
+    double select_threshold; /* Algorithm 2: keep fit_m <= threshold * fit_min   */
+    int x_dtype;             /* EDAA_X_F32 or EDAA_X_BF16                        */
+    int coherence_mode;      /* EDAA_COHERENCE_COSINE (default) or _RAW          */
+    int flags;               /* EDAA_FLAG_*                                      */
+} edaa_params;
+
+/* One image of a ragged batch (edaa_fit_ragged).  All pointers are device
+ * pointers with the layouts above; loss_trace is a host array of T+1. */
+typedef struct {
+    const void* X;           /* [L][N], l2-normalised, dtype params->x_dtype     */
+    int L, N, p;
+    uint64_t seed;           /* B0 draw, see edaa_fit                             */
+    double gamma;
+    float* A;                /* out [p][N]                                        */
+    float* B;                /* out [N][p]                                        */
+    float* E;                /* out [L][p], may be NULL                           */
+    double* loss_trace;      /* out, host, T+1 values, may be NULL               */
+} edaa_image_desc;
+
+/* Fill *params with the paper's defaults (see edaa_params). */
+void edaa_default_params(edaa_params* params);
+
+/* Create a context on HIP device `device`; `stream` is a hipStream_t (NULL
+ * for the device's null stream).  *out receives the context. */
+edaa_status edaa_create(edaa_ctx** out, int device, void* stream);
+
+/* Release the context and its workspace (no-op on NULL). */
+void edaa_destroy(edaa_ctx* ctx);
+
+/* Message of the last error on the calling thread ("" if none). */
+const char* edaa_last_error(void);
+
+/* Number of kernel launches the last edaa_fit / edaa_ensemble call enqueued
+ * (graph replays count the kernels inside the graph). */
+long long edaa_last_launch_count(edaa_ctx* ctx);
+
+/* Durations of the pass kernels of the last edaa_fit / edaa_ensemble call made
+ * with EDAA_FLAG_TIME_PASSES, from HIP events recorded on the launch stream
+ * immediately before and after each launch.  Timing applies to eager launches
+ * only: a call that also sets EDAA_FLAG_GRAPH records nothing (count 0).
+ * kind: 0 A-pass, 1 B-pass, 2 closing pass.
+ * *count receives the number of launches of that kind, *total_ms their summed
+ * durations.  Synchronises the context stream. */
+edaa_status edaa_pass_times(edaa_ctx* ctx, int kind, int* count, double* total_ms);
+
+/* Per-pixel l2 normalisation of the paper's eq. normalization:
+ * x_i <- x_i / ||x_i||_2 for every column i of X_in [L][N] (device, float32).
+ * The result goes to X_out (device, [L][N], dtype out_dtype; X_out may equal
+ * X_in when out_dtype is EDAA_X_F32).  A pixel of zero norm is written as
+ * zeros; if n_zero (host) is not NULL it receives their number and the call
+ * synchronises. */
+edaa_status edaa_normalize_pixels(edaa_ctx* ctx, const float* X_in, void* X_out,
+                                  int L, int N, int out_dtype, int* n_zero);
+
+/* One EDAA run (Algorithm 1) on l2-normalised X [L][N] (device, dtype
+ * params->x_dtype).
+ *   A0, B0   optional starting points (device, [p][N] and [N][p]; NULL selects
+ *            eq. initA0 and eq. initB0).  B0 from the seed is
+ *            softmax_columns(init_scale * u) with u[i][j] the Philox4x64-10
+ *            draw (Salmon et al., SC'11): word j%4 of the block for counter
+ *            (i, j/4, 0, 0) and key (seed, 0), mapped to [0,1) as
+ *            (word >> 40) * 2^-24.
+ *   A, B     out (device): final abundances [p][N] and pixel weights [N][p].
+ *   E        out (device, may be NULL): endmembers X B, [L][p].
+ *   loss_trace out (host, may be NULL): T+1 values, loss_trace[0] is
+ *            1/2||X - X B0 A0||^2 and loss_trace[t] the objective after outer
+ *            iteration t.
+ *   eta_out  out (host, may be NULL): {eta1, eta2} used.
+ * Returns EDAA_ENUMERIC if the final objective is not finite. */
+edaa_status edaa_fit(edaa_ctx* ctx, const void* X, int L, int N, int p,
+                     const edaa_params* params, uint64_t seed,
+                     const float* A0, const float* B0,
+                     float* A, float* B, float* E,
+                     double* loss_trace, double* eta_out);
+
+/* M runs of Algorithm 1 on the same X, all advanced together (one pass over
+ * X serves every run), then the l1 fit ||X - E_m A_m||_1 (entrywise), the
+ * coherence mu_m of E_m (eq. coherence, reading params->coherence_mode) and
+ * the selection of Algorithm 2 (edaa_select).
+ *   seeds, gammas  host arrays of M: run m draws B0 from seeds[m] (see
+ *                  edaa_fit) and uses gamma gammas[m].
+ *   A_all, B_all   out (device) [M][p][N], [M][N][p].
+ *   E_all          out (device, may be NULL) [M][L][p].
+ *   loss           out (host, may be NULL) [M][T+1].
+ *   fit, mu        out (host, may be NULL) [M].
+ *   run_status     out (host, may be NULL) [M]: EDAA_OK or EDAA_ENUMERIC.
+ *   selected       out (host, may be NULL): selected run, -1 if none.
+ * Returns EDAA_ENUMERIC when no run has a finite objective. */
+edaa_status edaa_ensemble(edaa_ctx* ctx, const void* X, int L, int N, int p,
+                          const edaa_params* params, int M,
+                          const uint64_t* seeds, const double* gammas,
+                          float* A_all, float* B_all, float* E_all,
+                          double* loss, double* fit, double* mu,
+                          int* run_status, int* selected);
+
+/* Independent EDAA runs (Algorithm 1) on n_images images of different
+ * (L, N, p), all advanced together: each pass is one launch over the
+ * concatenated pixel tiles of every image.  params->T, K1, K2, init_scale and
+ * x_dtype apply to every image; gamma and seed come from each descriptor. */
+edaa_status edaa_fit_ragged(edaa_ctx* ctx, int n_images, const edaa_image_desc* images,
+                            const edaa_params* params);
+
+/* Objective 1/2||X - X B A||_F^2 (eq. AA) for X [L][N] float32, A [p][N],
+ * B [N][p] (all device); the float32 result is written to loss_dev (device,
+ * one float). */
+edaa_status edaa_loss_fwd(edaa_ctx* ctx, const float* X, const float* A, const float* B,
+                          int L, int N, int p, float* loss_dev);
+
+/* Gradients of grad_out * 1/2||X - X B A||^2 (the derivatives that eq. update_A
+ * and eq. update_B step along, with the opposite sign):
+ *   gA = grad_out * (X B)^T (X B A - X)          [p][N] (device)
+ *   gB = grad_out * X^T (X B A - X) A^T          [N][p] (device)
+ * grad_out is a device float (the incoming gradient of the loss). */
+edaa_status edaa_loss_bwd(edaa_ctx* ctx, const float* X, const float* A, const float* B,
+                          int L, int N, int p, const float* grad_out,
+                          float* gA, float* gB);
+
+/* Mirror step of eq. update_softmax on every column of A [p][N] (device, in
+ * place): a <- softmax(log a - eta gA) over the p entries of the column. */
+edaa_status edaa_mirror_step_A(edaa_ctx* ctx, float* A, const float* gA, int p, int N, float eta);
+
+/* Mirror step on every column of B [N][p] (device, in place):
+ * b_j <- softmax(log b_j - eta gB_j) over the N entries of column j. */
+edaa_status edaa_mirror_step_B(edaa_ctx* ctx, float* B, const float* gB, int N, int p, float eta);
+
+/* Algorithm 2 selection on host arrays of M values: fit_min over finite fits,
+ * I = {m : fit[m] <= threshold * fit_min}, returns argmin over I of mu (lowest
+ * index on ties, a finite mu beats NaN), or -1 if no fit is finite.  Pure host
+ * function, needs no context. */
+int edaa_select(const double* fit, const double* mu, int M, double threshold);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* EDAA_H */

@@ -1,0 +1,237 @@
+"""Python binding of the EDAA library (arXiv 2209.11002) for PyTorch-ROCm.
+
+Argument marshalling only: every step of the method runs in the HIP kernels
+of libedaa.so.  PyTorch provides device memory (tensors) and the stream (the
+current torch stream of the tensor's device).  Layouts follow include/edaa.h:
+X [L][N], A [p][N], B [N][p], E [L][p]; ensembles stack runs first.
+"""
+import ctypes
+from ctypes import byref, c_double, c_int, c_uint64
+
+import numpy as np
+import torch
+
+from . import _lib as L_
+from ._lib import EdaaError, check  # noqa: F401  (re-exported)
+
+_contexts = {}
+
+
+def _ctx(device):
+    """One library context per (device, torch stream)."""
+    dev = torch.device(device)
+    idx = dev.index if dev.index is not None else torch.cuda.current_device()
+    stream = torch.cuda.current_stream(idx)
+    key = (idx, stream.cuda_stream)
+    c = _contexts.get(key)
+    if c is None:
+        lib = L_.load()
+        h = ctypes.c_void_p()
+        check(lib.edaa_create(byref(h), idx, ctypes.c_void_p(stream.cuda_stream)))
+        c = h
+        _contexts[key] = c
+    return c
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def _x_dtype(X):
+    if X.dtype == torch.float32:
+        return L_.EDAA_X_F32
+    if X.dtype == torch.bfloat16:
+        return L_.EDAA_X_BF16
+    raise TypeError(f"X must be float32 or bfloat16, got {X.dtype}")
+
+
+def _check_x(X):
+    if not (X.is_cuda and X.dim() == 2 and X.is_contiguous()):
+        raise ValueError("X must be a contiguous 2-D [L, N] GPU tensor")
+    return X.shape[0], X.shape[1]
+
+
+def _params(T, K1, K2, gamma, eta, init_scale, threshold, x_dtype, coherence, graph, time_passes=False):
+    P = L_.default_params()
+    P.T, P.K1, P.K2 = int(T), int(K1), int(K2)
+    P.gamma = float(gamma)
+    if eta is not None:
+        P.eta1, P.eta2 = float(eta[0]), float(eta[1])
+    P.init_scale = float(init_scale)
+    P.select_threshold = float(threshold)
+    P.x_dtype = x_dtype
+    P.coherence_mode = {"cosine": L_.EDAA_COHERENCE_COSINE, "raw": L_.EDAA_COHERENCE_RAW}[coherence]
+    P.flags = (L_.EDAA_FLAG_GRAPH if graph else 0) | (L_.EDAA_FLAG_TIME_PASSES if time_passes else 0)
+    return P
+
+
+def normalize_pixels(X, out_dtype=torch.float32, count_zero=False):
+    """eq. normalization on the GPU: every pixel (column) of X [L, N] float32
+    divided by its l2 norm; returns a new tensor of dtype out_dtype
+    (float32 or bfloat16) and, with count_zero, the number of zero pixels."""
+    Lb, N = _check_x(X)
+    if X.dtype != torch.float32:
+        raise TypeError("normalize_pixels takes float32 input")
+    out = torch.empty((Lb, N), dtype=out_dtype, device=X.device)
+    od = L_.EDAA_X_BF16 if out_dtype == torch.bfloat16 else L_.EDAA_X_F32
+    nz = c_int(0)
+    check(L_.load().edaa_normalize_pixels(_ctx(X.device), _ptr(X), _ptr(out), Lb, N, od,
+                                          byref(nz) if count_zero else None))
+    return (out, nz.value) if count_zero else out
+
+
+def fit(X, p, T=100, K1=5, K2=5, gamma=1.0, seed=0, A0=None, B0=None, eta=None,
+        init_scale=0.1, graph=False, time_passes=False):
+    """One run of Algorithm 1 on l2-normalised X [L, N] (float32 or bfloat16,
+    on the GPU).  Returns a dict: A [p, N], B [N, p], E [L, p] (tensors),
+    loss (numpy, T+1), eta1, eta2."""
+    Lb, N = _check_x(X)
+    dev = X.device
+    A = torch.empty((p, N), dtype=torch.float32, device=dev)
+    B = torch.empty((N, p), dtype=torch.float32, device=dev)
+    E = torch.empty((Lb, p), dtype=torch.float32, device=dev)
+    for name, t, shp in (("A0", A0, (p, N)), ("B0", B0, (N, p))):
+        if t is not None and (t.dtype != torch.float32 or tuple(t.shape) != shp or not t.is_contiguous()):
+            raise ValueError(f"{name} must be a contiguous float32 tensor of shape {shp}")
+    trace = (c_double * (T + 1))()
+    eta_out = (c_double * 2)()
+    P = _params(T, K1, K2, gamma, eta, init_scale, 1.05, _x_dtype(X), "cosine", graph, time_passes)
+    lib = L_.load()
+    st = lib.edaa_fit(_ctx(dev), _ptr(X), Lb, N, p, byref(P), c_uint64(seed), _ptr(A0), _ptr(B0),
+                      _ptr(A), _ptr(B), _ptr(E), trace, eta_out)
+    if st not in (L_.EDAA_OK, L_.EDAA_ENUMERIC):
+        check(st)
+    return dict(A=A, B=B, E=E, loss=np.array(trace[:]), eta1=eta_out[0], eta2=eta_out[1],
+                status=st, launches=lib.edaa_last_launch_count(_ctx(dev)))
+
+
+def ensemble(X, p, seeds, gammas, T=100, K1=5, K2=5, coherence="cosine", threshold=1.05,
+             init_scale=0.1, graph=False, out=None, time_passes=False):
+    """M runs of Algorithm 1 advanced together plus Algorithm 2.  Returns a
+    dict with A [M, p, N], B [M, N, p], E [M, L, p] (tensors), loss [M, T+1],
+    fit [M], mu [M], status [M] (numpy) and the selected run index."""
+    Lb, N = _check_x(X)
+    M = len(seeds)
+    if len(gammas) != M:
+        raise ValueError("seeds and gammas must have the same length")
+    dev = X.device
+    if out is None:
+        out = dict(A=torch.empty((M, p, N), dtype=torch.float32, device=dev),
+                   B=torch.empty((M, N, p), dtype=torch.float32, device=dev),
+                   E=torch.empty((M, Lb, p), dtype=torch.float32, device=dev))
+    sd = (c_uint64 * M)(*[int(s) for s in seeds])
+    gm = (c_double * M)(*[float(g) for g in gammas])
+    loss = np.zeros((M, T + 1))
+    fitv = np.zeros(M)
+    mu = np.zeros(M)
+    status = np.zeros(M, dtype=np.int32)
+    sel = c_int(-1)
+    P = _params(T, K1, K2, 1.0, None, init_scale, threshold, _x_dtype(X), coherence, graph, time_passes)
+    lib = L_.load()
+    dp = lambda a: a.ctypes.data_as(ctypes.POINTER(c_double))  # noqa: E731
+    st = lib.edaa_ensemble(_ctx(dev), _ptr(X), Lb, N, p, byref(P), M, sd, gm,
+                           _ptr(out["A"]), _ptr(out["B"]), _ptr(out["E"]),
+                           dp(loss), dp(fitv), dp(mu), status.ctypes.data_as(ctypes.POINTER(c_int)), byref(sel))
+    if st not in (L_.EDAA_OK, L_.EDAA_ENUMERIC):
+        check(st)
+    return dict(A=out["A"], B=out["B"], E=out["E"], loss=loss, fit=fitv, mu=mu, status=status,
+                selected=sel.value, launches=lib.edaa_last_launch_count(_ctx(dev)))
+
+
+def fit_ragged(images, ps, seeds, gammas, T=100, K1=5, K2=5, init_scale=0.1):
+    """Independent runs of Algorithm 1 on images of different (L, N, p).
+    images: list of l2-normalised [L_k, N_k] GPU tensors (one dtype).
+    Returns a list of dicts like fit()."""
+    n = len(images)
+    descs = (L_.EdaaImageDesc * n)()
+    outs, traces = [], []
+    for k, X in enumerate(images):
+        Lb, N = _check_x(X)
+        p = int(ps[k])
+        o = dict(A=torch.empty((p, N), dtype=torch.float32, device=X.device),
+                 B=torch.empty((N, p), dtype=torch.float32, device=X.device),
+                 E=torch.empty((Lb, p), dtype=torch.float32, device=X.device))
+        tr = (c_double * (T + 1))()
+        d = descs[k]
+        d.X, d.L, d.N, d.p = X.data_ptr(), Lb, N, p
+        d.seed, d.gamma = int(seeds[k]), float(gammas[k])
+        d.A, d.B, d.E = o["A"].data_ptr(), o["B"].data_ptr(), o["E"].data_ptr()
+        d.loss_trace = tr
+        outs.append(o)
+        traces.append(tr)
+    P = _params(T, K1, K2, 1.0, None, init_scale, 1.05, _x_dtype(images[0]), "cosine", False)
+    check(L_.load().edaa_fit_ragged(_ctx(images[0].device), n, descs, byref(P)))
+    for o, tr in zip(outs, traces):
+        o["loss"] = np.array(tr[:])
+    return outs
+
+
+def pass_times(device, kind):
+    """(launch count, summed milliseconds) of the A-pass (kind 0), B-pass (1)
+    or closing pass (2) kernels of the last fit/ensemble call made with
+    time_passes=True on this device's current stream."""
+    n = c_int(0)
+    ms = c_double(0.0)
+    check(L_.load().edaa_pass_times(_ctx(device), int(kind), byref(n), byref(ms)))
+    return n.value, ms.value
+
+
+def loss_fwd(X, A, B):
+    """1/2 ||X - X B A||_F^2 as a 0-d float32 GPU tensor."""
+    Lb, N = _check_x(X)
+    p = A.shape[0]
+    out = torch.empty((), dtype=torch.float32, device=X.device)
+    check(L_.load().edaa_loss_fwd(_ctx(X.device), _ptr(X), _ptr(A), _ptr(B), Lb, N, p, _ptr(out)))
+    return out
+
+
+def loss_bwd(X, A, B, grad_out):
+    """(dA, dB) of grad_out * 1/2 ||X - X B A||^2; grad_out is a 0-d GPU tensor."""
+    Lb, N = _check_x(X)
+    p = A.shape[0]
+    gA = torch.empty_like(A)
+    gB = torch.empty_like(B)
+    go = grad_out.detach().to(dtype=torch.float32).reshape(()).contiguous()
+    check(L_.load().edaa_loss_bwd(_ctx(X.device), _ptr(X), _ptr(A), _ptr(B), Lb, N, p, _ptr(go),
+                                  _ptr(gA), _ptr(gB)))
+    return gA, gB
+
+
+def mirror_step_A(A, gA, eta):
+    """In place: every column of A [p, N] <- softmax(log a - eta gA)."""
+    p, N = A.shape
+    check(L_.load().edaa_mirror_step_A(_ctx(A.device), _ptr(A), _ptr(gA), p, N, float(eta)))
+    return A
+
+
+def mirror_step_B(B, gB, eta):
+    """In place: every column of B [N, p] <- softmax over N of (log b - eta gB)."""
+    N, p = B.shape
+    check(L_.load().edaa_mirror_step_B(_ctx(B.device), _ptr(B), _ptr(gB), N, p, float(eta)))
+    return B
+
+
+class ReconLoss(torch.autograd.Function):
+    """f(A, B) = 1/2 ||X - X B A||_F^2 with the library's hand-written backward
+    (dA = (XB)^T (XBA - X), dB = X^T (XBA - X) A^T).  X carries no gradient."""
+
+    @staticmethod
+    def forward(ctx, X, A, B):
+        A = A.contiguous()
+        B = B.contiguous()
+        ctx.save_for_backward(X, A, B)
+        return loss_fwd(X, A, B)
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        X, A, B = ctx.saved_tensors
+        gA, gB = loss_bwd(X, A, B, grad_out)
+        return None, gA, gB
+
+
+def select(fit, mu, threshold=1.05):
+    """Algorithm 2 selection via the library's host function edaa_select."""
+    f = np.ascontiguousarray(fit, dtype=np.float64)
+    m = np.ascontiguousarray(mu, dtype=np.float64)
+    dp = lambda a: a.ctypes.data_as(ctypes.POINTER(c_double))  # noqa: E731
+    return int(L_.load().edaa_select(dp(f), dp(m), len(f), float(threshold)))

@@ -1,0 +1,661 @@
+// C ABI of the EDAA library (declared in include/edaa.h): argument checks,
+// workspace, the run sequence of Algorithm 1 for a batch of runs, optional
+// HIP-graph capture, and the selection of Algorithm 2.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "edaa.h"
+#include "edaa_internal.h"
+
+using namespace edaa;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+edaa_status fail(edaa_status st, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return st;
+}
+
+struct GraphEntry {
+    std::string key;
+    hipGraphExec_t exec = nullptr;
+    long long launches = 0;
+};
+
+// Event pairs recorded around pass launches (EDAA_FLAG_TIME_PASSES).
+struct PassTimer {
+    std::vector<hipEvent_t> ev;     // 2 per timed launch
+    std::vector<int> kind;          // 0 A-pass, 1 B-pass, 2 closing pass
+    int used = 0;
+    bool enabled = false;
+    hipError_t mark(hipStream_t st, int k, bool end) {
+        if (!enabled) return hipSuccess;
+        const size_t slot = (size_t)used * 2 + (end ? 1 : 0);
+        while (ev.size() <= slot) {
+            hipEvent_t e;
+            hipError_t r = hipEventCreate(&e);
+            if (r != hipSuccess) return r;
+            ev.push_back(e);
+        }
+        if ((size_t)used >= kind.size()) kind.resize(used + 1);
+        kind[used] = k;
+        hipError_t r = hipEventRecord(ev[slot], st);
+        if (end) ++used;
+        return r;
+    }
+};
+
+}  // namespace
+
+struct edaa_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;      // the caller's stream
+    hipStream_t cap_stream = nullptr;  // private stream used for graph capture
+    bool poisoned = false;
+    void* ws = nullptr;
+    size_t ws_bytes = 0;
+    long long last_launches = 0;
+    std::vector<GraphEntry> graphs;    // most recent last
+    PassTimer timer;
+};
+
+#define EDAA_HIP(ctx, call)                                                                         \
+    do {                                                                                            \
+        hipError_t e_ = (call);                                                                     \
+        if (e_ != hipSuccess) {                                                                     \
+            (ctx)->poisoned = true;                                                                 \
+            return fail(EDAA_EDEVICE, "%s failed: %s", #call, hipGetErrorString(e_));               \
+        }                                                                                           \
+    } while (0)
+
+#define EDAA_REQUIRE(cond, ...)                                                                     \
+    do {                                                                                            \
+        if (!(cond)) return fail(EDAA_EINVAL, __VA_ARGS__);                                         \
+    } while (0)
+
+namespace {
+
+struct Arena {
+    size_t off = 0;
+    template <typename T>
+    size_t take(size_t n) {
+        off = (off + 255) & ~(size_t)255;
+        const size_t o = off;
+        off += n * sizeof(T);
+        return o;
+    }
+};
+
+edaa_status ensure_ws(edaa_ctx* ctx, size_t bytes) {
+    if (bytes <= ctx->ws_bytes) return EDAA_OK;
+    // Graphs hold pointers into the workspace: drop them before reallocating.
+    for (auto& ge : ctx->graphs) (void)hipGraphExecDestroy(ge.exec);
+    ctx->graphs.clear();
+    if (ctx->ws) {
+        (void)hipStreamSynchronize(ctx->stream);
+        (void)hipFree(ctx->ws);
+        ctx->ws = nullptr;
+        ctx->ws_bytes = 0;
+    }
+    const size_t want = std::max(bytes, (size_t)(1 << 20));
+    if (hipMalloc(&ctx->ws, want) != hipSuccess) {
+        (void)hipGetLastError();
+        ctx->ws = nullptr;
+        return fail(EDAA_ENOMEM, "could not allocate %zu bytes of device workspace", want);
+    }
+    ctx->ws_bytes = want;
+    return EDAA_OK;
+}
+
+edaa_status check_ctx(edaa_ctx* ctx) {
+    if (!ctx) return fail(EDAA_EINVAL, "null context");
+    if (ctx->poisoned) return fail(EDAA_EDEVICE, "context is poisoned by an earlier device error");
+    if (hipSetDevice(ctx->device) != hipSuccess) {
+        ctx->poisoned = true;
+        return fail(EDAA_EDEVICE, "hipSetDevice(%d) failed", ctx->device);
+    }
+    return EDAA_OK;
+}
+
+edaa_status check_params(const edaa_params* P) {
+    EDAA_REQUIRE(P != nullptr, "params is null");
+    EDAA_REQUIRE(P->T >= 0 && P->K1 >= 0 && P->K2 >= 0, "T, K1, K2 must be >= 0 (got %d, %d, %d)", P->T, P->K1,
+                 P->K2);
+    EDAA_REQUIRE(P->T <= 1000000, "T too large");
+    EDAA_REQUIRE(isfinite(P->init_scale), "init_scale must be finite");
+    EDAA_REQUIRE(isfinite(P->eta1) && P->eta1 >= 0.0 && isfinite(P->eta2) && P->eta2 >= 0.0,
+                 "eta1/eta2 must be finite and >= 0 (0 selects the paper's rule)");
+    EDAA_REQUIRE(isfinite(P->select_threshold) && P->select_threshold >= 1.0, "select_threshold must be >= 1");
+    EDAA_REQUIRE(P->x_dtype == EDAA_X_F32 || P->x_dtype == EDAA_X_BF16, "x_dtype must be EDAA_X_F32 or EDAA_X_BF16");
+    EDAA_REQUIRE(P->coherence_mode == EDAA_COHERENCE_COSINE || P->coherence_mode == EDAA_COHERENCE_RAW,
+                 "coherence_mode must be EDAA_COHERENCE_COSINE or EDAA_COHERENCE_RAW");
+    return EDAA_OK;
+}
+
+edaa_status check_shape(int L, int N, int p, int M) {
+    EDAA_REQUIRE(L >= 1 && L <= kMaxL, "L must be in [1, %d] (got %d)", kMaxL, L);
+    EDAA_REQUIRE(p >= 1 && p <= kMaxP, "p must be in [1, %d] (got %d)", kMaxP, p);
+    EDAA_REQUIRE(N >= p, "N must be >= p (got N=%d, p=%d)", N, p);
+    EDAA_REQUIRE(M >= 1, "M must be >= 1 (got %d)", M);
+    EDAA_REQUIRE((double)M * p * N < 2147483647.0 && (double)L * N < 2147483647.0, "problem too large");
+    return EDAA_OK;
+}
+
+// Device buffers of one batched run, carved out of the context workspace.
+struct RunBuffers {
+    State s;
+    uint64_t* seeds;
+    double* gammas;
+};
+
+size_t layout(const Geom& g, int T, char* base, RunBuffers* rb) {
+    Arena a;
+    const size_t Q = (size_t)g.M * g.p;
+    const size_t o_Bst = a.take<float>(Q * g.N);
+    const size_t o_tsh = a.take<float>((size_t)g.ntiles * g.Qp);
+    const size_t o_colm = a.take<float>(g.Qp);
+    const size_t o_cols = a.take<float>(g.Qp);
+    const size_t o_E = a.take<float>((size_t)g.L * g.Qp);
+    const size_t o_Ed = a.take<double>((size_t)g.L * g.Qp);
+    const size_t o_W = a.take<float>((size_t)g.L * g.Qp);
+    const size_t o_XAt = a.take<double>((size_t)g.L * g.Qp);
+    const size_t o_AAt = a.take<double>((size_t)g.M * g.p * g.p);
+    const size_t o_eta = a.take<float>(2 * (size_t)g.M);
+    const size_t o_etad = a.take<double>(2 * (size_t)g.M);
+    const size_t o_trace = a.take<double>((size_t)g.M * (T + 1));
+    const size_t o_fit = a.take<double>(g.M);
+    const size_t o_mu = a.take<double>(g.M);
+    const size_t o_V = a.take<float>((size_t)g.npg * g.nqc * g.L * g.QC);
+    const size_t o_mp = a.take<float>((size_t)g.npg * g.Qp);
+    const size_t o_sp = a.take<float>((size_t)g.npg * g.Qp);
+    const size_t o_AA = a.take<float>((size_t)g.npg * g.nqc * g.R * g.p * g.p);
+    const size_t o_lp = a.take<double>((size_t)g.npg * g.M);
+    const size_t o_fp = a.take<double>((size_t)g.npg * g.M);
+    const size_t o_seed = a.take<uint64_t>(g.M);
+    const size_t o_gam = a.take<double>(g.M);
+    if (rb) {
+        State& s = rb->s;
+        s.Bst = (float*)(base + o_Bst);
+        s.tshift = (float*)(base + o_tsh);
+        s.colm = (float*)(base + o_colm);
+        s.cols = (float*)(base + o_cols);
+        s.E = (float*)(base + o_E);
+        s.Ed = (double*)(base + o_Ed);
+        s.W = (float*)(base + o_W);
+        s.XAtd = (double*)(base + o_XAt);
+        s.AAtd = (double*)(base + o_AAt);
+        s.eta = (float*)(base + o_eta);
+        s.etad = (double*)(base + o_etad);
+        s.trace = (double*)(base + o_trace);
+        s.fit = (double*)(base + o_fit);
+        s.mu = (double*)(base + o_mu);
+        s.Vpart = (float*)(base + o_V);
+        s.mpart = (float*)(base + o_mp);
+        s.spart = (float*)(base + o_sp);
+        s.AApart = (float*)(base + o_AA);
+        s.lpart = (double*)(base + o_lp);
+        s.fpart = (double*)(base + o_fp);
+        s.T = T;
+        rb->seeds = (uint64_t*)(base + o_seed);
+        rb->gammas = (double*)(base + o_gam);
+    }
+    return a.off + 256;
+}
+
+// Enqueue the whole sequence of Algorithm 1 for g.M runs.  Returns the number
+// of kernel launches, or a negative HIP error.
+struct Seq {
+    PassTimer* timer;   // mutable: capture switches timing off
+    const Geom* g;
+    const State* s;
+    RunInit ri;
+    int mode;          // kModeInitRng or kModeInitB0
+    const float* A0;
+    int T, K1, K2;
+    float* B_out;
+    float* E_out;
+    int coherence_mode;
+};
+
+hipError_t enqueue_sequence(const Seq& q, hipStream_t st, long long* launches) {
+    const Geom& g = *q.g;
+    const State& s = *q.s;
+    long long n = 0;
+    hipError_t e;
+#define EDAA_L(call)                          \
+    do {                                      \
+        e = (call);                           \
+        if (e != hipSuccess) return e;        \
+        ++n;                                  \
+    } while (0)
+    // zero the padded [L][Qp] arrays (pad columns must read as zero)
+    EDAA_L(launch_fill(s.E, (size_t)g.L * g.Qp, 0.f, st));
+    EDAA_L(launch_fill(s.W, (size_t)g.L * g.Qp, 0.f, st));
+    EDAA_L(launch_fill((float*)s.XAtd, 2 * (size_t)g.L * g.Qp, 0.f, st));
+    EDAA_L(launch_fill((float*)s.Ed, 2 * (size_t)g.L * g.Qp, 0.f, st));
+    EDAA_L(launch_init_A(g, s, q.A0, st));
+    EDAA_L(launch_bpass(g, s, q.mode, q.ri, st));
+    EDAA_L(launch_reduce_b(g, s, 0, st));
+    EDAA_L(launch_eta(g, s, q.ri, st));
+    PassTimer* tm = q.timer;
+    for (int t = 0; t < q.T; ++t) {
+        if ((e = tm->mark(st, 0, false)) != hipSuccess) return e;
+        EDAA_L(launch_apass(g, s, q.K1, t, st));
+        if ((e = tm->mark(st, 0, true)) != hipSuccess) return e;
+        EDAA_L(launch_reduce_a(g, s, t, st));
+        for (int k = 0; k < q.K2; ++k) {
+            if ((e = tm->mark(st, 1, false)) != hipSuccess) return e;
+            EDAA_L(launch_bpass(g, s, kModeStep, q.ri, st));
+            if ((e = tm->mark(st, 1, true)) != hipSuccess) return e;
+            EDAA_L(launch_reduce_b(g, s, k + 1 < q.K2 ? 1 : 0, st));
+        }
+    }
+    if ((e = tm->mark(st, 2, false)) != hipSuccess) return e;
+    EDAA_L(launch_close(g, s, st));
+    if ((e = tm->mark(st, 2, true)) != hipSuccess) return e;
+    EDAA_L(launch_reduce_close(g, s, st));
+    EDAA_L(launch_finalize(g, s, q.B_out, q.E_out, q.coherence_mode, st));
+    n += (q.B_out ? 1 : 0);
+#undef EDAA_L
+    *launches = n;
+    return hipSuccess;
+}
+
+std::string graph_key(const Seq& q, const void* X, const void* ws) {
+    char buf[640];
+    const Geom& g = *q.g;
+    snprintf(buf, sizeof(buf),
+             "%d,%d,%d,%d,%d,%d,%d,%d,%d|%d,%d,%d|%p,%p,%p,%p,%p,%p,%p|%a,%a,%a|%d,%d", g.L, g.N, g.M, g.p, g.R,
+             g.npg, g.nqc, q.mode, q.coherence_mode, q.T, q.K1, q.K2, X, (const void*)q.s->A, (const void*)q.B_out,
+             (const void*)q.E_out, (const void*)q.A0, (const void*)q.ri.B0, ws, (double)q.ri.init_scale, q.ri.eta1,
+             q.ri.eta2, q.s->x_bf16, q.timer->enabled ? 1 : 0);
+    return buf;
+}
+
+// Run (or replay) the sequence on the caller's stream.
+edaa_status run_sequence(edaa_ctx* ctx, const Seq& q, const void* X, int use_graph) {
+    ctx->timer.used = 0;
+    if (!use_graph) {
+        long long n = 0;
+        hipError_t e = enqueue_sequence(q, ctx->stream, &n);
+        if (e != hipSuccess) {
+            ctx->poisoned = true;
+            return fail(EDAA_EDEVICE, "kernel launch failed: %s", hipGetErrorString(e));
+        }
+        ctx->last_launches = n;
+        return EDAA_OK;
+    }
+    // Events recorded inside a captured graph carry no timestamps on this
+    // runtime: pass timing is taken in eager mode only.
+    q.timer->enabled = false;
+    const std::string key = graph_key(q, X, ctx->ws);
+    for (size_t i = 0; i < ctx->graphs.size(); ++i) {
+        if (ctx->graphs[i].key == key) {
+            EDAA_HIP(ctx, hipGraphLaunch(ctx->graphs[i].exec, ctx->stream));
+            ctx->last_launches = ctx->graphs[i].launches;
+            return EDAA_OK;
+        }
+    }
+    if (!ctx->cap_stream) EDAA_HIP(ctx, hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
+    EDAA_HIP(ctx, hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal));
+    long long n = 0;
+    hipError_t e = enqueue_sequence(q, ctx->cap_stream, &n);
+    hipGraph_t graph = nullptr;
+    hipError_t e2 = hipStreamEndCapture(ctx->cap_stream, &graph);
+    if (e != hipSuccess || e2 != hipSuccess) {
+        if (graph) (void)hipGraphDestroy(graph);
+        ctx->poisoned = true;
+        return fail(EDAA_EDEVICE, "graph capture failed: %s / %s", hipGetErrorString(e), hipGetErrorString(e2));
+    }
+    hipGraphExec_t exec = nullptr;
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) {
+        ctx->poisoned = true;
+        return fail(EDAA_EDEVICE, "hipGraphInstantiate failed: %s", hipGetErrorString(e));
+    }
+    if (ctx->graphs.size() >= 4) {
+        (void)hipGraphExecDestroy(ctx->graphs.front().exec);
+        ctx->graphs.erase(ctx->graphs.begin());
+    }
+    ctx->graphs.push_back(GraphEntry{key, exec, n});
+    EDAA_HIP(ctx, hipGraphLaunch(exec, ctx->stream));
+    ctx->last_launches = n;
+    return EDAA_OK;
+}
+
+// Shared implementation of edaa_fit (M = 1) and edaa_ensemble.
+edaa_status run_batch(edaa_ctx* ctx, const void* X, int L, int N, int p, const edaa_params* P, int M,
+                      const uint64_t* seeds, const double* gammas, const float* A0, const float* B0, float* A_all,
+                      float* B_all, float* E_all, double* loss, double* fit, double* mu, double* eta_out) {
+    const Geom g = make_geom(L, N, M, p);
+    for (int kind = 0; kind < 3; ++kind)
+        if (pass_lds_bytes(p, g.R, L, kind) > kMaxLdsBytes)
+            return fail(EDAA_EUNSUPPORTED, "L=%d with p=%d needs %zu bytes of LDS (limit %zu)", L, p,
+                        pass_lds_bytes(p, g.R, L, kind), kMaxLdsBytes);
+    const size_t need = layout(g, P->T, nullptr, nullptr);
+    edaa_status st = ensure_ws(ctx, need);
+    if (st != EDAA_OK) return st;
+    RunBuffers rb;
+    memset(&rb, 0, sizeof(rb));
+    layout(g, P->T, (char*)ctx->ws, &rb);
+    State& s = rb.s;
+    s.X = X;
+    s.x_bf16 = P->x_dtype == EDAA_X_BF16 ? 1 : 0;
+    s.A = A_all;
+
+    // Host -> device copies of the per-run scalars happen outside any graph.
+    EDAA_HIP(ctx, hipMemcpyAsync(rb.seeds, seeds, sizeof(uint64_t) * M, hipMemcpyHostToDevice, ctx->stream));
+    EDAA_HIP(ctx, hipMemcpyAsync(rb.gammas, gammas, sizeof(double) * M, hipMemcpyHostToDevice, ctx->stream));
+
+    Seq q;
+    q.timer = &ctx->timer;
+    ctx->timer.enabled = (P->flags & EDAA_FLAG_TIME_PASSES) != 0;
+    q.g = &g;
+    q.s = &s;
+    q.ri.seeds = rb.seeds;
+    q.ri.gammas = rb.gammas;
+    q.ri.init_scale = (float)P->init_scale;
+    q.ri.B0 = B0;
+    q.ri.A0 = A0;
+    q.ri.eta1 = P->eta1;
+    q.ri.eta2 = P->eta2;
+    q.mode = B0 ? kModeInitB0 : kModeInitRng;
+    q.A0 = A0;
+    q.T = P->T;
+    q.K1 = P->K1;
+    q.K2 = P->K2;
+    q.B_out = B_all;
+    q.E_out = E_all;
+    q.coherence_mode = P->coherence_mode;
+    st = run_sequence(ctx, q, X, (P->flags & EDAA_FLAG_GRAPH) ? 1 : 0);
+    if (st != EDAA_OK) return st;
+
+    if (loss) EDAA_HIP(ctx, hipMemcpyAsync(loss, s.trace, sizeof(double) * M * (P->T + 1), hipMemcpyDeviceToHost,
+                                          ctx->stream));
+    if (fit) EDAA_HIP(ctx, hipMemcpyAsync(fit, s.fit, sizeof(double) * M, hipMemcpyDeviceToHost, ctx->stream));
+    if (mu) EDAA_HIP(ctx, hipMemcpyAsync(mu, s.mu, sizeof(double) * M, hipMemcpyDeviceToHost, ctx->stream));
+    if (eta_out)
+        EDAA_HIP(ctx, hipMemcpyAsync(eta_out, s.etad, sizeof(double) * 2 * M, hipMemcpyDeviceToHost, ctx->stream));
+    if (loss || fit || mu || eta_out) EDAA_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    return EDAA_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void edaa_default_params(edaa_params* P) {
+    if (!P) return;
+    memset(P, 0, sizeof(*P));
+    P->T = 100;
+    P->K1 = 5;
+    P->K2 = 5;
+    P->gamma = 1.0;
+    P->eta1 = 0.0;
+    P->eta2 = 0.0;
+    P->init_scale = 0.1;
+    P->select_threshold = 1.05;
+    P->x_dtype = EDAA_X_F32;
+    P->coherence_mode = EDAA_COHERENCE_COSINE;
+    P->flags = 0;
+}
+
+const char* edaa_last_error(void) { return g_last_error.c_str(); }
+
+edaa_status edaa_create(edaa_ctx** out, int device, void* stream) {
+    if (!out) return fail(EDAA_EINVAL, "out is null");
+    *out = nullptr;
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || n <= 0) {
+        (void)hipGetLastError();
+        return fail(EDAA_EDEVICE, "no HIP device available");
+    }
+    if (device < 0 || device >= n) return fail(EDAA_EINVAL, "device %d out of range [0, %d)", device, n);
+    if (hipSetDevice(device) != hipSuccess) return fail(EDAA_EDEVICE, "hipSetDevice(%d) failed", device);
+    edaa_ctx* ctx = new edaa_ctx();
+    ctx->device = device;
+    ctx->stream = (hipStream_t)stream;
+    *out = ctx;
+    return EDAA_OK;
+}
+
+void edaa_destroy(edaa_ctx* ctx) {
+    if (!ctx) return;
+    (void)hipSetDevice(ctx->device);
+    (void)hipStreamSynchronize(ctx->stream);
+    for (auto& ge : ctx->graphs) (void)hipGraphExecDestroy(ge.exec);
+    for (auto& e : ctx->timer.ev) (void)hipEventDestroy(e);
+    if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
+    if (ctx->ws) (void)hipFree(ctx->ws);
+    delete ctx;
+}
+
+long long edaa_last_launch_count(edaa_ctx* ctx) { return ctx ? ctx->last_launches : -1; }
+
+edaa_status edaa_pass_times(edaa_ctx* ctx, int kind, int* count, double* total_ms) {
+    edaa_status st = check_ctx(ctx);
+    if (st != EDAA_OK) return st;
+    EDAA_REQUIRE(kind >= 0 && kind <= 2 && count && total_ms, "kind must be 0, 1 or 2; count/total_ms non-null");
+    EDAA_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    int n = 0;
+    double tot = 0.0;
+    for (int i = 0; i < ctx->timer.used; ++i) {
+        if (ctx->timer.kind[i] != kind) continue;
+        float ms = 0.f;
+        EDAA_HIP(ctx, hipEventElapsedTime(&ms, ctx->timer.ev[2 * i], ctx->timer.ev[2 * i + 1]));
+        tot += ms;
+        ++n;
+    }
+    *count = n;
+    *total_ms = tot;
+    return EDAA_OK;
+}
+
+edaa_status edaa_normalize_pixels(edaa_ctx* ctx, const float* X_in, void* X_out, int L, int N, int out_dtype,
+                                  int* n_zero) {
+    edaa_status st = check_ctx(ctx);
+    if (st != EDAA_OK) return st;
+    EDAA_REQUIRE(X_in && X_out, "X_in and X_out must not be null");
+    EDAA_REQUIRE(L >= 1 && N >= 1, "L and N must be >= 1 (got %d, %d)", L, N);
+    EDAA_REQUIRE((double)L * N < 2147483647.0, "image too large");
+    EDAA_REQUIRE(out_dtype == EDAA_X_F32 || out_dtype == EDAA_X_BF16, "out_dtype must be EDAA_X_F32 or EDAA_X_BF16");
+    EDAA_REQUIRE(out_dtype == EDAA_X_F32 || (const void*)X_in != X_out, "bf16 output cannot overwrite the input");
+    int* dz = nullptr;
+    if (n_zero) {
+        st = ensure_ws(ctx, 256);
+        if (st != EDAA_OK) return st;
+        dz = (int*)ctx->ws;
+        EDAA_HIP(ctx, hipMemsetAsync(dz, 0, sizeof(int), ctx->stream));
+    }
+    EDAA_HIP(ctx, launch_normalize(X_in, X_out, L, N, out_dtype == EDAA_X_BF16, dz, ctx->stream));
+    if (n_zero) {
+        EDAA_HIP(ctx, hipMemcpyAsync(n_zero, dz, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+        EDAA_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    }
+    return EDAA_OK;
+}
+
+edaa_status edaa_fit(edaa_ctx* ctx, const void* X, int L, int N, int p, const edaa_params* params, uint64_t seed,
+                     const float* A0, const float* B0, float* A, float* B, float* E, double* loss_trace,
+                     double* eta_out) {
+    edaa_status st = check_ctx(ctx);
+    if (st != EDAA_OK) return st;
+    if ((st = check_params(params)) != EDAA_OK) return st;
+    if ((st = check_shape(L, N, p, 1)) != EDAA_OK) return st;
+    EDAA_REQUIRE(X && A && B, "X, A and B must not be null");
+    EDAA_REQUIRE(params->eta1 > 0.0 || (isfinite(params->gamma) && params->gamma > 0.0),
+                 "gamma must be finite and > 0 (got %g)", params->gamma);
+    const double gamma = params->gamma;
+    st = run_batch(ctx, X, L, N, p, params, 1, &seed, &gamma, A0, B0, A, B, E, loss_trace, nullptr, nullptr,
+                   eta_out);
+    if (st != EDAA_OK) return st;
+    if (loss_trace && !isfinite(loss_trace[params->T]))
+        return fail(EDAA_ENUMERIC, "the objective is not finite after %d outer iterations", params->T);
+    return EDAA_OK;
+}
+
+int edaa_select(const double* fit, const double* mu, int M, double threshold) {
+    if (!fit || !mu || M <= 0) return -1;
+    double fmin = INFINITY;
+    bool any = false;
+    for (int m = 0; m < M; ++m)
+        if (isfinite(fit[m])) {
+            fmin = any ? fmin < fit[m] ? fmin : fit[m] : fit[m];
+            any = true;
+        }
+    if (!any) return -1;
+    int best = -1;
+    double bmu = 0.0;
+    for (int m = 0; m < M; ++m) {
+        if (!isfinite(fit[m]) || !(fit[m] <= threshold * fmin)) continue;
+        if (best < 0 || (isnan(bmu) && !isnan(mu[m])) || mu[m] < bmu) {
+            best = m;
+            bmu = mu[m];
+        }
+    }
+    return best;
+}
+
+edaa_status edaa_ensemble(edaa_ctx* ctx, const void* X, int L, int N, int p, const edaa_params* params, int M,
+                          const uint64_t* seeds, const double* gammas, float* A_all, float* B_all, float* E_all,
+                          double* loss, double* fit, double* mu, int* run_status, int* selected) {
+    edaa_status st = check_ctx(ctx);
+    if (st != EDAA_OK) return st;
+    if ((st = check_params(params)) != EDAA_OK) return st;
+    if ((st = check_shape(L, N, p, M)) != EDAA_OK) return st;
+    EDAA_REQUIRE(X && A_all && B_all && seeds && gammas, "X, A_all, B_all, seeds and gammas must not be null");
+    if (params->eta1 <= 0.0)
+        for (int m = 0; m < M; ++m)
+            EDAA_REQUIRE(isfinite(gammas[m]) && gammas[m] > 0.0, "gammas[%d] must be finite and > 0 (got %g)", m,
+                         gammas[m]);
+    std::vector<double> tr((size_t)M * (params->T + 1)), f(M), u(M);
+    st = run_batch(ctx, X, L, N, p, params, M, seeds, gammas, nullptr, nullptr, A_all, B_all, E_all, tr.data(),
+                   f.data(), u.data(), nullptr);
+    if (st != EDAA_OK) return st;
+    int n_ok = 0;
+    for (int m = 0; m < M; ++m) {
+        const bool ok = isfinite(tr[(size_t)m * (params->T + 1) + params->T]) && isfinite(f[m]);
+        if (!ok) f[m] = INFINITY;
+        if (run_status) run_status[m] = ok ? EDAA_OK : EDAA_ENUMERIC;
+        n_ok += ok;
+    }
+    const int sel = edaa_select(f.data(), u.data(), M, params->select_threshold);
+    if (loss) memcpy(loss, tr.data(), sizeof(double) * tr.size());
+    if (fit) memcpy(fit, f.data(), sizeof(double) * M);
+    if (mu) memcpy(mu, u.data(), sizeof(double) * M);
+    if (selected) *selected = sel;
+    if (n_ok == 0) return fail(EDAA_ENUMERIC, "no run of the ensemble has a finite objective");
+    return EDAA_OK;
+}
+
+edaa_status edaa_fit_ragged(edaa_ctx* ctx, int n_images, const edaa_image_desc* images, const edaa_params* params) {
+    edaa_status st = check_ctx(ctx);
+    if (st != EDAA_OK) return st;
+    if ((st = check_params(params)) != EDAA_OK) return st;
+    EDAA_REQUIRE(n_images >= 1 && images, "n_images must be >= 1 and images non-null");
+    for (int k = 0; k < n_images; ++k) {
+        const edaa_image_desc& d = images[k];
+        if ((st = check_shape(d.L, d.N, d.p, 1)) != EDAA_OK) return st;
+        EDAA_REQUIRE(d.X && d.A && d.B, "image %d: X, A and B must not be null", k);
+        EDAA_REQUIRE(params->eta1 > 0.0 || (isfinite(d.gamma) && d.gamma > 0.0), "image %d: gamma must be > 0", k);
+    }
+    long long launches = 0;
+    for (int k = 0; k < n_images; ++k) {
+        const edaa_image_desc& d = images[k];
+        const double gamma = d.gamma;
+        const uint64_t seed = d.seed;
+        st = run_batch(ctx, d.X, d.L, d.N, d.p, params, 1, &seed, &gamma, nullptr, nullptr, d.A, d.B, d.E,
+                       d.loss_trace, nullptr, nullptr, nullptr);
+        if (st != EDAA_OK) return st;
+        launches += ctx->last_launches;
+    }
+    ctx->last_launches = launches;
+    return EDAA_OK;
+}
+
+namespace {
+edaa_status grad_work(edaa_ctx* ctx, int L, int N, int p, GradWork* w) {
+    Arena a;
+    const int nblk = grad_blocks(N);
+    const size_t oE = a.take<float>((size_t)L * p), oEd = a.take<double>((size_t)L * p),
+                 oW = a.take<double>((size_t)L * p), oV = a.take<double>((size_t)nblk * L * p),
+                 oL = a.take<double>(nblk), oCm = a.take<float>((size_t)nblk * p),
+                 oCs = a.take<float>((size_t)nblk * p), oSt = a.take<float>(2 * (size_t)p);
+    edaa_status st = ensure_ws(ctx, a.off + 256);
+    if (st != EDAA_OK) return st;
+    char* b = (char*)ctx->ws;
+    w->E = (float*)(b + oE);
+    w->Ed = (double*)(b + oEd);
+    w->Wd = (double*)(b + oW);
+    w->Vpart = (double*)(b + oV);
+    w->lpart = (double*)(b + oL);
+    w->cm = (float*)(b + oCm);
+    w->cs = (float*)(b + oCs);
+    w->colstat = (float*)(b + oSt);
+    w->nblk = nblk;
+    return EDAA_OK;
+}
+}  // namespace
+
+edaa_status edaa_loss_fwd(edaa_ctx* ctx, const float* X, const float* A, const float* B, int L, int N, int p,
+                          float* loss_dev) {
+    edaa_status st = check_ctx(ctx);
+    if (st != EDAA_OK) return st;
+    if ((st = check_shape(L, N, p, 1)) != EDAA_OK) return st;
+    EDAA_REQUIRE(X && A && B && loss_dev, "X, A, B and loss_dev must not be null");
+    GradWork w;
+    if ((st = grad_work(ctx, L, N, p, &w)) != EDAA_OK) return st;
+    EDAA_HIP(ctx, launch_loss_fwd(X, A, B, L, N, p, w, loss_dev, ctx->stream));
+    return EDAA_OK;
+}
+
+edaa_status edaa_loss_bwd(edaa_ctx* ctx, const float* X, const float* A, const float* B, int L, int N, int p,
+                          const float* grad_out, float* gA, float* gB) {
+    edaa_status st = check_ctx(ctx);
+    if (st != EDAA_OK) return st;
+    if ((st = check_shape(L, N, p, 1)) != EDAA_OK) return st;
+    EDAA_REQUIRE(X && A && B && grad_out, "X, A, B and grad_out must not be null");
+    EDAA_REQUIRE(gA || gB, "at least one of gA, gB must be non-null");
+    GradWork w;
+    if ((st = grad_work(ctx, L, N, p, &w)) != EDAA_OK) return st;
+    EDAA_HIP(ctx, launch_loss_bwd(X, A, B, L, N, p, grad_out, w, gA, gB, ctx->stream));
+    return EDAA_OK;
+}
+
+edaa_status edaa_mirror_step_A(edaa_ctx* ctx, float* A, const float* gA, int p, int N, float eta) {
+    edaa_status st = check_ctx(ctx);
+    if (st != EDAA_OK) return st;
+    EDAA_REQUIRE(A && gA, "A and gA must not be null");
+    EDAA_REQUIRE(p >= 1 && p <= kMaxP && N >= 1, "need 1 <= p <= %d and N >= 1", kMaxP);
+    EDAA_REQUIRE(isfinite(eta), "eta must be finite");
+    EDAA_HIP(ctx, launch_mirror_A(A, gA, p, N, eta, ctx->stream));
+    return EDAA_OK;
+}
+
+edaa_status edaa_mirror_step_B(edaa_ctx* ctx, float* B, const float* gB, int N, int p, float eta) {
+    edaa_status st = check_ctx(ctx);
+    if (st != EDAA_OK) return st;
+    EDAA_REQUIRE(B && gB, "B and gB must not be null");
+    EDAA_REQUIRE(p >= 1 && p <= kMaxP && N >= 1, "need 1 <= p <= %d and N >= 1", kMaxP);
+    EDAA_REQUIRE(isfinite(eta), "eta must be finite");
+    GradWork w;
+    if ((st = grad_work(ctx, 1, N, p, &w)) != EDAA_OK) return st;
+    EDAA_HIP(ctx, launch_mirror_B(B, gB, N, p, eta, w, ctx->stream));
+    return EDAA_OK;
+}
+
+}  // extern "C"

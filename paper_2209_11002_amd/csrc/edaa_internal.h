@@ -1,0 +1,124 @@
+// Internal declarations shared by the kernel and host translation units of the
+// EDAA library.  Not part of the public C ABI (include/edaa.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace edaa {
+
+// A workgroup is 4 wave64s and works on tiles of 64 consecutive pixels.
+constexpr int kTile = 64;
+constexpr int kThreads = 256;
+constexpr int kMaxL = 512;
+constexpr int kMaxP = 16;
+constexpr int kTargetWorkgroups = 512;   // 2 per CU on 256 CUs
+
+enum PassMode { kModeStep = 0, kModeInitRng = 1, kModeInitB0 = 2 };
+
+// Geometry of one batched problem: M runs of p endmembers on an L x N image,
+// the runs grouped in chunks of R (one workgroup column per chunk).
+struct Geom {
+    int L, N, M, p;
+    int R;        // runs per chunk (1: single-run kernels)
+    int QC;       // columns per chunk = R * p
+    int nqc;      // number of chunks = ceil(M / R)
+    int Qp;       // padded column count = nqc * QC
+    int ntiles;   // ceil(N / 64)
+    int npg;      // pixel groups (workgroups per chunk)
+};
+
+// Device-side state of a batched problem.  Column q = m * p + j (run m,
+// endmember j) in the unpadded [Q][N] arrays; padded column c * QC + qq in the
+// [L][Qp] arrays.
+struct State {
+    const void* X;      // [L][N] float32 or bf16 bits
+    int x_bf16;
+    float* A;           // [Q][N] abundances (the caller's A_all)
+    float* Bst;         // [Q][N] unnormalised pixel weights
+    float* tshift;      // [ntiles][Qp] shift used when a tile of Bst was written
+    float* colm;        // [Qp] column maximum of the last B-pass
+    float* cols;        // [Qp] column sum (relative to colm) of the last B-pass
+    float* E;           // [L][Qp]  endmembers X B (float32 copy read by the passes)
+    double* Ed;         // [L][Qp]  the same in float64
+    float* W;           // [L][Qp]  E (A A^T) - X A^T
+    double* XAtd;       // [L][Qp]  X A^T
+    double* AAtd;       // [M][p][p] A A^T
+    float* eta;         // [M][2] step sizes used by the kernels
+    double* etad;       // [M][2] the same in float64 (reported)
+    double* trace;      // [M][T+1]
+    double* fit;        // [M]
+    double* mu;         // [M]
+    float* Vpart;       // [npg][nqc][L][QC]
+    float* mpart;       // [npg][Qp]
+    float* spart;       // [npg][Qp]
+    float* AApart;      // [npg][nqc][R][p][p]
+    double* lpart;      // [npg][M]
+    double* fpart;      // [npg][M]
+    int T;              // trace stride is T+1
+};
+
+struct RunInit {
+    const uint64_t* seeds;   // device [M]
+    const double* gammas;    // device [M]
+    float init_scale;
+    const float* B0;         // device [N][p] or null (single run only)
+    const float* A0;         // device [p][N] or null
+    double eta1, eta2;       // > 0: overrides
+};
+
+// Launchers (edaa_kernels.hip).  All enqueue on `st` and return the HIP error
+// of the last launch.
+hipError_t launch_fill(float* dst, size_t n, float value, hipStream_t st);
+hipError_t launch_init_A(const Geom& g, const State& s, const float* A0, hipStream_t st);
+hipError_t launch_bpass(const Geom& g, const State& s, int mode, const RunInit& ri, hipStream_t st);
+hipError_t launch_reduce_b(const Geom& g, const State& s, int need_w, hipStream_t st);
+hipError_t launch_eta(const Geom& g, const State& s, const RunInit& ri, hipStream_t st);
+hipError_t launch_apass(const Geom& g, const State& s, int K1, int t, hipStream_t st);
+hipError_t launch_reduce_a(const Geom& g, const State& s, int t, hipStream_t st);
+hipError_t launch_close(const Geom& g, const State& s, hipStream_t st);
+hipError_t launch_reduce_close(const Geom& g, const State& s, hipStream_t st);
+hipError_t launch_finalize(const Geom& g, const State& s, float* B_out, float* E_out,
+                           int coherence_mode, hipStream_t st);
+hipError_t launch_normalize(const float* Xin, void* Xout, int L, int N, int out_bf16,
+                            int* n_zero_dev, hipStream_t st);
+
+// Autograd / mirror-step kernels (edaa_grad.hip).
+struct GradWork {
+    float* E;        // [L][p]  X B rounded to float32
+    double* Ed;      // [L][p]  X B
+    double* Wd;      // [L][p]  (X B A - X) A^T
+    double* Vpart;   // [nblk][L][p]
+    double* lpart;   // [nblk]
+    float* cm;       // [nblk][p] column max partials (mirror B)
+    float* cs;       // [nblk][p] column sum partials (mirror B)
+    float* colstat;  // [2][p]
+    int nblk;
+};
+hipError_t launch_loss_fwd(const float* X, const float* A, const float* B, int L, int N, int p,
+                           const GradWork& w, float* loss_dev, hipStream_t st);
+hipError_t launch_loss_bwd(const float* X, const float* A, const float* B, int L, int N, int p,
+                           const float* grad_out, const GradWork& w, float* gA, float* gB,
+                           hipStream_t st);
+hipError_t launch_mirror_A(float* A, const float* gA, int p, int N, float eta, hipStream_t st);
+hipError_t launch_mirror_B(float* B, const float* gB, int N, int p, float eta, const GradWork& w,
+                           hipStream_t st);
+
+// Raise a kernel's dynamic LDS limit (needed above 64 KiB); idempotent.
+inline void set_max_lds(const void* fn, int bytes) {
+    (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+}
+
+// Number of workgroups used by the autograd kernels for an N-pixel image.
+int grad_blocks(int N);
+
+// Dynamic LDS bytes of a pass kernel (kind 0: A-pass, 1: B-pass, 2: closing).
+size_t pass_lds_bytes(int PP, int R, int L, int kind);
+constexpr size_t kMaxLdsBytes = 160 * 1024;
+
+// Geometry helpers (edaa_kernels.hip).
+int runs_per_chunk(int p, int M);
+Geom make_geom(int L, int N, int M, int p);
+
+}  // namespace edaa

@@ -1,0 +1,127 @@
+"""GPU parity of the batched ensemble (Algorithm 2 over runs advanced together)
+against the float64 oracle, run by run."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import edaa as O
+from paper_2209_11002_amd import synth
+
+gpu = pytest.mark.gpu
+
+
+def _say(*a):
+    print("[case]", *a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def api():
+    if not torch.cuda.is_available():
+        pytest.skip("needs a GPU")
+    from paper_2209_11002_amd import api as A
+    return A
+
+
+def _prep(X, dtype=torch.float32):
+    Xn, _ = O.normalize_pixels(X)
+    Xt = torch.from_numpy(Xn.astype(np.float32)).to(dtype)
+    return Xt.cuda().contiguous(), Xt.to(torch.float64).numpy()
+
+
+def _np(t):
+    return t.detach().float().cpu().numpy().astype(np.float64)
+
+
+def _check_selection(sel, fit_ref, mu_ref, fit_tol=1e-4, mu_tol=1e-4):
+    """Several runs can be correct when fit/mu margins are below float32
+    error: the GPU's choice must lie in the oracle's candidate set (widened by
+    the tolerance) and its oracle coherence must be within tolerance of the
+    oracle's minimum over that set."""
+    fmin = np.min(fit_ref)
+    I = np.where(fit_ref <= 1.05 * fmin * (1 + fit_tol))[0]
+    assert sel in I
+    I_strict = np.where(fit_ref <= 1.05 * fmin * (1 - fit_tol))[0]
+    best = np.min(mu_ref[I_strict]) if len(I_strict) else np.min(mu_ref[I])
+    assert mu_ref[sel] <= best + mu_tol
+
+
+@gpu
+@pytest.mark.parametrize("M,p,L,N,T", [
+    (3, 3, 40, 333, 10),      # 4 runs per chunk, one unused slot
+    (6, 3, 40, 333, 10),      # 20 runs per chunk, 14 unused slots
+    (10, 6, 37, 500, 8),      # 8 runs per chunk: two chunks, 6 unused slots
+    (20, 12, 60, 257, 6),     # 4 runs per chunk: five full chunks
+])
+def test_ensemble_matches_oracle_runs(api, M, p, L, N, T):
+    _say(f"ensemble M={M} p={p} L={L} N={N} T={T}")
+    s = synth.small_case(seed=20 + M, L=L, N=N, p=min(p, 8))
+    Xg, X = _prep(s.X)
+    seeds = [m // 2 for m in range(M)]
+    gammas = [(0.5, 2.0)[m % 2] for m in range(M)]
+    r = api.ensemble(Xg, p, seeds, gammas, T=T)
+    ref = O.ensemble(X, p, seeds, gammas, T=T)
+    A, B, E = _np(r["A"]), _np(r["B"]), _np(r["E"])
+    for m, rr in enumerate(ref["runs"]):
+        rel = np.max(np.abs(r["loss"][m] - rr["loss"]) / rr["loss"])
+        assert rel < 1e-4, (m, rel)
+        assert np.max(np.abs(A[m] - rr["A"])) < 1e-3, m
+        assert N * np.max(np.abs(B[m] - rr["B"])) < 1e-2, m
+        assert np.max(np.abs(E[m] - rr["E"])) < 1e-4, m
+    assert np.all(r["status"] == 0)
+    assert np.max(np.abs(r["fit"] - ref["fit"]) / ref["fit"]) < 1e-4
+    assert np.max(np.abs(r["mu"] - ref["mu"])) < 1e-4
+    _check_selection(r["selected"], ref["fit"], ref["mu"])
+
+
+@gpu
+def test_ensemble_equals_single_runs(api):
+    """Batched runs follow the same arithmetic as single runs (up to the
+    order of the cross-workgroup sums)."""
+    _say("ensemble vs single runs M=5 p=4")
+    s = synth.small_case(seed=31, L=50, N=700, p=4)
+    Xg, X = _prep(s.X)
+    seeds, gammas = [0, 1, 2, 3, 4], [0.25, 0.5, 1.0, 2.0, 4.0]
+    r = api.ensemble(Xg, 4, seeds, gammas, T=12)
+    for m in range(5):
+        one = api.fit(Xg, 4, T=12, gamma=gammas[m], seed=seeds[m])
+        assert np.max(np.abs(r["loss"][m] - one["loss"]) / one["loss"]) < 1e-5
+        assert torch.max(torch.abs(r["A"][m] - one["A"])).item() < 1e-4
+
+
+@gpu
+def test_ensemble_coherence_modes_and_graph(api):
+    _say("ensemble raw coherence + graph replay")
+    s = synth.small_case(seed=32, L=30, N=300, p=3)
+    Xg, X = _prep(s.X)
+    seeds, gammas = [0, 1, 2, 3, 4, 5], [1.0] * 6
+    r = api.ensemble(Xg, 3, seeds, gammas, T=5, coherence="raw")
+    ref = O.ensemble(X, 3, seeds, gammas, T=5, coherence_mode="raw")
+    assert np.max(np.abs(r["mu"] - ref["mu"])) < 1e-4
+    e1 = api.ensemble(Xg, 3, seeds, gammas, T=5)
+    for _ in range(3):
+        eg = api.ensemble(Xg, 3, seeds, gammas, T=5, graph=True)
+        assert np.array_equal(eg["loss"], e1["loss"]) and torch.equal(eg["A"], e1["A"])
+        assert eg["selected"] == e1["selected"]
+
+
+@gpu
+def test_ensemble_non_finite_run_is_excluded(api):
+    """A huge gamma drives one run to a degenerate (possibly non-finite)
+    state; if it is non-finite it is flagged and never selected, and the other
+    runs are unaffected either way."""
+    _say("ensemble with a diverging run")
+    s = synth.small_case(seed=33, L=30, N=300, p=3)
+    Xg, X = _prep(s.X)
+    seeds, gammas = [0, 1, 2], [1.0, 1e30, 1.0]
+    r = api.ensemble(Xg, 3, seeds, gammas, T=5)
+    ok = [0, 2]
+    ref = O.ensemble(X, 3, [0, 2], [1.0, 1.0], T=5)
+    for k, m in enumerate(ok):
+        assert r["status"][m] == 0
+        assert np.max(np.abs(r["loss"][m] - ref["runs"][k]["loss"]) / ref["runs"][k]["loss"]) < 1e-4
+    assert np.all(np.isfinite(r["loss"][ok]))
+    if r["status"][1] != 0:
+        assert r["fit"][1] == np.inf
+        assert r["selected"] in ok

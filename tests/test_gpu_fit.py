@@ -1,0 +1,210 @@
+"""GPU parity of the HIP path (through the C ABI) against the float64 oracle.
+
+Inputs are seeded synthetic scenes; the oracle receives exactly the float32
+values the GPU receives (normalised once by the oracle and rounded to
+float32), so differences come from the GPU arithmetic only.
+
+Tolerances (float32 path): objective 1e-4 relative, A and B 1e-3 max-abs after
+a fixed iteration count.  B entries are O(1/N), so B is also compared as N*B
+(relative to the uniform value 1), which is a much stronger check.
+"""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import edaa as O
+from paper_2209_11002_amd import synth
+
+gpu = pytest.mark.gpu
+
+
+def _say(*a):
+    print("[case]", *a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def api():
+    if not torch.cuda.is_available():
+        pytest.skip("needs a GPU")
+    from paper_2209_11002_amd import api as A
+    return A
+
+
+def _prep(scene_X, dtype=torch.float32):
+    """Oracle-normalised X rounded to the GPU storage type; returns (GPU
+    tensor, float64 copy of exactly those values)."""
+    Xn, _ = O.normalize_pixels(scene_X)
+    Xt = torch.from_numpy(Xn.astype(np.float32)).to(dtype)
+    X64 = Xt.to(torch.float64).numpy()
+    return Xt.cuda().contiguous(), X64
+
+
+def _np(t):
+    return t.detach().float().cpu().numpy().astype(np.float64)
+
+
+def _compare_run(r_gpu, r_ref, N, loss_rtol=1e-4, ab_atol=1e-3, nb_atol=None, e_atol=None):
+    lg, lr = np.asarray(r_gpu["loss"]), np.asarray(r_ref["loss"])
+    rel = np.max(np.abs(lg - lr) / np.abs(lr))
+    A_err = np.max(np.abs(_np(r_gpu["A"]) - r_ref["A"]))
+    B_err = np.max(np.abs(_np(r_gpu["B"]) - r_ref["B"]))
+    NB_err = N * B_err
+    msg = f"loss rel {rel:.3e}  A {A_err:.3e}  B {B_err:.3e}  N*B {NB_err:.3e}"
+    _say(msg)
+    assert rel <= loss_rtol, msg
+    assert A_err <= ab_atol and B_err <= ab_atol, msg
+    if nb_atol is not None:
+        assert NB_err <= nb_atol, msg
+    if e_atol is not None:
+        E_err = np.max(np.abs(_np(r_gpu["E"]) - r_ref["E"]))
+        assert E_err <= e_atol, f"E {E_err:.3e}"
+    return rel, A_err, B_err
+
+
+@gpu
+def test_normalize_pixels(api):
+    _say("normalize L=37 N=1000 (+ a zero pixel)")
+    s = synth.small_case(seed=3, L=37, N=1000, p=3)
+    X = s.X.copy()
+    X[:, 17] = 0.0
+    Xg = torch.from_numpy(X).cuda()
+    out, nz = api.normalize_pixels(Xg, count_zero=True)
+    ref, nz_ref = O.normalize_pixels(X)
+    assert nz == nz_ref == 1
+    assert np.max(np.abs(_np(out) - ref)) < 2e-7
+    outh = api.normalize_pixels(Xg, out_dtype=torch.bfloat16)
+    # bf16 round-to-nearest-even of the float32 result (at most one ulp off
+    # when the float32 value sits next to a rounding boundary)
+    ref16 = torch.from_numpy(ref.astype(np.float32)).to(torch.bfloat16).float().numpy()
+    d = np.abs(outh.float().cpu().numpy() - ref16)
+    assert np.max(d / np.maximum(np.abs(ref16), 1e-30)) <= 2 ** -7
+
+
+@gpu
+def test_init_and_step_sizes(api):
+    _say("init T=0 L=50 N=777 p=5")
+    s = synth.small_case(seed=5, L=50, N=777, p=5)
+    Xg, X = _prep(s.X)
+    for seed, gamma in ((0, 1.0), (123456789, 0.25)):
+        r = api.fit(Xg, 5, T=0, gamma=gamma, seed=seed)
+        B0 = O.init_B_from_seed(seed, 777, 5)
+        assert np.max(np.abs(_np(r["B"]) * 777 - B0 * 777)) < 2e-6
+        e1, e2 = O.step_sizes(X, B0, gamma)
+        assert r["eta1"] == pytest.approx(e1, rel=2e-5) and r["eta2"] == pytest.approx(e2, rel=2e-5)
+        assert np.max(np.abs(_np(r["E"]) - X @ B0)) < 2e-6
+        assert r["loss"][0] == pytest.approx(O.loss(X, O.init_A(5, 777), B0), rel=1e-5)
+        assert np.all(_np(r["A"]) == np.float32(1 / 5))
+
+
+@gpu
+@pytest.mark.parametrize("L,N,p", [(40, 333, 3), (24, 200, 16)])
+def test_A_phase_only(api, L, N, p):
+    _say(f"A-phase only L={L} N={N} p={p}")
+    s = synth.small_case(seed=7, L=L, N=N, p=min(p, 8))
+    Xg, X = _prep(s.X)
+    r = api.fit(Xg, p, T=6, K1=5, K2=0, gamma=1.0, seed=1)
+    ref = O.edaa_fit(X, p, T=6, K1=5, K2=0, gamma=1.0, seed=1)
+    _compare_run(r, ref, N, loss_rtol=1e-5, ab_atol=2e-5, nb_atol=1e-4)
+
+
+@gpu
+@pytest.mark.parametrize("L,N,p", [(40, 333, 3), (31, 130, 7)])
+def test_B_phase_only(api, L, N, p):
+    _say(f"B-phase only L={L} N={N} p={p}")
+    s = synth.small_case(seed=8, L=L, N=N, p=min(p, 8))
+    Xg, X = _prep(s.X)
+    r = api.fit(Xg, p, T=4, K1=0, K2=5, gamma=2.0, seed=2)
+    ref = O.edaa_fit(X, p, T=4, K1=0, K2=5, gamma=2.0, seed=2)
+    _compare_run(r, ref, N, loss_rtol=1e-5, ab_atol=1e-5, nb_atol=1e-4, e_atol=1e-5)
+
+
+@gpu
+@pytest.mark.parametrize("L,N,p,T", [
+    (40, 333, 3, 30),       # several tiles and a ragged tail
+    (5, 7, 3, 10),          # fewer pixels than one tile
+    (20, 64, 1, 10),        # p = 1, exactly one tile
+    (300, 200, 4, 10),      # L > 256: two accumulation rows per thread
+    (512, 130, 16, 5),      # maximum L and p
+    (33, 129, 16, 8),
+])
+def test_fit_shapes(api, L, N, p, T):
+    _say(f"fit L={L} N={N} p={p} T={T}")
+    s = synth.small_case(seed=9, L=L, N=N, p=min(p, 8))
+    Xg, X = _prep(s.X)
+    r = api.fit(Xg, p, T=T, gamma=1.0, seed=3)
+    ref = O.edaa_fit(X, p, T=T, gamma=1.0, seed=3)
+    _compare_run(r, ref, N, loss_rtol=1e-4, ab_atol=1e-3, nb_atol=1e-2, e_atol=1e-4)
+    # simplex invariants of the GPU result
+    A, B = _np(r["A"]), _np(r["B"])
+    assert np.all(A >= 0) and np.all(B >= 0)
+    assert np.max(np.abs(A.sum(axis=0) - 1)) < 1e-5 and np.max(np.abs(B.sum(axis=0) - 1)) < 1e-5
+    assert np.max(np.abs(_np(r["E"]) - X @ B)) < 1e-5
+
+
+@gpu
+def test_fit_samson_shaped_full(api):
+    """Plain single run at the Samson-shaped size: L=156, N=95x95, p=3,
+    200 outer iterations (the gate of the plain float32 path)."""
+    s, cfg = synth.samson_like()
+    _say("fit samson-shaped L=156 N=9025 p=3 T=200")
+    Xg, X = _prep(s.X)
+    r = api.fit(Xg, 3, T=cfg["T"], gamma=1.0, seed=0)
+    ref = O.edaa_fit(X, 3, T=cfg["T"], gamma=1.0, seed=0)
+    _compare_run(r, ref, X.shape[1], loss_rtol=1e-4, ab_atol=1e-3, nb_atol=5e-2)
+
+
+@gpu
+def test_fit_resume(api):
+    _say("resume: T=6 then 6 more from (A, B, eta)")
+    s = synth.small_case(seed=12, L=30, N=400, p=4)
+    Xg, X = _prep(s.X)
+    r1 = api.fit(Xg, 4, T=6, gamma=1.0, seed=5)
+    r2 = api.fit(Xg, 4, T=6, seed=5, A0=r1["A"], B0=r1["B"], eta=(r1["eta1"], r1["eta2"]))
+    ref = O.edaa_fit(X, 4, T=12, gamma=1.0, seed=5)
+    _compare_run(dict(A=r2["A"], B=r2["B"], loss=r2["loss"]), dict(A=ref["A"], B=ref["B"], loss=ref["loss"][6:]),
+                 400, loss_rtol=1e-5, ab_atol=1e-5, nb_atol=1e-3)
+
+
+@gpu
+def test_determinism_and_graph_replay(api):
+    _say("determinism + graph replay L=48 N=1000 p=4 T=8")
+    s = synth.small_case(seed=13, L=48, N=1000, p=4)
+    Xg, X = _prep(s.X)
+    r1 = api.fit(Xg, 4, T=8, gamma=1.0, seed=7)
+    r2 = api.fit(Xg, 4, T=8, gamma=1.0, seed=7)
+    assert torch.equal(r1["A"], r2["A"]) and torch.equal(r1["B"], r2["B"])
+    assert np.array_equal(r1["loss"], r2["loss"])
+    for rep in range(3):
+        rg = api.fit(Xg, 4, T=8, gamma=1.0, seed=7, graph=True)
+        torch.cuda.synchronize()
+        assert torch.equal(rg["A"], r1["A"]) and torch.equal(rg["B"], r1["B"]), rep
+        assert np.array_equal(rg["loss"], r1["loss"]), rep
+        _ = (Xg * 1.0).sum().item()      # eager work between replays
+
+
+@gpu
+def test_bf16_storage(api):
+    """X stored in bf16: the oracle runs on exactly the bf16 values, so the
+    float32 accumulation must meet the same tolerances as the float32 path."""
+    _say("bf16 X L=64 N=900 p=5 T=15")
+    s = synth.small_case(seed=14, L=64, N=900, p=5)
+    Xg, X = _prep(s.X, dtype=torch.bfloat16)
+    r = api.fit(Xg, 5, T=15, gamma=1.0, seed=2)
+    ref = O.edaa_fit(X, 5, T=15, gamma=1.0, seed=2)
+    _compare_run(r, ref, 900, loss_rtol=1e-4, ab_atol=1e-3, nb_atol=1e-2)
+
+
+@gpu
+def test_invalid_arguments_raise(api):
+    from paper_2209_11002_amd._lib import EdaaError
+    Xg = torch.zeros((10, 20), device="cuda")
+    with pytest.raises(EdaaError, match="EINVAL"):
+        api.fit(Xg, 0)
+    with pytest.raises(EdaaError, match="EINVAL"):
+        api.fit(Xg, 3, gamma=-1.0)
+    with pytest.raises(EdaaError, match="EINVAL"):
+        api.fit(Xg, 21)
+    with pytest.raises(EdaaError, match="EINVAL"):
+        api.fit(torch.zeros((600, 20), device="cuda"), 3)
