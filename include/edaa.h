@@ -25,7 +25,7 @@
  *     available from edaa_last_error() on the calling thread.  A HIP runtime
  *     failure returns EDAA_EDEVICE and poisons the context (later calls on it
  *     return EDAA_EDEVICE).
- *   - Sizes: 1 <= p <= 16, p <= N, 1 <= L <= 512, N < 2^31 / (M p).
+ *   - Sizes: 1 <= p <= 16, p <= N, 1 <= L <= 448, N < 2^31 / (M p).
  */
 #ifndef EDAA_H
 #define EDAA_H

@@ -168,9 +168,9 @@ size_t layout(const Geom& g, int T, char* base, RunBuffers* rb) {
     const size_t o_tsh = a.take<float>((size_t)g.ntiles * g.Qp);
     const size_t o_colm = a.take<float>(g.Qp);
     const size_t o_cols = a.take<float>(g.Qp);
-    const size_t o_E = a.take<float>((size_t)g.L * g.Qp);
+    const size_t o_E = a.take<float>((size_t)(g.L + kPadRows) * g.Qp);
     const size_t o_Ed = a.take<double>((size_t)g.L * g.Qp);
-    const size_t o_W = a.take<float>((size_t)g.L * g.Qp);
+    const size_t o_W = a.take<float>((size_t)(g.L + kPadRows) * g.Qp);
     const size_t o_XAt = a.take<double>((size_t)g.L * g.Qp);
     const size_t o_AAt = a.take<double>((size_t)g.M * g.p * g.p);
     const size_t o_eta = a.take<float>(2 * (size_t)g.M);
@@ -242,8 +242,8 @@ hipError_t enqueue_sequence(const Seq& q, hipStream_t st, long long* launches) {
         ++n;                                  \
     } while (0)
     // zero the padded [L][Qp] arrays (pad columns must read as zero)
-    EDAA_L(launch_fill(s.E, (size_t)g.L * g.Qp, 0.f, st));
-    EDAA_L(launch_fill(s.W, (size_t)g.L * g.Qp, 0.f, st));
+    EDAA_L(launch_fill(s.E, (size_t)(g.L + kPadRows) * g.Qp, 0.f, st));
+    EDAA_L(launch_fill(s.W, (size_t)(g.L + kPadRows) * g.Qp, 0.f, st));
     EDAA_L(launch_fill((float*)s.XAtd, 2 * (size_t)g.L * g.Qp, 0.f, st));
     EDAA_L(launch_fill((float*)s.Ed, 2 * (size_t)g.L * g.Qp, 0.f, st));
     EDAA_L(launch_init_A(g, s, q.A0, st));
@@ -256,6 +256,7 @@ hipError_t enqueue_sequence(const Seq& q, hipStream_t st, long long* launches) {
         EDAA_L(launch_apass(g, s, q.K1, t, st));
         if ((e = tm->mark(st, 0, true)) != hipSuccess) return e;
         EDAA_L(launch_reduce_a(g, s, t, st));
+        ++n;   // launch_reduce_a enqueues two kernels
         for (int k = 0; k < q.K2; ++k) {
             if ((e = tm->mark(st, 1, false)) != hipSuccess) return e;
             EDAA_L(launch_bpass(g, s, kModeStep, q.ri, st));

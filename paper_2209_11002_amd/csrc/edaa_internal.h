@@ -11,9 +11,10 @@ namespace edaa {
 // A workgroup is 4 wave64s and works on tiles of 64 consecutive pixels.
 constexpr int kTile = 64;
 constexpr int kThreads = 256;
-constexpr int kMaxL = 512;
+constexpr int kMaxL = 448;
 constexpr int kMaxP = 16;
 constexpr int kTargetWorkgroups = 512;   // 2 per CU on 256 CUs
+constexpr int kPadRows = 17;             // zero rows after the L rows of E and W
 
 enum PassMode { kModeStep = 0, kModeInitRng = 1, kModeInitB0 = 2 };
 
@@ -27,6 +28,7 @@ struct Geom {
     int Qp;       // padded column count = nqc * QC
     int ntiles;   // ceil(N / 64)
     int npg;      // pixel groups (workgroups per chunk)
+    int dbuf;     // pass kernels double-buffer the X tile in LDS
 };
 
 // Device-side state of a batched problem.  Column q = m * p + j (run m,
@@ -40,9 +42,10 @@ struct State {
     float* tshift;      // [ntiles][Qp] shift used when a tile of Bst was written
     float* colm;        // [Qp] column maximum of the last B-pass
     float* cols;        // [Qp] column sum (relative to colm) of the last B-pass
-    float* E;           // [L][Qp]  endmembers X B (float32 copy read by the passes)
+    float* E;           // [L + kPadRows][Qp]  endmembers X B (float32 copy read by the
+                        // passes; rows >= L are zero)
     double* Ed;         // [L][Qp]  the same in float64
-    float* W;           // [L][Qp]  E (A A^T) - X A^T
+    float* W;           // [L + kPadRows][Qp]  E (A A^T) - X A^T (rows >= L zero)
     double* XAtd;       // [L][Qp]  X A^T
     double* AAtd;       // [M][p][p] A A^T
     float* eta;         // [M][2] step sizes used by the kernels
@@ -118,7 +121,7 @@ size_t pass_lds_bytes(int PP, int R, int L, int kind);
 constexpr size_t kMaxLdsBytes = 160 * 1024;
 
 // Geometry helpers (edaa_kernels.hip).
-int runs_per_chunk(int p, int M);
+int runs_per_chunk(int p, int M, int L);
 Geom make_geom(int L, int N, int M, int p);
 
 }  // namespace edaa

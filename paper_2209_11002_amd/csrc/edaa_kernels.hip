@@ -11,13 +11,19 @@
 //            W = E (A A^T) - X A^T, followed by E <- X B_new
 //            (the new E is accumulated in the same pass over X).
 //
-// Every pass streams X once in tiles of 64 pixels x L bands staged in LDS; the
-// tile serves both contractions of the pass (the per-pixel projection with E or
-// W, and the accumulation X_tile * weights^T over the tile's pixels).  Runs of
-// an ensemble are stacked along the endmember axis, R runs per workgroup
-// column, so that one X tile serves every run.  Cross-workgroup sums go
-// through per-workgroup partials reduced in a fixed order (deterministic); the
-// column softmax over N uses per-tile shifts and an online (max, sum) merge.
+// Every pass streams X once in tiles of 64 pixels x L bands staged in LDS.  A
+// tile serves both contractions of the pass:
+//   * the per-pixel projection S = U^T X_tile (U = E or W, L x QC), and
+//   * the accumulation V += X_tile Wt over the tile's 64 pixels (Wt = the
+//     tile's new abundances or B weights, 64 x QC), which is a dense GEMM run
+//     on the matrix cores (v_mfma_f32_16x16x4f32, float32 in and out).
+// Runs of an ensemble are stacked along the endmember axis, R runs per
+// workgroup column (a "chunk" of QC = R p columns), so one X tile serves every
+// run of the chunk; with R > 1 the projection is an MFMA GEMM as well.  With
+// R = 1 (one run per chunk) the projection is vector FMA with the U operand
+// in scalar registers.  Cross-workgroup sums go through per-workgroup partials
+// reduced in a fixed order (deterministic); the column softmax over N uses
+// per-tile shifts and an online (max, sum) merge.
 #include <math.h>
 
 #include "edaa_internal.h"
@@ -25,7 +31,22 @@
 namespace edaa {
 namespace {
 
-constexpr int kPad = kTile + 1;   // LDS row stride of the X tile (no bank conflicts)
+constexpr int kXS = 68;   // LDS pitch (floats) of an X tile row of 64 pixels
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+// D(16x16) += A(16x4) B(4x16).  Lane l holds A[l % 16][l / 16] and
+// B[l / 16][l % 16]; D[4 (l / 16) + v][l % 16] is element v of its float4.
+__device__ __forceinline__ f4 mfma16(float a, float b, f4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+// The same shape in float64 (v_mfma_f64_16x16x4f64): same A and B lane
+// layout, but element v of lane l's double4 is D[4 v + l / 16][l % 16].
+__device__ __forceinline__ d4 mfma16d(double a, double b, d4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
 
 __device__ __forceinline__ int uniform_int(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
@@ -44,6 +65,35 @@ __device__ __forceinline__ double wave_sum(double v) {
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
     return v;
 }
+
+// Wave-wide max / sum: within each row of 16 lanes by DPP (quad permutes,
+// then row rotations by 4 and 8), then across the 4 rows from lanes 0, 16,
+// 32, 48.  The result is the same in every lane.
+template <int CTRL>
+__device__ __forceinline__ float dpp(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+__device__ __forceinline__ float lane_f(float v, int l) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+__device__ __forceinline__ float wave_max_dpp(float v) {
+    v = fmaxf(v, dpp<0xB1>(v));
+    v = fmaxf(v, dpp<0x4E>(v));
+    v = fmaxf(v, dpp<0x124>(v));
+    v = fmaxf(v, dpp<0x128>(v));
+    return fmaxf(fmaxf(lane_f(v, 0), lane_f(v, 16)), fmaxf(lane_f(v, 32), lane_f(v, 48)));
+}
+__device__ __forceinline__ float wave_sum_dpp(float v) {
+    v += dpp<0xB1>(v);
+    v += dpp<0x4E>(v);
+    v += dpp<0x124>(v);
+    v += dpp<0x128>(v);
+    return (lane_f(v, 0) + lane_f(v, 16)) + (lane_f(v, 32) + lane_f(v, 48));
+}
+
+// e^x and ln x from the hardware base-2 instructions (v_exp_f32, v_log_f32).
+__device__ __forceinline__ float fast_exp(float x) { return __builtin_amdgcn_exp2f(x * 1.4426950408889634f); }
+__device__ __forceinline__ float fast_log(float x) { return __builtin_amdgcn_logf(x) * 0.6931471805599453f; }
 
 __device__ __forceinline__ float bf16_to_f32(uint16_t b) { return __uint_as_float(((uint32_t)b) << 16); }
 
@@ -93,29 +143,49 @@ __device__ __forceinline__ void wg_coords(const Geom& g, int& pg, int& c) {
     }
 }
 
-// Stage X[:, tile*64 : tile*64+64] in LDS as float (zero past N).
-__device__ __forceinline__ void load_tile(const void* X, int x_bf16, int L, int N, int tile, float* Xs) {
+// X tile staging.  dma_tile issues direct global->LDS loads
+// (global_load_lds_dword, no registers involved) of X[:, tile*64 : +64] into
+// rows [0, L) of an LDS tile: wave w loads the rows w, w + 4, ..., one
+// 64-pixel row per instruction.  Lanes past N load pixel N-1; those columns
+// only ever meet a zero weight.  The loads complete asynchronously: the
+// caller waits (s_waitcnt) and synchronises the workgroup before reading.
+// load_tile_sync is the register path used for bf16 X (converted to float).
+__device__ __forceinline__ void dma_tile(const float* X, int L, int N, int tile, float* Xs) {
+    const int lane = threadIdx.x & 63, w = uniform_int(threadIdx.x >> 6);
+    const float* src = X + min(tile * kTile + lane, N - 1);
+    for (int l = w; l < L; l += 4) __builtin_amdgcn_global_load_lds(src + (size_t)l * N, Xs + l * kXS, 4, 0, 0);
+}
+
+__device__ __forceinline__ void load_tile_sync(const void* X, int x_bf16, int L, int N, int tile, float* Xs) {
     const int i = threadIdx.x & 63, r0 = threadIdx.x >> 6;
     const int pix = tile * kTile + i;
     const bool ok = pix < N;
-    if (x_bf16) {
-        const uint16_t* Xh = (const uint16_t*)X;
-#pragma unroll 8
-        for (int l = r0; l < L; l += 4) Xs[l * kPad + i] = ok ? bf16_to_f32(Xh[(size_t)l * N + pix]) : 0.f;
-    } else {
-        const float* Xf = (const float*)X;
-#pragma unroll 8
-        for (int l = r0; l < L; l += 4) Xs[l * kPad + i] = ok ? Xf[(size_t)l * N + pix] : 0.f;
+    const size_t pc = (size_t)min(pix, N - 1);
+    constexpr int B = 16;
+    for (int l0 = r0; l0 < L; l0 += 4 * B) {
+        float v[B];
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+            const size_t off = (size_t)min(l0 + 4 * b, L - 1) * N + pc;
+            v[b] = x_bf16 ? bf16_to_f32(((const uint16_t*)X)[off]) : ((const float*)X)[off];
+        }
+#pragma unroll
+        for (int b = 0; b < B; ++b)
+            if (l0 + 4 * b < L) Xs[(l0 + 4 * b) * kXS + i] = ok ? v[b] : 0.f;
     }
+}
+
+__device__ __forceinline__ void load_tile(const void* X, int x_bf16, int L, int N, int tile, float* Xs) {
+    load_tile_sync(X, x_bf16, L, N, tile, Xs);
 }
 
 // K1 entropic steps of eq. update_A for one pixel: a <- softmax(log a -
 // eta1 (G a - P)), P = E^T x.  The logarithm is carried between steps.
-template <int PP>
-__device__ __forceinline__ void a_steps(float (&a)[PP], const float (&P)[PP], const float* G, float eta1, int K1) {
+template <int PP, typename GT>
+__device__ __forceinline__ void a_steps(float (&a)[PP], const float (&P)[PP], const GT* G, float eta1, int K1) {
     float la[PP];
 #pragma unroll
-    for (int j = 0; j < PP; ++j) la[j] = logf(a[j]);
+    for (int j = 0; j < PP; ++j) la[j] = fast_log(a[j]);
     for (int k = 0; k < K1; ++k) {
         float v[PP];
         float mx = -INFINITY;
@@ -123,7 +193,7 @@ __device__ __forceinline__ void a_steps(float (&a)[PP], const float (&P)[PP], co
         for (int j = 0; j < PP; ++j) {
             float gj = -P[j];
 #pragma unroll
-            for (int kk = 0; kk < PP; ++kk) gj = fmaf(G[j * PP + kk], a[kk], gj);
+            for (int kk = 0; kk < PP; ++kk) gj = fmaf((float)G[j * PP + kk], a[kk], gj);
             v[j] = fmaf(-eta1, gj, la[j]);
             mx = fmaxf(mx, v[j]);
         }
@@ -131,10 +201,10 @@ __device__ __forceinline__ void a_steps(float (&a)[PP], const float (&P)[PP], co
 #pragma unroll
         for (int j = 0; j < PP; ++j) {
             v[j] -= mx;
-            a[j] = expf(v[j]);
+            a[j] = fast_exp(v[j]);
             ssum += a[j];
         }
-        const float inv = 1.f / ssum, lsum = logf(ssum);
+        const float inv = 1.f / ssum, lsum = fast_log(ssum);
 #pragma unroll
         for (int j = 0; j < PP; ++j) {
             a[j] *= inv;
@@ -145,212 +215,361 @@ __device__ __forceinline__ void a_steps(float (&a)[PP], const float (&P)[PP], co
 
 template <int PP, int R>
 struct Shape {
-    static constexpr int QC = PP * R;                          // columns per chunk
-    static constexpr int QCs = (QC + 3) & ~3;                  // LDS row stride of weights
-    static constexpr int RW = (R == 1) ? 1 : R / 4;            // runs per wave (R > 1)
-    static constexpr int AAN = R * PP * PP;                    // A A^T entries per chunk
-    static constexpr int AAT = (AAN + kThreads - 1) / kThreads;
-    static constexpr int CPW = (R == 1) ? (PP + 3) / 4 : RW * PP;   // softmax columns per wave
+    static constexpr int QC = PP * R;                   // columns per chunk
+    static constexpr int QCP = (QC + 15) & ~15;         // padded to MFMA blocks of 16
+    static constexpr int NCB = QCP / 16;                // column blocks
+    static constexpr int WTS = QCP + 1;                 // LDS pitch of the per-pixel weight rows
+    static constexpr int RW = (R + 3) / 4;              // runs per wave in the A-step phase (r = w + 4k < R)
+    static constexpr int CPW = (QC + 3) / 4;            // softmax columns per wave (q = w + 4k)
+    static constexpr int NRBW = (R == 1) ? 8 : 4;       // accumulation row blocks per wave (L <= 512 / 256)
+    static constexpr int NGB = 2 * NCB - 1;             // Gram blocks (qb, qb) and (qb, qb+1)
+    static constexpr int NGBW = (NGB + 3) / 4;          // Gram blocks per wave
 };
 
-// Accumulate V[l][q] += sum_i Xs[l][i] * Ws[i][q] for the rows of this thread.
-template <int QC, int QCs>
-__device__ __forceinline__ void accumulate_rows(float (&V)[2][QC], const float* Xs, const float* Ws, int L) {
+// LDS layout of a pass kernel, in floats.  LP = L rounded up to 16.
+struct PassLds {
+    int xs, wt, f, ec, gs, ps, xx, pd, xs2, total;
+};
+// dbuf: a second X tile buffer, so that the next tile loads while the
+// current one is processed.
+__host__ __device__ inline PassLds pass_lds(int PP, int R, int L, int dbuf = 0) {
+    const int QC = PP * R, QCP = (QC + 15) & ~15, WTS = QCP + 1;
+    const int LP = (L + 15) & ~15;
+    PassLds o;
+    o.xs = 0;
+    o.wt = o.xs + LP * kXS;                    // [64][WTS] weights (also projection results, R > 1)
+    o.f = o.wt + kTile * WTS;                  // [QCP] rescale factors
+    o.ec = o.f + QCP;                          // [LP][WTS] projection operand chunk (E or W)
+    o.gs = o.ec + LP * WTS;                    // [R][PP][PP] Gram matrices (double, 2 floats each)
+    o.gs = (o.gs + 1) & ~1;
+    o.ps = o.gs + 2 * R * PP * PP;
+    o.xx = o.ps;                               // [64] squared pixel norms (double, 2 floats each)
+    o.pd = o.xx + 2 * kTile;                   // [64][WTS] low part of the A-pass projection
+    o.xs2 = o.pd + kTile * WTS;
+    o.total = o.xs2 + (dbuf ? LP * kXS : 0);
+    return o;
+}
+
+// V += X_tile Wt on the matrix cores.  Wave w owns the row blocks
+// rb = w + 4 j (16 bands each) and every column block; with SCALE the
+// running accumulation of column q is first multiplied by F[q].  The B
+// operands (Wt, 64 x QCP) are loaded once per tile and reused for every row
+// block; the optional Gram accumulation Wt^T Wt reuses them as well.
+template <int NCB, int NRBW, int WTS, bool SCALE, int NGBW>
+__device__ __forceinline__ void mfma_accumulate(f4 (&acc)[NRBW][NCB], f4 (&gram)[NGBW], bool do_gram,
+                                                const float* Xs, const float* Wt, const float* F, int nrb, int w,
+                                                int lane) {
+    const int m = lane & 15, kk = lane >> 4;
+    float bop[16][NCB];
 #pragma unroll
-    for (int rr = 0; rr < 2; ++rr) {
-        const int l = threadIdx.x + rr * kThreads;
-        if (l < L) {
-            const float* xr = Xs + l * kPad;
-            for (int i = 0; i < kTile; ++i) {
-                const float x = xr[i];
-                const float* wr = Ws + i * QCs;
+    for (int k = 0; k < 16; ++k)
 #pragma unroll
-                for (int q = 0; q < QC; ++q) V[rr][q] = fmaf(x, wr[q], V[rr][q]);
+        for (int cb = 0; cb < NCB; ++cb) bop[k][cb] = Wt[(4 * k + kk) * WTS + 16 * cb + m];
+#pragma unroll
+    for (int j = 0; j < NRBW; ++j) {
+        const int rb = w + 4 * j;
+        if (rb < nrb) {
+            if (SCALE) {
+#pragma unroll
+                for (int cb = 0; cb < NCB; ++cb) acc[j][cb] *= F[16 * cb + m];
+            }
+            const float* xr = Xs + (16 * rb + m) * kXS + kk;
+#pragma unroll
+            for (int k = 0; k < 16; ++k) {
+                const float a = xr[4 * k];
+#pragma unroll
+                for (int cb = 0; cb < NCB; ++cb) acc[j][cb] = mfma16(a, bop[k][cb], acc[j][cb]);
+            }
+        }
+    }
+    if (do_gram) {
+#pragma unroll
+        for (int gi = 0; gi < NGBW; ++gi) {
+            const int gb = w + 4 * gi;                 // (qb, qb) for even gb, (qb, qb+1) for odd
+            if (gb < 2 * NCB - 1) {
+                const int q1 = gb >> 1, q2 = q1 + (gb & 1);
+#pragma unroll
+                for (int k = 0; k < 16; ++k) {
+                    float a = 0.f, b = 0.f;
+#pragma unroll
+                    for (int cb = 0; cb < NCB; ++cb) {
+                        if (cb == q1) a = bop[k][cb];
+                        if (cb == q2) b = bop[k][cb];
+                    }
+                    gram[gi] = mfma16(a, b, gram[gi]);
+                }
             }
         }
     }
 }
 
+// Write the accumulated V (rows < L, columns < QC) of this workgroup.
+template <int NCB, int NRBW, int QC>
+__device__ __forceinline__ void store_acc(const f4 (&acc)[NRBW][NCB], float* Vp, int L, int nrb, int w, int lane) {
+    const int m = lane & 15, kk = lane >> 4;
+#pragma unroll
+    for (int j = 0; j < NRBW; ++j) {
+        const int rb = w + 4 * j;
+        if (rb < nrb)
+#pragma unroll
+            for (int cb = 0; cb < NCB; ++cb) {
+                const int q = 16 * cb + m;
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int l = 16 * rb + 4 * kk + v;
+                    if (l < L && q < QC) Vp[(size_t)l * QC + q] = acc[j][cb][v];
+                }
+            }
+    }
+}
+
+// Projection of the tile by a chunk operand staged in LDS (R > 1): wave w
+// computes the 16 pixels 16w..16w+15 for all QCP columns, S[q][i] =
+// sum_l Ec[l][q] Xs[l][i]; results go to Sc[i][q].  Also returns, for the
+// same pixels, the partial sums of x^2 over the bands this lane touched.
+template <int NCB, int WTS>
+__device__ __forceinline__ float mfma_project(const float* Ec, const float* Xs, float* Sc, int LK, int w, int lane) {
+    const int m = lane & 15, kk = lane >> 4;
+    f4 s[NCB];
+#pragma unroll
+    for (int cb = 0; cb < NCB; ++cb) s[cb] = f4{0.f, 0.f, 0.f, 0.f};
+    float xx = 0.f;
+    const float* xb = Xs + kk * kXS + 16 * w + m;
+    const float* eb = Ec + kk * WTS + m;
+    for (int k = 0; k < LK; k += 4) {
+        const float b = xb[k * kXS];
+        xx = fmaf(b, b, xx);
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb) s[cb] = mfma16(eb[k * WTS + 16 * cb], b, s[cb]);
+    }
+#pragma unroll
+    for (int cb = 0; cb < NCB; ++cb)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) Sc[(16 * w + m) * WTS + 16 * cb + 4 * kk + v] = s[cb][v];
+    return xx;
+}
+
+// The A-pass projection in float64: P = E^T x feeds the objective
+// ||x - E a||^2 = ||x||^2 - 2 a.P + a.G a, whose terms are of order ||x||^2
+// while the result is of the order of the residual, so P and ||x||^2 are
+// accumulated in float64 (products of float32 values are exact in float64).
+// P is kept as a float pair, hi = fl(P) (used by the A-steps) and
+// lo = fl(P - hi), which carries it to about 48 bits; returns the partial
+// ||x||^2 of this lane's bands.
+template <int NCB, int WTS>
+__device__ __forceinline__ double mfma_project_f64(const float* Ec, const float* Xs, float* Sc, float* Plo, int LK,
+                                                   int w, int lane) {
+    const int m = lane & 15, kk = lane >> 4;
+    d4 s[NCB];
+#pragma unroll
+    for (int cb = 0; cb < NCB; ++cb) s[cb] = d4{0.0, 0.0, 0.0, 0.0};
+    double xx = 0.0;
+    const float* xb = Xs + kk * kXS + 16 * w + m;
+    const float* eb = Ec + kk * WTS + m;
+    for (int k = 0; k < LK; k += 4) {
+        const double b = (double)xb[k * kXS];
+        xx = fma(b, b, xx);
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb) s[cb] = mfma16d((double)eb[k * WTS + 16 * cb], b, s[cb]);
+    }
+#pragma unroll
+    for (int cb = 0; cb < NCB; ++cb)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const float hi = (float)s[cb][v];
+            Sc[(16 * w + m) * WTS + 16 * cb + 4 * v + kk] = hi;
+            Plo[(16 * w + m) * WTS + 16 * cb + 4 * v + kk] = (float)(s[cb][v] - (double)hi);
+        }
+    return xx;
+}
+
+// Stage U[:, chunk] (rows < L, QCP columns) in LDS with rows L..LP-1 zero.
+template <int QC, int QCP, int WTS>
+__device__ __forceinline__ void stage_chunk(const float* __restrict__ U, int Qp, int col0, int L, int LP, float* Ec) {
+    for (int e = threadIdx.x; e < LP * QCP; e += kThreads) {
+        const int l = e / QCP, q = e % QCP;
+        Ec[l * WTS + q] = (l < L && q < QC) ? U[(size_t)l * Qp + col0 + q] : 0.f;
+    }
+}
+
 // --------------------------------------------------------------------------
-// A-pass: per tile, residual at the incoming (A, E) for the objective trace,
+// A-pass: per tile, the objective at the incoming (A, E) for the trace,
 // P = E^T x, K1 A-steps, write A, accumulate X A^T and A A^T partials.
 // --------------------------------------------------------------------------
 template <int PP, int R>
-__global__ __launch_bounds__(kThreads, 2) void k_apass(Geom g, State s, const float* __restrict__ E, int K1) {
+__global__ __launch_bounds__(kThreads, 1) void k_apass(Geom g, State s, const float* __restrict__ E, int K1) {
     using S = Shape<PP, R>;
-    constexpr int QC = S::QC, QCs = S::QCs, RW = S::RW, AAN = S::AAN, AAT = S::AAT;
+    constexpr int QC = S::QC, QCP = S::QCP, NCB = S::NCB, WTS = S::WTS, RW = S::RW, NRBW = S::NRBW;
+    constexpr int NGBW = S::NGBW;
     extern __shared__ float smem[];
-    float* Xs = smem;                         // [L][kPad]
-    float* As = Xs + g.L * kPad;              // [kTile][QCs]
-    float* Gs = As + kTile * QCs;             // [R][PP][PP]
-    float* Ps = Gs + AAN;                     // R == 1: [4][kTile][PP]
-    float* Ls = Ps + 4 * kTile * PP;          // R == 1: [4][kTile]
+    const PassLds lo = pass_lds(PP, R, g.L, g.dbuf);
+    float* Xs = smem + lo.xs;
+    float* Wt = smem + lo.wt;
+    float* Ec = smem + lo.ec;
+    double* Gd = (double*)(smem + lo.gs);
+    float* Xb[2] = {Xs, g.dbuf ? smem + lo.xs2 : Xs};
+    double* XX = (double*)(smem + lo.xx);
+    float* Plo = smem + lo.pd;
 
     int pg, c;
     wg_coords(g, pg, c);
     const int tid = threadIdx.x, lane = tid & 63;
     const int w = uniform_int(tid >> 6);
-    const int L = g.L, N = g.N;
+    const int L = g.L, N = g.N, LP = (L + 15) & ~15, nrb = LP / 16;
     const int col0 = c * QC;
     float* __restrict__ A = s.A;
 
-    // Gram matrices G_m = E_m^T E_m of this chunk's runs, from the E chunk
-    // staged in the (not yet used) X tile buffer.
-    for (int e = tid; e < L * QC; e += kThreads) {
-        const int l = e / QC, q = e % QC;
-        Xs[e] = E[(size_t)l * g.Qp + col0 + q];
+    // Gram matrices of this chunk's runs, in float64 from the float32 E the
+    // projection uses (so that the objective formed from P and G below is
+    // consistent with that E).
+    stage_chunk<QC, QCP, WTS>(E, g.Qp, col0, L, LP, Ec);
+    __syncthreads();
+    for (int e = tid; e < R * PP * PP; e += kThreads) {
+        const int r = e / (PP * PP), jk = e % (PP * PP), j = jk / PP, k = jk % PP;
+        const float* Ek = Ec + r * PP;
+        double acc = 0.0;
+        for (int l = 0; l < L; ++l) acc = fma((double)Ek[l * WTS + j], (double)Ek[l * WTS + k], acc);
+        Gd[e] = acc;
     }
     __syncthreads();
-    for (int e = tid; e < AAN; e += kThreads) {
-        const int r = e / (PP * PP), jk = e % (PP * PP), j = jk / PP, k = jk % PP;
-        const float* Ec = Xs + r * PP;
-        float acc = 0.f;
-        for (int l = 0; l < L; ++l) acc = fmaf(Ec[l * QC + j], Ec[l * QC + k], acc);
-        Gs[e] = acc;
+    // zero the X rows beyond L and the weight padding (never written later)
+    for (int e = tid; e < (LP - L) * kXS; e += kThreads) {
+        Xb[0][L * kXS + e] = 0.f;
+        Xb[1][L * kXS + e] = 0.f;
     }
+    for (int e = tid; e < kTile * WTS; e += kThreads) Wt[e] = 0.f;
 
-    float V[2][QC];
+    f4 acc[NRBW][NCB], gram[NGBW];
 #pragma unroll
-    for (int rr = 0; rr < 2; ++rr)
+    for (int j = 0; j < NRBW; ++j)
 #pragma unroll
-        for (int q = 0; q < QC; ++q) V[rr][q] = 0.f;
-    float aa[AAT];
+        for (int cb = 0; cb < NCB; ++cb) acc[j][cb] = f4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int e = 0; e < AAT; ++e) aa[e] = 0.f;
+    for (int j = 0; j < NGBW; ++j) gram[j] = f4{0.f, 0.f, 0.f, 0.f};
     double lacc[RW];
 #pragma unroll
     for (int r = 0; r < RW; ++r) lacc[r] = 0.0;
 
-    for (int tile = pg; tile < g.ntiles; tile += g.npg) {
+    // Pipeline: the X tile (direct-to-LDS loads) and this thread's
+    // abundances (registers) of tile t + npg are requested while tile t is
+    // processed.
+    const bool dma = !s.x_bf16;
+    float an[RW][PP];
+    auto load_a = [&](int tile) {
+        const size_t pixc = (size_t)min(tile * kTile + lane, N - 1);
+#pragma unroll
+        for (int k = 0; k < RW; ++k) {
+            const int m = c * R + min(w + 4 * k, R - 1);
+#pragma unroll
+            for (int j = 0; j < PP; ++j) an[k][j] = A[(size_t)(min(m, g.M - 1) * PP + j) * N + pixc];
+        }
+    };
+    __syncthreads();
+    if (pg < g.ntiles) {
+        if (dma) dma_tile((const float*)s.X, L, N, pg, Xb[0]);
+        load_a(pg);
+    }
+    int it = 0;
+    for (int tile = pg; tile < g.ntiles; tile += g.npg, ++it) {
+        float* Xs = Xb[it & 1];
+        if (!dma) {
+            __syncthreads();
+            load_tile_sync(s.X, s.x_bf16, L, N, tile, Xs);
+        }
+        __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();
-        load_tile(s.X, s.x_bf16, L, N, tile, Xs);
         const int pix = tile * kTile + lane;
         const bool pok = pix < N;
-        __syncthreads();
-        if constexpr (R == 1) {
-            const int m = c;   // single run
-            float a[PP], P[PP];
+        float a[RW][PP];
 #pragma unroll
-            for (int j = 0; j < PP; ++j) {
-                a[j] = pok ? A[(size_t)(m * PP + j) * N + pix] : 0.f;
-                P[j] = 0.f;
-            }
-            float ls = 0.f;
-            const int Lq = (L + 3) >> 2, l0 = w * Lq, l1 = min(L, l0 + Lq);
-            for (int l = l0; l < l1; ++l) {
-                const float x = Xs[l * kPad + lane];
-                const float* El = E + (size_t)l * g.Qp + col0;
-                float r = x;
+        for (int k = 0; k < RW; ++k) {
+            const int m = c * R + w + 4 * k;
+            const bool mok = m < g.M && w + 4 * k < R;
 #pragma unroll
-                for (int j = 0; j < PP; ++j) {
-                    const float e = El[j];
-                    P[j] = fmaf(e, x, P[j]);
-                    r = fmaf(-e, a[j], r);
-                }
-                ls = fmaf(r, r, ls);
-            }
-#pragma unroll
-            for (int j = 0; j < PP; ++j) Ps[(w * kTile + lane) * PP + j] = P[j];
-            Ls[w * kTile + lane] = ls;
+            for (int j = 0; j < PP; ++j) a[k][j] = (mok && pok) ? an[k][j] : 0.f;
+        }
+        const int nt = tile + g.npg;
+        if (nt < g.ntiles) {
+            load_a(nt);
+            if (dma && g.dbuf) dma_tile((const float*)s.X, L, N, nt, Xb[(it + 1) & 1]);
+        }
+        {
+            // projection on the matrix cores: P for pixels 16w..16w+15
+            double xx = mfma_project_f64<NCB, WTS>(Ec, Xs, Wt, Plo, (L + 3) & ~3, w, lane);
+            xx += __shfl_xor(xx, 16);       // the 4 band classes of the pixel
+            xx += __shfl_xor(xx, 32);
+            if (lane < 16) XX[16 * w + lane] = xx;
             __syncthreads();
-            if (w == 0) {
+            // A-steps: lane = pixel, runs r = w + 4k of the chunk
+            const double xnorm = XX[lane];
 #pragma unroll
-                for (int j = 0; j < PP; ++j)
-                    P[j] = Ps[lane * PP + j] + Ps[(kTile + lane) * PP + j] + Ps[(2 * kTile + lane) * PP + j] +
-                           Ps[(3 * kTile + lane) * PP + j];
-                const float lsum = Ls[lane] + Ls[kTile + lane] + Ls[2 * kTile + lane] + Ls[3 * kTile + lane];
-                if (pok) lacc[0] += (double)lsum;
-                a_steps<PP>(a, P, Gs, s.eta[2 * m], K1);
+            for (int k = 0; k < RW; ++k) {
+                const int r = w + 4 * k, m = c * R + r;
+                if (r >= R) continue;                 // uniform per wave
+                const bool mok = m < g.M;
+                float P[PP];
 #pragma unroll
-                for (int j = 0; j < PP; ++j) {
-                    if (pok) A[(size_t)(m * PP + j) * N + pix] = a[j];
-                    As[lane * QCs + j] = pok ? a[j] : 0.f;
-                }
-            }
-        } else {
-            float a[RW][PP], P[RW][PP], ls[RW];
-#pragma unroll
-            for (int r = 0; r < RW; ++r) {
-                const int m = c * R + w * RW + r;
-                const bool rok = pok && m < g.M;
-#pragma unroll
-                for (int j = 0; j < PP; ++j) {
-                    a[r][j] = rok ? A[(size_t)(m * PP + j) * N + pix] : 0.f;
-                    P[r][j] = 0.f;
-                }
-                ls[r] = 0.f;
-            }
-            const float* Ew = E + col0 + w * RW * PP;
-            for (int l = 0; l < L; ++l) {
-                const float x = Xs[l * kPad + lane];
-                const float* El = Ew + (size_t)l * g.Qp;
-#pragma unroll
-                for (int r = 0; r < RW; ++r) {
-                    float rv = x;
+                for (int j = 0; j < PP; ++j) P[j] = Wt[lane * WTS + r * PP + j];
+                const double* Gr = Gd + r * PP * PP;
+                if (mok && pok) {
+                    // ||x - E a||^2 = ||x||^2 - 2 a.P + a.G a, in float64
+                    double q = xnorm;
 #pragma unroll
                     for (int j = 0; j < PP; ++j) {
-                        const float e = El[r * PP + j];
-                        P[r][j] = fmaf(e, x, P[r][j]);
-                        rv = fmaf(-e, a[r][j], rv);
-                    }
-                    ls[r] = fmaf(rv, rv, ls[r]);
-                }
-            }
+                        double ga = 0.0;
 #pragma unroll
-            for (int r = 0; r < RW; ++r) {
-                const int m = c * R + w * RW + r;
-                const bool mok = m < g.M;
-                if (mok) {
-                    if (pok) lacc[r] += (double)ls[r];
-                    a_steps<PP>(a[r], P[r], Gs + (w * RW + r) * PP * PP, s.eta[2 * m], K1);
+                        for (int kk = 0; kk < PP; ++kk) ga = fma(Gr[j * PP + kk], (double)a[k][kk], ga);
+                        const double pj = (double)P[j] + (double)Plo[lane * WTS + r * PP + j];
+                        q = fma((double)a[k][j], ga - 2.0 * pj, q);
+                    }
+                    lacc[k] += q;
                 }
+                if (mok) a_steps<PP>(a[k], P, Gr, s.eta[2 * m], K1);
 #pragma unroll
                 for (int j = 0; j < PP; ++j) {
-                    if (mok && pok) A[(size_t)(m * PP + j) * N + pix] = a[r][j];
-                    As[lane * QCs + (w * RW + r) * PP + j] = (mok && pok) ? a[r][j] : 0.f;
+                    if (mok && pok) A[(size_t)(m * PP + j) * N + pix] = a[k][j];
+                    Wt[lane * WTS + r * PP + j] = (mok && pok) ? a[k][j] : 0.f;
                 }
             }
         }
         __syncthreads();
-        accumulate_rows<QC, QCs>(V, Xs, As, L);
-#pragma unroll
-        for (int e = 0; e < AAT; ++e) {
-            const int idx = tid + e * kThreads;
-            if (idx < AAN) {
-                const int r = idx / (PP * PP), jk = idx % (PP * PP), j = jk / PP, k = jk % PP;
-                float acc = aa[e];
-                for (int i = 0; i < kTile; ++i) acc = fmaf(As[i * QCs + r * PP + j], As[i * QCs + r * PP + k], acc);
-                aa[e] = acc;
-            }
+        mfma_accumulate<NCB, NRBW, WTS, false, NGBW>(acc, gram, true, Xs, Wt, nullptr, nrb, w, lane);
+        if (nt < g.ntiles && dma && !g.dbuf) {
+            __syncthreads();                        // single buffer: reload after every reader
+            dma_tile((const float*)s.X, L, N, nt, Xs);
         }
     }
 
     const size_t wgi = (size_t)pg * g.nqc + c;
-    float* Vp = s.Vpart + wgi * (size_t)L * QC;
+    store_acc<NCB, NRBW, QC>(acc, s.Vpart + wgi * (size_t)L * QC, L, nrb, w, lane);
+    // A A^T of every run from the Gram blocks: entry (q1, q2) of block
+    // (qb1, qb2) with q1 = 16 qb1 + 4 (lane/16) + v, q2 = 16 qb2 + lane%16.
+    {
+        const int m16 = lane & 15, kk = lane >> 4;
+        float* AAp = s.AApart + wgi * (size_t)(R * PP * PP);
 #pragma unroll
-    for (int rr = 0; rr < 2; ++rr) {
-        const int l = tid + rr * kThreads;
-        if (l < L)
+        for (int gi = 0; gi < NGBW; ++gi) {
+            const int gb = w + 4 * gi;
+            if (gb < 2 * NCB - 1) {
+                const int qb1 = gb >> 1, qb2 = qb1 + (gb & 1);
 #pragma unroll
-            for (int q = 0; q < QC; ++q) Vp[(size_t)l * QC + q] = V[rr][q];
+                for (int v = 0; v < 4; ++v) {
+                    const int q1 = 16 * qb1 + 4 * kk + v, q2 = 16 * qb2 + m16;
+                    if (q1 < QC && q2 < QC && q1 / PP == q2 / PP) {
+                        const int r = q1 / PP, j = q1 % PP, k = q2 % PP;
+                        AAp[r * PP * PP + j * PP + k] = gram[gi][v];
+                        if (qb1 != qb2) AAp[r * PP * PP + k * PP + j] = gram[gi][v];
+                    }
+                }
+            }
+        }
     }
 #pragma unroll
-    for (int e = 0; e < AAT; ++e) {
-        const int idx = tid + e * kThreads;
-        if (idx < AAN) s.AApart[wgi * AAN + idx] = aa[e];
-    }
-    if constexpr (R == 1) {
-        if (w == 0) {
-            const double tot = wave_sum(lacc[0]);
-            if (lane == 0) s.lpart[(size_t)pg * g.M + c] = tot;
-        }
-    } else {
-#pragma unroll
-        for (int r = 0; r < RW; ++r) {
-            const int m = c * R + w * RW + r;
-            const double tot = wave_sum(lacc[r]);
-            if (lane == 0 && m < g.M) s.lpart[(size_t)pg * g.M + m] = tot;
-        }
+    for (int k = 0; k < RW; ++k) {
+        const int r = w + 4 * k, m = c * R + r;
+        if (r >= R) continue;
+        const double tot = wave_sum(lacc[k]);
+        if (lane == 0 && m < g.M) s.lpart[(size_t)pg * g.M + m] = tot;
     }
 }
 
@@ -361,172 +580,183 @@ __global__ __launch_bounds__(kThreads, 2) void k_apass(Geom g, State s, const fl
 // tile's shift; accumulate X * weights^T.
 // --------------------------------------------------------------------------
 template <int PP, int R>
-__global__ __launch_bounds__(kThreads, 2) void k_bpass(Geom g, State s, const float* __restrict__ W, int mode,
-                                                        RunInit ri) {
+__global__ __launch_bounds__(kThreads, 1) void k_bpass(Geom g, State s, const float* __restrict__ W, int mode,
+                                                       RunInit ri) {
     using S = Shape<PP, R>;
-    constexpr int QC = S::QC, QCs = S::QCs, RW = S::RW, CPW = S::CPW;
+    constexpr int QC = S::QC, QCP = S::QCP, NCB = S::NCB, WTS = S::WTS, CPW = S::CPW, NRBW = S::NRBW;
     extern __shared__ float smem[];
-    float* Xs = smem;                         // [L][kPad]
-    float* Ws = Xs + g.L * kPad;              // [kTile][QCs]
-    float* Fs = Ws + kTile * QCs;             // [QCs]
-    float* Ps = Fs + QCs;                     // R == 1: [4][kTile][PP]
+    const PassLds lo = pass_lds(PP, R, g.L, g.dbuf);
+    float* Xs = smem + lo.xs;
+    float* Wt = smem + lo.wt;
+    float* F = smem + lo.f;
+    float* Ec = smem + lo.ec;
+    float* Xb[2] = {Xs, g.dbuf ? smem + lo.xs2 : Xs};
 
     int pg, c;
     wg_coords(g, pg, c);
     const int tid = threadIdx.x, lane = tid & 63;
     const int w = uniform_int(tid >> 6);
-    const int L = g.L, N = g.N;
+    const int L = g.L, N = g.N, LP = (L + 15) & ~15, nrb = LP / 16;
     const int col0 = c * QC;
+    const bool step = (mode == kModeStep);
 
-    // Columns owned by this wave for the softmax part: local column index
-    // (within the chunk), run and endmember.
-    int qloc[CPW], mrun_idx[CPW], jend[CPW];
-    bool qok[CPW];
-#pragma unroll
-    for (int k = 0; k < CPW; ++k) {
-        if constexpr (R == 1) {
-            const int j = w + 4 * k;
-            qloc[k] = j; mrun_idx[k] = c; jend[k] = j;
-            qok[k] = j < PP;
-        } else {
-            const int r = k / PP, j = k % PP;
-            qloc[k] = (w * RW + r) * PP + j; mrun_idx[k] = c * R + w * RW + r; jend[k] = j;
-            qok[k] = mrun_idx[k] < g.M;
-        }
+    for (int e = tid; e < (LP - L) * kXS; e += kThreads) {
+        Xb[0][L * kXS + e] = 0.f;
+        Xb[1][L * kXS + e] = 0.f;
     }
+    for (int e = tid; e < kTile * WTS; e += kThreads) Wt[e] = 0.f;
+    for (int e = tid; e < QCP; e += kThreads) F[e] = 0.f;
+    if (step) stage_chunk<QC, QCP, WTS>(W, g.Qp, col0, L, LP, Ec);
+
+    // softmax columns of this wave: q = w + 4k (uniform per wave)
     float mrun[CPW], srun[CPW], lzc[CPW], eta2[CPW];
 #pragma unroll
     for (int k = 0; k < CPW; ++k) {
-        mrun[k] = -INFINITY; srun[k] = 0.f; lzc[k] = 0.f; eta2[k] = 0.f;
-        if (qok[k] && mode == kModeStep) {
-            const int qp = col0 + qloc[k];
-            lzc[k] = -s.colm[qp] - logf(s.cols[qp]);
-            eta2[k] = s.eta[2 * mrun_idx[k] + 1];
+        const int q = w + 4 * k, m = c * R + q / PP;
+        mrun[k] = -INFINITY;
+        srun[k] = 0.f;
+        lzc[k] = 0.f;
+        eta2[k] = 0.f;
+        if (q < QC && m < g.M && step) {
+            lzc[k] = -s.colm[col0 + q] - logf(s.cols[col0 + q]);
+            eta2[k] = s.eta[2 * m + 1];
         }
     }
 
-    float V[2][QC];
+    f4 acc[NRBW][NCB], gdummy[1];
 #pragma unroll
-    for (int rr = 0; rr < 2; ++rr)
+    for (int j = 0; j < NRBW; ++j)
 #pragma unroll
-        for (int q = 0; q < QC; ++q) V[rr][q] = 0.f;
+        for (int cb = 0; cb < NCB; ++cb) acc[j][cb] = f4{0.f, 0.f, 0.f, 0.f};
 
-    for (int tile = pg; tile < g.ntiles; tile += g.npg) {
-        __syncthreads();
-        load_tile(s.X, s.x_bf16, L, N, tile, Xs);
-        const int pix = tile * kTile + lane;
-        const bool pok = pix < N;
-        __syncthreads();
-
-        float gv[CPW];
-#pragma unroll
-        for (int k = 0; k < CPW; ++k) gv[k] = 0.f;
-        if (mode == kModeStep) {
-            if constexpr (R == 1) {
-                float P[PP];
-#pragma unroll
-                for (int j = 0; j < PP; ++j) P[j] = 0.f;
-                const int Lq = (L + 3) >> 2, l0 = w * Lq, l1 = min(L, l0 + Lq);
-                for (int l = l0; l < l1; ++l) {
-                    const float x = Xs[l * kPad + lane];
-                    const float* Wl = W + (size_t)l * g.Qp + col0;
-#pragma unroll
-                    for (int j = 0; j < PP; ++j) P[j] = fmaf(Wl[j], x, P[j]);
-                }
-#pragma unroll
-                for (int j = 0; j < PP; ++j) Ps[(w * kTile + lane) * PP + j] = P[j];
-                __syncthreads();
-#pragma unroll
-                for (int k = 0; k < CPW; ++k)
-                    if (qok[k]) {
-                        const int j = jend[k];
-                        gv[k] = Ps[lane * PP + j] + Ps[(kTile + lane) * PP + j] + Ps[(2 * kTile + lane) * PP + j] +
-                                Ps[(3 * kTile + lane) * PP + j];
-                    }
-            } else {
-                const float* Ww = W + col0 + w * RW * PP;
-                for (int l = 0; l < L; ++l) {
-                    const float x = Xs[l * kPad + lane];
-                    const float* Wl = Ww + (size_t)l * g.Qp;
-#pragma unroll
-                    for (int k = 0; k < CPW; ++k) gv[k] = fmaf(Wl[k], x, gv[k]);
-                }
-            }
-        }
-
+    // Pipeline: the X tile (direct-to-LDS loads) and this wave's B state and
+    // shifts (registers) of tile t + npg are requested while tile t is
+    // processed.
+    const bool dma = !s.x_bf16;
+    float bn[CPW], tn[CPW];
+    auto load_b = [&](int tile) {
+        const size_t pixc = (size_t)min(tile * kTile + lane, N - 1);
 #pragma unroll
         for (int k = 0; k < CPW; ++k) {
-            if (!qok[k]) {
-                if constexpr (R != 1) {
-                    Ws[lane * QCs + qloc[k]] = 0.f;
-                    if (lane == 0) Fs[qloc[k]] = 0.f;
-                }
-                continue;
+            const int q = w + 4 * k, m = c * R + q / PP, j = q % PP;
+            bn[k] = 1.f;
+            tn[k] = 0.f;
+            if (step && q < QC && m < g.M) {
+                bn[k] = s.Bst[(size_t)(m * PP + j) * N + pixc];
+                tn[k] = s.tshift[(size_t)tile * g.Qp + col0 + q];
             }
-            const int m = mrun_idx[k], j = jend[k], q = m * PP + j, qp = col0 + qloc[k];
-            float v = -INFINITY;
-            if (pok) {
-                if (mode == kModeStep) {
-                    const float b = s.Bst[(size_t)q * N + pix];
-                    v = logf(b) + (s.tshift[(size_t)tile * g.Qp + qp] + lzc[k]) - eta2[k] * gv[k];
+        }
+    };
+    __syncthreads();
+    if (pg < g.ntiles) {
+        if (dma) dma_tile((const float*)s.X, L, N, pg, Xb[0]);
+        load_b(pg);
+    }
+    int it = 0;
+    for (int tile = pg; tile < g.ntiles; tile += g.npg, ++it) {
+        float* Xs = Xb[it & 1];
+        if (!dma) {
+            __syncthreads();
+            load_tile_sync(s.X, s.x_bf16, L, N, tile, Xs);
+        }
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+        const int pix = tile * kTile + lane;
+        const bool pok = pix < N;
+        float bv[CPW], ts[CPW];
+#pragma unroll
+        for (int k = 0; k < CPW; ++k) {
+            bv[k] = bn[k];
+            ts[k] = tn[k];
+        }
+        const int nt = tile + g.npg;
+        if (nt < g.ntiles) {
+            load_b(nt);
+            if (dma && g.dbuf) dma_tile((const float*)s.X, L, N, nt, Xb[(it + 1) & 1]);
+        }
+
+        if (step) {
+            (void)mfma_project<NCB, WTS>(Ec, Xs, Wt, (L + 3) & ~3, w, lane);
+            __syncthreads();
+        }
+
+        // softmax part, in phases so that the reductions of the owned
+        // columns are independent of each other
+        float v[CPW], wv[CPW], mnew[CPW], f[CPW];
+#pragma unroll
+        for (int k = 0; k < CPW; ++k) {
+            const int q = w + 4 * k, m = c * R + q / PP, j = q % PP;
+            v[k] = -INFINITY;
+            if (q < QC && m < g.M && pok) {
+                if (step) {
+                    const float gv = Wt[lane * WTS + q];
+                    v[k] = fast_log(bv[k]) + (ts[k] + lzc[k]) - eta2[k] * gv;
                 } else if (mode == kModeInitRng) {
-                    v = ri.init_scale * uniform_u(ri.seeds[m], pix, j);
+                    v[k] = ri.init_scale * uniform_u(ri.seeds[m], pix, j);
                 } else {
-                    v = logf(ri.B0[(size_t)pix * PP + j]);
+                    v[k] = fast_log(ri.B0[(size_t)pix * PP + j]);
                 }
             }
-            const float mt = wave_max(v);
-            const float mnew = fmaxf(mrun[k], mt);
-            const float f = (mrun[k] == -INFINITY) ? 0.f : expf(mrun[k] - mnew);
-            const float wv = (v == -INFINITY) ? 0.f : expf(v - mnew);
-            srun[k] = srun[k] * f + wave_sum(wv);
-            mrun[k] = mnew;
-            if (pok) s.Bst[(size_t)q * N + pix] = wv;
-            if (lane == 0) {
-                s.tshift[(size_t)tile * g.Qp + qp] = mnew;
-                Fs[qloc[k]] = f;
+        }
+#pragma unroll
+        for (int k = 0; k < CPW; ++k) {
+            const int q = w + 4 * k, m = c * R + q / PP;
+            if (q < QC && m < g.M) {
+                mnew[k] = fmaxf(mrun[k], wave_max_dpp(v[k]));
+                f[k] = (mrun[k] == -INFINITY) ? 0.f : fast_exp(mrun[k] - mnew[k]);
+                wv[k] = (v[k] == -INFINITY) ? 0.f : fast_exp(v[k] - mnew[k]);
             }
-            Ws[lane * QCs + qloc[k]] = wv;
+        }
+#pragma unroll
+        for (int k = 0; k < CPW; ++k) {
+            const int q = w + 4 * k, m = c * R + q / PP, j = q % PP;
+            if (q < QC && m < g.M) {
+                srun[k] = srun[k] * f[k] + wave_sum_dpp(wv[k]);
+                mrun[k] = mnew[k];
+                if (pok) s.Bst[(size_t)(m * PP + j) * N + pix] = wv[k];
+                if (lane == 0) {
+                    s.tshift[(size_t)tile * g.Qp + col0 + q] = mnew[k];
+                    F[q] = f[k];
+                }
+                Wt[lane * WTS + q] = wv[k];
+            } else if (q < QC) {                         // unused run slot of the last chunk
+                Wt[lane * WTS + q] = 0.f;
+                if (lane == 0) F[q] = 0.f;
+            }
         }
         __syncthreads();
-        // rescale the running accumulation to the new shifts, then add the tile
-#pragma unroll
-        for (int rr = 0; rr < 2; ++rr)
-#pragma unroll
-            for (int q = 0; q < QC; ++q) V[rr][q] *= Fs[q];
-        accumulate_rows<QC, QCs>(V, Xs, Ws, L);
+        mfma_accumulate<NCB, NRBW, WTS, true, 1>(acc, gdummy, false, Xs, Wt, F, nrb, w, lane);
+        if (nt < g.ntiles && dma && !g.dbuf) {
+            __syncthreads();                        // single buffer: reload after every reader
+            dma_tile((const float*)s.X, L, N, nt, Xs);
+        }
     }
 
     const size_t wgi = (size_t)pg * g.nqc + c;
-    float* Vp = s.Vpart + wgi * (size_t)L * QC;
-#pragma unroll
-    for (int rr = 0; rr < 2; ++rr) {
-        const int l = tid + rr * kThreads;
-        if (l < L)
-#pragma unroll
-            for (int q = 0; q < QC; ++q) Vp[(size_t)l * QC + q] = V[rr][q];
-    }
+    store_acc<NCB, NRBW, QC>(acc, s.Vpart + wgi * (size_t)L * QC, L, nrb, w, lane);
     if (lane == 0) {
 #pragma unroll
         for (int k = 0; k < CPW; ++k) {
-            if (!qok[k] && R == 1) continue;
-            const int qp = col0 + qloc[k];
-            s.mpart[(size_t)pg * g.Qp + qp] = qok[k] ? mrun[k] : -INFINITY;
-            s.spart[(size_t)pg * g.Qp + qp] = qok[k] ? srun[k] : 0.f;
+            const int q = w + 4 * k, m = c * R + q / PP;
+            if (q >= QC) continue;
+            const bool ok = m < g.M;
+            s.mpart[(size_t)pg * g.Qp + col0 + q] = ok ? mrun[k] : -INFINITY;
+            s.spart[(size_t)pg * g.Qp + col0 + q] = ok ? srun[k] : 0.f;
         }
     }
 }
 
 // --------------------------------------------------------------------------
-// Closing pass: objective and l1 fit of every run at the final (A, E).
+// Closing pass: objective and l1 fit of every run at the final (A, E), from
+// the per-band residual (the l1 fit needs it band by band).
 // --------------------------------------------------------------------------
 template <int PP, int R>
 __global__ __launch_bounds__(kThreads, 2) void k_close(Geom g, State s, const float* __restrict__ E) {
-    using S = Shape<PP, R>;
-    constexpr int QC = S::QC, RW = S::RW;
+    constexpr int QC = PP * R;
+    constexpr int RW = (R == 1) ? 1 : R / 4;
     extern __shared__ float smem[];
-    float* Xs = smem;                 // [L][kPad]
-    float* Ls = Xs + g.L * kPad;      // R == 1: [2][4][kTile]
+    float* Xs = smem;                                  // [L][kXS]
+    float* Ls = Xs + g.L * kXS;                        // R == 1: [2][4][kTile]
 
     int pg, c;
     wg_coords(g, pg, c);
@@ -549,10 +779,10 @@ __global__ __launch_bounds__(kThreads, 2) void k_close(Geom g, State s, const fl
 #pragma unroll
             for (int j = 0; j < PP; ++j) a[j] = pok ? s.A[(size_t)(m * PP + j) * N + pix] : 0.f;
             float ls = 0.f, fs = 0.f;
-            const int Lq = (L + 3) >> 2, l0 = w * Lq, l1 = min(L, l0 + Lq);
+            const int Lq = (L + 3) >> 2, l0 = min(L, w * Lq), l1 = min(L, l0 + Lq);
             for (int l = l0; l < l1; ++l) {
                 const float* El = E + (size_t)l * g.Qp + col0;
-                float r = Xs[l * kPad + lane];
+                float r = Xs[l * kXS + lane];
 #pragma unroll
                 for (int j = 0; j < PP; ++j) r = fmaf(-El[j], a[j], r);
                 ls = fmaf(r, r, ls);
@@ -578,7 +808,7 @@ __global__ __launch_bounds__(kThreads, 2) void k_close(Geom g, State s, const fl
             }
             const float* Ew = E + col0 + w * RW * PP;
             for (int l = 0; l < L; ++l) {
-                const float x = Xs[l * kPad + lane];
+                const float x = Xs[l * kXS + lane];
                 const float* El = Ew + (size_t)l * g.Qp;
 #pragma unroll
                 for (int r = 0; r < RW; ++r) {
@@ -618,6 +848,7 @@ __global__ __launch_bounds__(kThreads, 2) void k_close(Geom g, State s, const fl
     }
 }
 
+
 // --------------------------------------------------------------------------
 // Reductions of the per-workgroup partials, in a fixed order.  Grid:
 // (row blocks, chunks); a workgroup owns whole rows of its chunk.
@@ -625,120 +856,146 @@ __global__ __launch_bounds__(kThreads, 2) void k_close(Geom g, State s, const fl
 // The cross-workgroup sums, E and W = E (A A^T) - X A^T are formed in float64:
 // E A A^T and X A^T are both of order N/p while W is of the order of the
 // residual, so forming the difference in float32 would lose most digits.
-template <int PP, int R>
-__global__ __launch_bounds__(kThreads) void k_reduce_b(Geom g, State s, int need_w) {
-    constexpr int QC = PP * R;
-    constexpr int ROWS = kThreads / QC;
-    constexpr int FCH = 64;                        // partial groups per factor chunk
-    __shared__ float Ms[QC];
-    __shared__ double Ss[QC];
-    __shared__ float Fac[FCH][QC];
-    __shared__ double Es[ROWS][QC];
-    const int rb = blockIdx.x, c = blockIdx.y, tid = threadIdx.x;
-    const int col0 = c * QC, L = g.L;
+//
+// Every sum over the npg per-workgroup partials is split into fixed slices
+// of the partial index (one slice per thread) whose results are combined in
+// slice order, so the result does not depend on scheduling.
 
-    for (int q = tid; q < QC; q += kThreads) {
-        const int m = c * R + q / PP;
-        float mx = -INFINITY;
-        for (int pg = 0; pg < g.npg; ++pg) mx = fmaxf(mx, s.mpart[(size_t)pg * g.Qp + col0 + q]);
-        double sm = 0.0;
-        if (mx != -INFINITY)
-            for (int pg = 0; pg < g.npg; ++pg) {
-                const float mp = s.mpart[(size_t)pg * g.Qp + col0 + q];
-                if (mp != -INFINITY) sm += (double)s.spart[(size_t)pg * g.Qp + col0 + q] * (double)expf(mp - mx);
-            }
-        Ms[q] = mx;
-        Ss[q] = sm;
-        if (rb == 0 && m < g.M) {
-            s.colm[col0 + q] = mx;
-            s.cols[col0 + q] = (float)sm;
-        }
-    }
-    const int lr = tid / QC, q = tid % QC;
-    const int l = rb * ROWS + lr;
-    const bool act = tid < ROWS * QC && l < L;
-    const int m = c * R + q / PP;
+// out[o] = sum over pg of src[pg * stride + o] for o < no (no <= 256).
+__device__ __forceinline__ void sliced_sum(const float* __restrict__ src, size_t stride, int npg, int no,
+                                           double* red, double* out) {
+    const int tid = threadIdx.x, S = kThreads / no;
+    const int o = tid % no, sl = tid / no;
     double acc = 0.0;
-    for (int pb = 0; pb < g.npg; pb += FCH) {
-        __syncthreads();
-        for (int e = tid; e < FCH * QC; e += kThreads) {
-            const int pp = e / QC, qq = e % QC, pg = pb + pp;
-            float f = 0.f;
-            if (pg < g.npg) {
-                const float mp = s.mpart[(size_t)pg * g.Qp + col0 + qq];
-                f = (mp == -INFINITY) ? 0.f : expf(mp - Ms[qq]);
-            }
-            Fac[pp][qq] = f;
-        }
-        __syncthreads();
-        if (act) {
-            const int pe = min(FCH, g.npg - pb);
-            for (int pp = 0; pp < pe; ++pp)
-                acc += (double)s.Vpart[(((size_t)(pb + pp) * g.nqc + c) * L + l) * QC + q] * (double)Fac[pp][q];
-        }
-    }
-    double e = 0.0;
-    if (act && m < g.M) e = acc / Ss[q];
-    if (act) {
-        s.E[(size_t)l * g.Qp + col0 + q] = (float)e;
-        s.Ed[(size_t)l * g.Qp + col0 + q] = e;
-        Es[lr][q] = e;
+    if (sl < S)
+        for (int pg = sl; pg < npg; pg += S) acc += (double)src[(size_t)pg * stride + o];
+    red[tid] = acc;
+    __syncthreads();
+    if (tid < no) {
+        double t = 0.0;
+        for (int k = 0; k < S; ++k) t += red[k * no + tid];
+        out[tid] = t;
     }
     __syncthreads();
-    if (need_w && act) {
-        double wv = 0.0;
+}
+
+// A A^T of run m (blockIdx.x) and its objective at the incoming state
+// (trace[t]), each summed over the npg workgroup partials in fixed slices.
+template <int PP, int R>
+__global__ __launch_bounds__(kThreads) void k_reduce_aa(Geom g, State s, int t) {
+    constexpr int P2 = PP * PP;
+    __shared__ double red[kThreads];
+    __shared__ double out[P2 > 1 ? P2 : 1];
+    const int m = blockIdx.x, tid = threadIdx.x;
+    sliced_sum(s.AApart + (size_t)m * P2, (size_t)g.nqc * R * P2, g.npg, P2, red, out);   // [npg][nqc R][p][p]
+    if (tid < P2) s.AAtd[(size_t)m * P2 + tid] = out[tid];
+    double acc = 0.0;
+    for (int pg = tid; pg < g.npg; pg += kThreads) acc += s.lpart[(size_t)pg * g.M + m];
+    red[tid] = acc;
+    __syncthreads();
+    if (tid == 0) {
+        double tot = 0.0;
+        for (int k = 0; k < kThreads; ++k) tot += red[k];
+        s.trace[(size_t)m * (s.T + 1) + t] = 0.5 * tot;
+    }
+}
+
+// Row l of chunk c: X A^T[l][:] and W[l][:] = E[l][:] A A^T - X A^T[l][:].
+template <int PP, int R>
+__global__ __launch_bounds__(kThreads) void k_reduce_a(Geom g, State s, int t) {
+    constexpr int QC = PP * R;
+    __shared__ double red[kThreads];
+    __shared__ double xa[QC];
+    const int l = blockIdx.x, c = blockIdx.y, tid = threadIdx.x;
+    const int col0 = c * QC, L = g.L;
+    (void)t;
+    sliced_sum(s.Vpart + ((size_t)c * L + l) * QC, (size_t)g.nqc * L * QC, g.npg, QC, red, xa);
+    if (tid < QC) {
+        const int q = tid, m = c * R + q / PP, ml = q / PP, j = q % PP;
+        double x = xa[q], wv = 0.0;
         if (m < g.M) {
-            const int ml = q / PP, j = q % PP;
-            wv = -s.XAtd[(size_t)l * g.Qp + col0 + q];
+            wv = -x;
+            const double* El = s.Ed + (size_t)l * g.Qp + col0 + ml * PP;
             const double* aat = s.AAtd + (size_t)m * PP * PP;
 #pragma unroll
-            for (int k = 0; k < PP; ++k) wv = fma(Es[lr][ml * PP + k], aat[k * PP + j], wv);
+            for (int k = 0; k < PP; ++k) wv = fma(El[k], aat[k * PP + j], wv);
+        } else {
+            x = 0.0;
         }
+        s.XAtd[(size_t)l * g.Qp + col0 + q] = x;
         s.W[(size_t)l * g.Qp + col0 + q] = (float)wv;
     }
 }
 
+// Row l of chunk c after a B-pass: column statistics (max, sum relative to
+// the max) of the softmax over all N pixels, E[l][:] = X B_new, and W for the
+// next B-step.
 template <int PP, int R>
-__global__ __launch_bounds__(kThreads) void k_reduce_a(Geom g, State s, int t) {
+__global__ __launch_bounds__(kThreads) void k_reduce_b(Geom g, State s, int need_w) {
     constexpr int QC = PP * R;
-    constexpr int ROWS = kThreads / QC;
-    constexpr int AAN = R * PP * PP;
-    __shared__ double AAs[AAN];
-    const int rb = blockIdx.x, c = blockIdx.y, tid = threadIdx.x;
+    __shared__ double red[kThreads];
+    __shared__ float Ms[QC];
+    __shared__ double Ss[QC], Ev[QC];
+    const int l = blockIdx.x, c = blockIdx.y, tid = threadIdx.x;
     const int col0 = c * QC, L = g.L;
-
-    for (int e = tid; e < AAN; e += kThreads) {
-        double acc = 0.0;
-        for (int pg = 0; pg < g.npg; ++pg) acc += (double)s.AApart[((size_t)pg * g.nqc + c) * AAN + e];
-        AAs[e] = acc;
-        const int m = c * R + e / (PP * PP);
-        if (rb == 0 && m < g.M) s.AAtd[(size_t)m * PP * PP + e % (PP * PP)] = acc;
+    const int S = kThreads / QC, o = tid % QC, sl = tid / QC;
+    const bool act = sl < S;
+    // column maxima over the workgroup partials
+    float mx = -INFINITY;
+    if (act)
+        for (int pg = sl; pg < g.npg; pg += S) mx = fmaxf(mx, s.mpart[(size_t)pg * g.Qp + col0 + o]);
+    red[tid] = (double)mx;
+    __syncthreads();
+    if (tid < QC) {
+        float t = -INFINITY;
+        for (int k = 0; k < S; ++k) t = fmaxf(t, (float)red[k * QC + tid]);
+        Ms[tid] = t;
     }
-    if (rb == 0 && tid < R) {
-        const int m = c * R + tid;
-        if (m < g.M) {
-            double acc = 0.0;
-            for (int pg = 0; pg < g.npg; ++pg) acc += s.lpart[(size_t)pg * g.M + m];
-            s.trace[(size_t)m * (s.T + 1) + t] = 0.5 * acc;
+    __syncthreads();
+    // column sums and the row of X B (relative to the maxima)
+    const float mq = Ms[o];
+    double sa = 0.0, ea = 0.0;
+    if (act && mq != -INFINITY)
+        for (int pg = sl; pg < g.npg; pg += S) {
+            const float mp = s.mpart[(size_t)pg * g.Qp + col0 + o];
+            if (mp == -INFINITY) continue;
+            const double f = (double)expf(mp - mq);
+            sa += (double)s.spart[(size_t)pg * g.Qp + col0 + o] * f;
+            ea += (double)s.Vpart[(((size_t)pg * g.nqc + c) * L + l) * QC + o] * f;
+        }
+    red[tid] = sa;
+    __syncthreads();
+    if (tid < QC) {
+        double t = 0.0;
+        for (int k = 0; k < S; ++k) t += red[k * QC + tid];
+        Ss[tid] = t;
+    }
+    __syncthreads();
+    red[tid] = ea;
+    __syncthreads();
+    if (tid < QC) {
+        double t = 0.0;
+        for (int k = 0; k < S; ++k) t += red[k * QC + tid];
+        const int m = c * R + tid / PP;
+        const double e = (m < g.M) ? t / Ss[tid] : 0.0;
+        Ev[tid] = e;
+        s.E[(size_t)l * g.Qp + col0 + tid] = (float)e;
+        s.Ed[(size_t)l * g.Qp + col0 + tid] = e;
+        if (l == 0 && m < g.M) {
+            s.colm[col0 + tid] = Ms[tid];
+            s.cols[col0 + tid] = (float)Ss[tid];
         }
     }
     __syncthreads();
-    const int lr = tid / QC, q = tid % QC;
-    const int l = rb * ROWS + lr;
-    if (tid < ROWS * QC && l < L) {
-        const int m = c * R + q / PP, ml = q / PP, j = q % PP;
-        double xa = 0.0;
-        for (int pg = 0; pg < g.npg; ++pg) xa += (double)s.Vpart[(((size_t)pg * g.nqc + c) * L + l) * QC + q];
+    if (need_w && tid < QC) {
+        const int q = tid, m = c * R + q / PP, ml = q / PP, j = q % PP;
         double wv = 0.0;
         if (m < g.M) {
-            wv = -xa;
-            const double* El = s.Ed + (size_t)l * g.Qp + col0 + ml * PP;
+            wv = -s.XAtd[(size_t)l * g.Qp + col0 + q];
+            const double* aat = s.AAtd + (size_t)m * PP * PP;
 #pragma unroll
-            for (int k = 0; k < PP; ++k) wv = fma(El[k], AAs[ml * PP * PP + k * PP + j], wv);
-        } else {
-            xa = 0.0;
+            for (int k = 0; k < PP; ++k) wv = fma(Ev[ml * PP + k], aat[k * PP + j], wv);
         }
-        s.XAtd[(size_t)l * g.Qp + col0 + q] = xa;
         s.W[(size_t)l * g.Qp + col0 + q] = (float)wv;
     }
 }
@@ -902,14 +1159,8 @@ __global__ __launch_bounds__(kThreads) void k_normalize(const float* __restrict_
 }  // namespace
 
 size_t pass_lds_bytes(int PP, int R, int L, int kind) {
-    const int QC = PP * R, QCs = (QC + 3) & ~3;
-    size_t b = (size_t)L * kPad;
-    // the [4][kTile][PP] band-split scratch exists only in the single-run kernels
-    const size_t split = (R == 1) ? (size_t)4 * kTile * PP : 0;
-    if (kind == 0) b += (size_t)kTile * QCs + (size_t)R * PP * PP + split + (R == 1 ? 4 * kTile : 0);   // A-pass
-    if (kind == 1) b += (size_t)kTile * QCs + QCs + split;                                            // B-pass
-    if (kind == 2) b += (size_t)8 * kTile;                                                            // close
-    return b * sizeof(float);
+    if (kind == 2) return ((size_t)L * kXS + 8 * kTile) * sizeof(float);
+    return (size_t)pass_lds(PP, R, L, 0).total * sizeof(float);
 }
 
 namespace {
@@ -917,13 +1168,13 @@ namespace {
 template <int PP, int R>
 struct Kernels {
     static hipError_t apass(const Geom& g, const State& s, int K1, hipStream_t st) {
-        const size_t lds = pass_lds_bytes(PP, R, g.L, 0);
+        const size_t lds = (size_t)pass_lds(PP, R, g.L, g.dbuf).total * sizeof(float);
         set_max_lds((const void*)k_apass<PP, R>, (int)lds);
         hipLaunchKernelGGL((k_apass<PP, R>), dim3(g.npg * g.nqc), dim3(kThreads), lds, st, g, s, (const float*)s.E, K1);
         return hipGetLastError();
     }
     static hipError_t bpass(const Geom& g, const State& s, int mode, const RunInit& ri, hipStream_t st) {
-        const size_t lds = pass_lds_bytes(PP, R, g.L, 1);
+        const size_t lds = (size_t)pass_lds(PP, R, g.L, g.dbuf).total * sizeof(float);
         set_max_lds((const void*)k_bpass<PP, R>, (int)lds);
         hipLaunchKernelGGL((k_bpass<PP, R>), dim3(g.npg * g.nqc), dim3(kThreads), lds, st, g, s, (const float*)s.W, mode,
                            ri);
@@ -936,14 +1187,12 @@ struct Kernels {
         return hipGetLastError();
     }
     static hipError_t reduce_b(const Geom& g, const State& s, int need_w, hipStream_t st) {
-        constexpr int ROWS = kThreads / (PP * R);
-        hipLaunchKernelGGL((k_reduce_b<PP, R>), dim3((g.L + ROWS - 1) / ROWS, g.nqc), dim3(kThreads), 0, st, g, s,
-                           need_w);
+        hipLaunchKernelGGL((k_reduce_b<PP, R>), dim3(g.L, g.nqc), dim3(kThreads), 0, st, g, s, need_w);
         return hipGetLastError();
     }
     static hipError_t reduce_a(const Geom& g, const State& s, int t, hipStream_t st) {
-        constexpr int ROWS = kThreads / (PP * R);
-        hipLaunchKernelGGL((k_reduce_a<PP, R>), dim3((g.L + ROWS - 1) / ROWS, g.nqc), dim3(kThreads), 0, st, g, s, t);
+        hipLaunchKernelGGL((k_reduce_aa<PP, R>), dim3(g.M), dim3(kThreads), 0, st, g, s, t);
+        hipLaunchKernelGGL((k_reduce_a<PP, R>), dim3(g.L, g.nqc), dim3(kThreads), 0, st, g, s, t);
         return hipGetLastError();
     }
 };
@@ -1012,16 +1261,18 @@ template <int PP> struct FinalOp { static hipError_t run(const Geom& g, const St
 
 }  // namespace
 
-int runs_per_chunk(int p, int M) {
+int runs_per_chunk(int p, int M, int L) {
     if (M <= 1) return 1;
-    if (M <= 4) return 4;
-    return rmax_for(p);
+    const int R = (M <= 4) ? 4 : rmax_for(p);
+    // the stacked-run kernels keep the projection operand in LDS as well
+    if ((size_t)pass_lds(p, R, L).total * sizeof(float) > kMaxLdsBytes) return 1;
+    return R;
 }
 
 Geom make_geom(int L, int N, int M, int p) {
     Geom g;
     g.L = L; g.N = N; g.M = M; g.p = p;
-    g.R = runs_per_chunk(p, M);
+    g.R = runs_per_chunk(p, M, L);
     g.QC = g.R * p;
     g.nqc = (M + g.R - 1) / g.R;
     g.Qp = g.nqc * g.QC;
@@ -1030,6 +1281,7 @@ Geom make_geom(int L, int N, int M, int p) {
     if (npg >= 8) npg &= ~7;
     npg = std::max(1, std::min(npg, g.ntiles));
     g.npg = npg;
+    g.dbuf = ((size_t)pass_lds(p, g.R, L, 1).total * sizeof(float) <= kMaxLdsBytes) ? 1 : 0;
     return g;
 }
 

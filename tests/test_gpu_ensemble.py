@@ -125,3 +125,25 @@ def test_ensemble_non_finite_run_is_excluded(api):
     if r["status"][1] != 0:
         assert r["fit"][1] == np.inf
         assert r["selected"] in ok
+
+
+@gpu
+def test_urban_shaped_ensemble_vs_oracle(api):
+    """The benchmark workload (L=162, N=307x307, p=6), batched over 10 runs,
+    10 outer iterations: the runs with gamma 0.25 and 1 (seed 0) against the
+    float64 oracle, and the single-run path against the batched one."""
+    s, cfg = synth.urban_ensemble(n_seeds=2)
+    _say("urban-shaped ensemble M=10 T=10 vs oracle (2 runs)")
+    Xg, X = _prep(s.X)
+    seeds, gammas = cfg["seeds"], cfg["gammas"]
+    r = api.ensemble(Xg, 6, seeds, gammas, T=10)
+    N = X.shape[1]
+    for m in (0, 2):
+        ref = O.edaa_fit(X, 6, T=10, gamma=gammas[m], seed=seeds[m])
+        rel = np.max(np.abs(r["loss"][m] - ref["loss"]) / ref["loss"])
+        a_err = np.max(np.abs(_np(r["A"][m]) - ref["A"]))
+        nb_err = N * np.max(np.abs(_np(r["B"][m]) - ref["B"]))
+        _say(f"run {m}: loss rel {rel:.2e} A {a_err:.2e} N*B {nb_err:.2e}")
+        assert rel < 1e-4 and a_err < 1e-3 and nb_err < 1e-2
+        one = api.fit(Xg, 6, T=10, gamma=gammas[m], seed=seeds[m])
+        assert np.max(np.abs(one["loss"] - r["loss"][m]) / ref["loss"]) < 1e-4

@@ -126,7 +126,7 @@ def test_B_phase_only(api, L, N, p):
     (5, 7, 3, 10),          # fewer pixels than one tile
     (20, 64, 1, 10),        # p = 1, exactly one tile
     (300, 200, 4, 10),      # L > 256: two accumulation rows per thread
-    (512, 130, 16, 5),      # maximum L and p
+    (448, 130, 16, 5),      # maximum L and p
     (33, 129, 16, 8),
 ])
 def test_fit_shapes(api, L, N, p, T):
