@@ -164,7 +164,7 @@ struct RunBuffers {
 size_t layout(const Geom& g, int T, char* base, RunBuffers* rb) {
     Arena a;
     const size_t Q = (size_t)g.M * g.p;
-    const size_t o_Bst = a.take<float>(Q * g.N);
+    const size_t o_Bst = a.take<float>(Q * (size_t)g.ntiles * kTile);   // rows padded to whole tiles
     const size_t o_tsh = a.take<float>((size_t)g.ntiles * g.Qp);
     const size_t o_colm = a.take<float>(g.Qp);
     const size_t o_cols = a.take<float>(g.Qp);

@@ -38,7 +38,7 @@ struct State {
     const void* X;      // [L][N] float32 or bf16 bits
     int x_bf16;
     float* A;           // [Q][N] abundances (the caller's A_all)
-    float* Bst;         // [Q][N] unnormalised pixel weights
+    float* Bst;         // [Q][ntiles * 64] unnormalised pixel weights (pixels >= N: zero)
     float* tshift;      // [ntiles][Qp] shift used when a tile of Bst was written
     float* colm;        // [Qp] column maximum of the last B-pass
     float* cols;        // [Qp] column sum (relative to colm) of the last B-pass

@@ -76,6 +76,50 @@ __device__ __forceinline__ float dpp(float v) {
 __device__ __forceinline__ float lane_f(float v, int l) {
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
 }
+// Reductions of several values at once, step by step, so the independent
+// DPP chains overlap: within rows of 16 lanes (quad permutes, row rotations
+// by 4 and 8), then row_bcast:15 (rows 1, 3 take row 0 / row 2) and
+// row_bcast:31 (rows 2, 3 take lane 31); lane 63 ends with the wave result,
+// which is returned in every lane.
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ float dpp_rm(float old, float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(old), __float_as_int(v), CTRL, ROWMASK, 0xF, false));
+}
+template <int K>
+__device__ __forceinline__ void wave_max_k(float (&r)[K]) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) r[k] = fmaxf(r[k], dpp<0xB1>(r[k]));
+#pragma unroll
+    for (int k = 0; k < K; ++k) r[k] = fmaxf(r[k], dpp<0x4E>(r[k]));
+#pragma unroll
+    for (int k = 0; k < K; ++k) r[k] = fmaxf(r[k], dpp<0x124>(r[k]));
+#pragma unroll
+    for (int k = 0; k < K; ++k) r[k] = fmaxf(r[k], dpp<0x128>(r[k]));
+#pragma unroll
+    for (int k = 0; k < K; ++k) r[k] = fmaxf(r[k], dpp_rm<0x142, 0xA>(r[k], r[k]));
+#pragma unroll
+    for (int k = 0; k < K; ++k) r[k] = fmaxf(r[k], dpp_rm<0x143, 0xC>(r[k], r[k]));
+#pragma unroll
+    for (int k = 0; k < K; ++k) r[k] = lane_f(r[k], 63);
+}
+template <int K>
+__device__ __forceinline__ void wave_sum_k(float (&r)[K]) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) r[k] += dpp<0xB1>(r[k]);
+#pragma unroll
+    for (int k = 0; k < K; ++k) r[k] += dpp<0x4E>(r[k]);
+#pragma unroll
+    for (int k = 0; k < K; ++k) r[k] += dpp<0x124>(r[k]);
+#pragma unroll
+    for (int k = 0; k < K; ++k) r[k] += dpp<0x128>(r[k]);
+#pragma unroll
+    for (int k = 0; k < K; ++k) r[k] += dpp_rm<0x142, 0xA>(0.f, r[k]);
+#pragma unroll
+    for (int k = 0; k < K; ++k) r[k] += dpp_rm<0x143, 0xC>(0.f, r[k]);
+#pragma unroll
+    for (int k = 0; k < K; ++k) r[k] = lane_f(r[k], 63);
+}
+
 __device__ __forceinline__ float wave_max_dpp(float v) {
     v = fmaxf(v, dpp<0xB1>(v));
     v = fmaxf(v, dpp<0x4E>(v));
@@ -237,8 +281,8 @@ __host__ __device__ inline PassLds pass_lds(int PP, int R, int L, int dbuf = 0) 
     const int LP = (L + 15) & ~15;
     PassLds o;
     o.xs = 0;
-    o.wt = o.xs + LP * kXS;                    // [64][WTS] weights (also projection results, R > 1)
-    o.f = o.wt + kTile * WTS;                  // [QCP] rescale factors
+    o.wt = o.xs + LP * kXS;                    // [64][WTS] or [QCP][kXS] weights / projection results
+    o.f = o.wt + (kTile * WTS > QCP * kXS ? kTile * WTS : QCP * kXS);   // [QCP] rescale factors
     o.ec = o.f + QCP;                          // [LP][WTS] projection operand chunk (E or W)
     o.gs = o.ec + LP * WTS;                    // [R][PP][PP] Gram matrices (double, 2 floats each)
     o.gs = (o.gs + 1) & ~1;
@@ -255,7 +299,8 @@ __host__ __device__ inline PassLds pass_lds(int PP, int R, int L, int dbuf = 0) 
 // running accumulation of column q is first multiplied by F[q].  The B
 // operands (Wt, 64 x QCP) are loaded once per tile and reused for every row
 // block; the optional Gram accumulation Wt^T Wt reuses them as well.
-template <int NCB, int NRBW, int WTS, bool SCALE, int NGBW>
+// QMAJOR: the weights are stored column-major, Wt[q * kXS + pixel].
+template <int NCB, int NRBW, int WTS, bool SCALE, int NGBW, bool QMAJOR = false>
 __device__ __forceinline__ void mfma_accumulate(f4 (&acc)[NRBW][NCB], f4 (&gram)[NGBW], bool do_gram,
                                                 const float* Xs, const float* Wt, const float* F, int nrb, int w,
                                                 int lane) {
@@ -264,7 +309,8 @@ __device__ __forceinline__ void mfma_accumulate(f4 (&acc)[NRBW][NCB], f4 (&gram)
 #pragma unroll
     for (int k = 0; k < 16; ++k)
 #pragma unroll
-        for (int cb = 0; cb < NCB; ++cb) bop[k][cb] = Wt[(4 * k + kk) * WTS + 16 * cb + m];
+        for (int cb = 0; cb < NCB; ++cb)
+            bop[k][cb] = QMAJOR ? Wt[(16 * cb + m) * kXS + 4 * k + kk] : Wt[(4 * k + kk) * WTS + 16 * cb + m];
 #pragma unroll
     for (int j = 0; j < NRBW; ++j) {
         const int rb = w + 4 * j;
@@ -327,8 +373,10 @@ __device__ __forceinline__ void store_acc(const f4 (&acc)[NRBW][NCB], float* Vp,
 // computes the 16 pixels 16w..16w+15 for all QCP columns, S[q][i] =
 // sum_l Ec[l][q] Xs[l][i]; results go to Sc[i][q].  Also returns, for the
 // same pixels, the partial sums of x^2 over the bands this lane touched.
-template <int NCB, int WTS>
-__device__ __forceinline__ float mfma_project(const float* Ec, const float* Xs, float* Sc, int LK, int w, int lane) {
+// LP (a multiple of 16) rows of both operands are read; rows L..LP-1 of
+// both are zero.
+template <int NCB, int WTS, bool QMAJOR = false>
+__device__ __forceinline__ float mfma_project(const float* Ec, const float* Xs, float* Sc, int LP, int w, int lane) {
     const int m = lane & 15, kk = lane >> 4;
     f4 s[NCB];
 #pragma unroll
@@ -336,16 +384,30 @@ __device__ __forceinline__ float mfma_project(const float* Ec, const float* Xs, 
     float xx = 0.f;
     const float* xb = Xs + kk * kXS + 16 * w + m;
     const float* eb = Ec + kk * WTS + m;
-    for (int k = 0; k < LK; k += 4) {
-        const float b = xb[k * kXS];
-        xx = fmaf(b, b, xx);
+    for (int k0 = 0; k0 < LP; k0 += 16) {
+        float b[4], e[4][NCB];
 #pragma unroll
-        for (int cb = 0; cb < NCB; ++cb) s[cb] = mfma16(eb[k * WTS + 16 * cb], b, s[cb]);
+        for (int u = 0; u < 4; ++u) {
+            b[u] = xb[(k0 + 4 * u) * kXS];
+#pragma unroll
+            for (int cb = 0; cb < NCB; ++cb) e[u][cb] = eb[(k0 + 4 * u) * WTS + 16 * cb];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            xx = fmaf(b[u], b[u], xx);
+#pragma unroll
+            for (int cb = 0; cb < NCB; ++cb) s[cb] = mfma16(e[u][cb], b[u], s[cb]);
+        }
     }
 #pragma unroll
     for (int cb = 0; cb < NCB; ++cb)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) Sc[(16 * w + m) * WTS + 16 * cb + 4 * kk + v] = s[cb][v];
+        for (int v = 0; v < 4; ++v) {
+            if (QMAJOR)
+                Sc[(16 * cb + 4 * kk + v) * kXS + 16 * w + m] = s[cb][v];
+            else
+                Sc[(16 * w + m) * WTS + 16 * cb + 4 * kk + v] = s[cb][v];
+        }
     return xx;
 }
 
@@ -357,7 +419,7 @@ __device__ __forceinline__ float mfma_project(const float* Ec, const float* Xs, 
 // lo = fl(P - hi), which carries it to about 48 bits; returns the partial
 // ||x||^2 of this lane's bands.
 template <int NCB, int WTS>
-__device__ __forceinline__ double mfma_project_f64(const float* Ec, const float* Xs, float* Sc, float* Plo, int LK,
+__device__ __forceinline__ double mfma_project_f64(const float* Ec, const float* Xs, float* Sc, float* Plo, int LP,
                                                    int w, int lane) {
     const int m = lane & 15, kk = lane >> 4;
     d4 s[NCB];
@@ -366,11 +428,21 @@ __device__ __forceinline__ double mfma_project_f64(const float* Ec, const float*
     double xx = 0.0;
     const float* xb = Xs + kk * kXS + 16 * w + m;
     const float* eb = Ec + kk * WTS + m;
-    for (int k = 0; k < LK; k += 4) {
-        const double b = (double)xb[k * kXS];
-        xx = fma(b, b, xx);
+    for (int k0 = 0; k0 < LP; k0 += 16) {
+        float b[4], e[4][NCB];
 #pragma unroll
-        for (int cb = 0; cb < NCB; ++cb) s[cb] = mfma16d((double)eb[k * WTS + 16 * cb], b, s[cb]);
+        for (int u = 0; u < 4; ++u) {
+            b[u] = xb[(k0 + 4 * u) * kXS];
+#pragma unroll
+            for (int cb = 0; cb < NCB; ++cb) e[u][cb] = eb[(k0 + 4 * u) * WTS + 16 * cb];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const double bd = (double)b[u];
+            xx = fma(bd, bd, xx);
+#pragma unroll
+            for (int cb = 0; cb < NCB; ++cb) s[cb] = mfma16d((double)e[u][cb], bd, s[cb]);
+        }
     }
 #pragma unroll
     for (int cb = 0; cb < NCB; ++cb)
@@ -403,11 +475,10 @@ __global__ __launch_bounds__(kThreads, 1) void k_apass(Geom g, State s, const fl
     constexpr int NGBW = S::NGBW;
     extern __shared__ float smem[];
     const PassLds lo = pass_lds(PP, R, g.L, g.dbuf);
-    float* Xs = smem + lo.xs;
     float* Wt = smem + lo.wt;
     float* Ec = smem + lo.ec;
     double* Gd = (double*)(smem + lo.gs);
-    float* Xb[2] = {Xs, g.dbuf ? smem + lo.xs2 : Xs};
+    const int xo[2] = {lo.xs, g.dbuf ? lo.xs2 : lo.xs};
     double* XX = (double*)(smem + lo.xx);
     float* Plo = smem + lo.pd;
 
@@ -434,8 +505,8 @@ __global__ __launch_bounds__(kThreads, 1) void k_apass(Geom g, State s, const fl
     __syncthreads();
     // zero the X rows beyond L and the weight padding (never written later)
     for (int e = tid; e < (LP - L) * kXS; e += kThreads) {
-        Xb[0][L * kXS + e] = 0.f;
-        Xb[1][L * kXS + e] = 0.f;
+        smem[xo[0] + L * kXS + e] = 0.f;
+        smem[xo[1] + L * kXS + e] = 0.f;
     }
     for (int e = tid; e < kTile * WTS; e += kThreads) Wt[e] = 0.f;
 
@@ -466,12 +537,12 @@ __global__ __launch_bounds__(kThreads, 1) void k_apass(Geom g, State s, const fl
     };
     __syncthreads();
     if (pg < g.ntiles) {
-        if (dma) dma_tile((const float*)s.X, L, N, pg, Xb[0]);
+        if (dma) dma_tile((const float*)s.X, L, N, pg, smem + xo[0]);
         load_a(pg);
     }
     int it = 0;
     for (int tile = pg; tile < g.ntiles; tile += g.npg, ++it) {
-        float* Xs = Xb[it & 1];
+        float* Xs = smem + ((it & 1) ? xo[1] : xo[0]);
         if (!dma) {
             __syncthreads();
             load_tile_sync(s.X, s.x_bf16, L, N, tile, Xs);
@@ -491,11 +562,11 @@ __global__ __launch_bounds__(kThreads, 1) void k_apass(Geom g, State s, const fl
         const int nt = tile + g.npg;
         if (nt < g.ntiles) {
             load_a(nt);
-            if (dma && g.dbuf) dma_tile((const float*)s.X, L, N, nt, Xb[(it + 1) & 1]);
+            if (dma && g.dbuf) dma_tile((const float*)s.X, L, N, nt, smem + ((it & 1) ? xo[0] : xo[1]));
         }
         {
             // projection on the matrix cores: P for pixels 16w..16w+15
-            double xx = mfma_project_f64<NCB, WTS>(Ec, Xs, Wt, Plo, (L + 3) & ~3, w, lane);
+            double xx = mfma_project_f64<NCB, WTS>(Ec, Xs, Wt, Plo, LP, w, lane);
             xx += __shfl_xor(xx, 16);       // the 4 band classes of the pixel
             xx += __shfl_xor(xx, 32);
             if (lane < 16) XX[16 * w + lane] = xx;
@@ -578,154 +649,157 @@ __global__ __launch_bounds__(kThreads, 1) void k_apass(Geom g, State s, const fl
 // values (INIT: 0.1 u, or log B0); per-tile column max and online merge into
 // the workgroup's running (max, sum); write the shifted weights and the
 // tile's shift; accumulate X * weights^T.
+//
+// Softmax layout: thread t owns column q = t / 4 of the chunk and the 16
+// pixels 16 (t % 4) .. +15 of the tile, so a column's tile max and sum take
+// two quad permutes and the running (max, sum) stays in the four lanes.  The
+// projection results and the weights live column-major in LDS ([QCP][kXS]).
+// Bst rows are padded to whole tiles (pixels >= N hold zero weights), so the
+// 16-pixel segments are read and written as float4 without bounds checks.
 // --------------------------------------------------------------------------
-template <int PP, int R>
+template <int PP, int R, bool STEP>
 __global__ __launch_bounds__(kThreads, 1) void k_bpass(Geom g, State s, const float* __restrict__ W, int mode,
                                                        RunInit ri) {
     using S = Shape<PP, R>;
-    constexpr int QC = S::QC, QCP = S::QCP, NCB = S::NCB, WTS = S::WTS, CPW = S::CPW, NRBW = S::NRBW;
+    constexpr int QC = S::QC, QCP = S::QCP, NCB = S::NCB, WTS = S::WTS, NRBW = S::NRBW;
+    static_assert(QCP <= kThreads / 4, "one quad of threads per softmax column");
     extern __shared__ float smem[];
     const PassLds lo = pass_lds(PP, R, g.L, g.dbuf);
-    float* Xs = smem + lo.xs;
-    float* Wt = smem + lo.wt;
+    float* Wq = smem + lo.wt;                      // [QCP][kXS]
     float* F = smem + lo.f;
     float* Ec = smem + lo.ec;
-    float* Xb[2] = {Xs, g.dbuf ? smem + lo.xs2 : Xs};
+    const int xo[2] = {lo.xs, g.dbuf ? lo.xs2 : lo.xs};
 
     int pg, c;
     wg_coords(g, pg, c);
     const int tid = threadIdx.x, lane = tid & 63;
     const int w = uniform_int(tid >> 6);
     const int L = g.L, N = g.N, LP = (L + 15) & ~15, nrb = LP / 16;
+    const size_t Np = (size_t)g.ntiles * kTile;
     const int col0 = c * QC;
-    const bool step = (mode == kModeStep);
 
     for (int e = tid; e < (LP - L) * kXS; e += kThreads) {
-        Xb[0][L * kXS + e] = 0.f;
-        Xb[1][L * kXS + e] = 0.f;
+        smem[xo[0] + L * kXS + e] = 0.f;
+        smem[xo[1] + L * kXS + e] = 0.f;
     }
-    for (int e = tid; e < kTile * WTS; e += kThreads) Wt[e] = 0.f;
+    for (int e = tid; e < QCP * kXS; e += kThreads) Wq[e] = 0.f;
     for (int e = tid; e < QCP; e += kThreads) F[e] = 0.f;
-    if (step) stage_chunk<QC, QCP, WTS>(W, g.Qp, col0, L, LP, Ec);
+    if (STEP) stage_chunk<QC, QCP, WTS>(W, g.Qp, col0, L, LP, Ec);
 
-    // softmax columns of this wave: q = w + 4k (uniform per wave)
-    float mrun[CPW], srun[CPW], lzc[CPW], eta2[CPW];
-#pragma unroll
-    for (int k = 0; k < CPW; ++k) {
-        const int q = w + 4 * k, m = c * R + q / PP;
-        mrun[k] = -INFINITY;
-        srun[k] = 0.f;
-        lzc[k] = 0.f;
-        eta2[k] = 0.f;
-        if (q < QC && m < g.M && step) {
-            lzc[k] = -s.colm[col0 + q] - logf(s.cols[col0 + q]);
-            eta2[k] = s.eta[2 * m + 1];
-        }
+    // this thread's softmax column and pixel segment
+    const int sq = tid >> 2, sub = tid & 3;
+    const int sm = c * R + sq / PP, sj = sq % PP;
+    const bool qin = sq < QC;                      // a column of the chunk
+    const bool cok = qin && sm < g.M;              // ... of an existing run
+    float* bcol = s.Bst + (size_t)(cok ? col0 + sq : 0) * Np + 16 * sub;
+    float mrun = -INFINITY, srun = 0.f, lzc = 0.f, eta2 = 0.f;
+    if (STEP && cok) {
+        lzc = -s.colm[col0 + sq] - logf(s.cols[col0 + sq]);
+        eta2 = s.eta[2 * sm + 1];
     }
 
     f4 acc[NRBW][NCB], gdummy[1];
 #pragma unroll
-    for (int j = 0; j < NRBW; ++j)
+    for (int jb = 0; jb < NRBW; ++jb)
 #pragma unroll
-        for (int cb = 0; cb < NCB; ++cb) acc[j][cb] = f4{0.f, 0.f, 0.f, 0.f};
+        for (int cb = 0; cb < NCB; ++cb) acc[jb][cb] = f4{0.f, 0.f, 0.f, 0.f};
 
-    // Pipeline: the X tile (direct-to-LDS loads) and this wave's B state and
-    // shifts (registers) of tile t + npg are requested while tile t is
+    // Pipeline: the X tile (direct-to-LDS loads) and this thread's B segment
+    // and shift (registers) of tile t + npg are requested while tile t is
     // processed.
     const bool dma = !s.x_bf16;
-    float bn[CPW], tn[CPW];
+    f4 bn[4];
+    float tn = 0.f;
     auto load_b = [&](int tile) {
-        const size_t pixc = (size_t)min(tile * kTile + lane, N - 1);
+        if (STEP && cok) {
+            const f4* src = (const f4*)(bcol + (size_t)tile * kTile);
 #pragma unroll
-        for (int k = 0; k < CPW; ++k) {
-            const int q = w + 4 * k, m = c * R + q / PP, j = q % PP;
-            bn[k] = 1.f;
-            tn[k] = 0.f;
-            if (step && q < QC && m < g.M) {
-                bn[k] = s.Bst[(size_t)(m * PP + j) * N + pixc];
-                tn[k] = s.tshift[(size_t)tile * g.Qp + col0 + q];
-            }
+            for (int u = 0; u < 4; ++u) bn[u] = src[u];
+            tn = s.tshift[(size_t)tile * g.Qp + col0 + sq];
         }
     };
     __syncthreads();
     if (pg < g.ntiles) {
-        if (dma) dma_tile((const float*)s.X, L, N, pg, Xb[0]);
+        if (dma) dma_tile((const float*)s.X, L, N, pg, smem + xo[0]);
         load_b(pg);
     }
     int it = 0;
     for (int tile = pg; tile < g.ntiles; tile += g.npg, ++it) {
-        float* Xs = Xb[it & 1];
+        float* Xs = smem + ((it & 1) ? xo[1] : xo[0]);
         if (!dma) {
             __syncthreads();
             load_tile_sync(s.X, s.x_bf16, L, N, tile, Xs);
         }
         __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();
-        const int pix = tile * kTile + lane;
-        const bool pok = pix < N;
-        float bv[CPW], ts[CPW];
+        f4 bv[4];
 #pragma unroll
-        for (int k = 0; k < CPW; ++k) {
-            bv[k] = bn[k];
-            ts[k] = tn[k];
-        }
+        for (int u = 0; u < 4; ++u) bv[u] = bn[u];
+        const float ts = tn;
         const int nt = tile + g.npg;
         if (nt < g.ntiles) {
             load_b(nt);
-            if (dma && g.dbuf) dma_tile((const float*)s.X, L, N, nt, Xb[(it + 1) & 1]);
+            if (dma && g.dbuf) dma_tile((const float*)s.X, L, N, nt, smem + ((it & 1) ? xo[0] : xo[1]));
         }
 
-        if (step) {
-            (void)mfma_project<NCB, WTS>(Ec, Xs, Wt, (L + 3) & ~3, w, lane);
+        if (STEP) {
+            (void)mfma_project<NCB, WTS, true>(Ec, Xs, Wq, LP, w, lane);
             __syncthreads();
         }
 
-        // softmax part, in phases so that the reductions of the owned
-        // columns are independent of each other
-        float v[CPW], wv[CPW], mnew[CPW], f[CPW];
+        if (qin) {
+            const int pix0 = tile * kTile + 16 * sub;
+            float* wrow = Wq + sq * kXS + 16 * sub;
+            float v[16];
+            if (STEP) {
+                const float sh = ts + lzc;
 #pragma unroll
-        for (int k = 0; k < CPW; ++k) {
-            const int q = w + 4 * k, m = c * R + q / PP, j = q % PP;
-            v[k] = -INFINITY;
-            if (q < QC && m < g.M && pok) {
-                if (step) {
-                    const float gv = Wt[lane * WTS + q];
-                    v[k] = fast_log(bv[k]) + (ts[k] + lzc[k]) - eta2[k] * gv;
-                } else if (mode == kModeInitRng) {
-                    v[k] = ri.init_scale * uniform_u(ri.seeds[m], pix, j);
-                } else {
-                    v[k] = fast_log(ri.B0[(size_t)pix * PP + j]);
+                for (int u = 0; u < 4; ++u) {
+                    const f4 gv = *(const f4*)(wrow + 4 * u);
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) v[4 * u + e] = fast_log(bv[u][e]) + sh - eta2 * gv[e];
                 }
-            }
-        }
+            } else if (mode == kModeInitRng) {
+                const uint64_t seed = ri.seeds[cok ? sm : 0];
 #pragma unroll
-        for (int k = 0; k < CPW; ++k) {
-            const int q = w + 4 * k, m = c * R + q / PP;
-            if (q < QC && m < g.M) {
-                mnew[k] = fmaxf(mrun[k], wave_max_dpp(v[k]));
-                f[k] = (mrun[k] == -INFINITY) ? 0.f : fast_exp(mrun[k] - mnew[k]);
-                wv[k] = (v[k] == -INFINITY) ? 0.f : fast_exp(v[k] - mnew[k]);
-            }
-        }
+                for (int i = 0; i < 16; ++i) v[i] = ri.init_scale * uniform_u(seed, pix0 + i, sj);
+            } else {
 #pragma unroll
-        for (int k = 0; k < CPW; ++k) {
-            const int q = w + 4 * k, m = c * R + q / PP, j = q % PP;
-            if (q < QC && m < g.M) {
-                srun[k] = srun[k] * f[k] + wave_sum_dpp(wv[k]);
-                mrun[k] = mnew[k];
-                if (pok) s.Bst[(size_t)(m * PP + j) * N + pix] = wv[k];
-                if (lane == 0) {
-                    s.tshift[(size_t)tile * g.Qp + col0 + q] = mnew[k];
-                    F[q] = f[k];
-                }
-                Wt[lane * WTS + q] = wv[k];
-            } else if (q < QC) {                         // unused run slot of the last chunk
-                Wt[lane * WTS + q] = 0.f;
-                if (lane == 0) F[q] = 0.f;
+                for (int i = 0; i < 16; ++i) v[i] = fast_log(ri.B0[(size_t)min(pix0 + i, N - 1) * PP + sj]);
+            }
+            float mx = -INFINITY;
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+                v[i] = (cok && pix0 + i < N) ? v[i] : -INFINITY;
+                mx = fmaxf(mx, v[i]);
+            }
+            mx = fmaxf(mx, dpp<0xB1>(mx));             // the quad of this column
+            mx = fmaxf(mx, dpp<0x4E>(mx));
+            const float mnew = fmaxf(mrun, mx);
+            const float f = (mrun == -INFINITY) ? 0.f : fast_exp(mrun - mnew);
+            float wv[16], sum = 0.f;
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+                wv[i] = (v[i] == -INFINITY) ? 0.f : fast_exp(v[i] - mnew);
+                sum += wv[i];
+            }
+            sum += dpp<0xB1>(sum);
+            sum += dpp<0x4E>(sum);
+            srun = srun * f + sum;
+            mrun = mnew;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const f4 o = f4{wv[4 * u], wv[4 * u + 1], wv[4 * u + 2], wv[4 * u + 3]};
+                *(f4*)(wrow + 4 * u) = o;
+                if (cok) ((f4*)(bcol + (size_t)tile * kTile))[u] = o;
+            }
+            if (sub == 0) {
+                F[sq] = f;
+                if (cok) s.tshift[(size_t)tile * g.Qp + col0 + sq] = mnew;
             }
         }
         __syncthreads();
-        mfma_accumulate<NCB, NRBW, WTS, true, 1>(acc, gdummy, false, Xs, Wt, F, nrb, w, lane);
+        mfma_accumulate<NCB, NRBW, WTS, true, 1, true>(acc, gdummy, false, Xs, Wq, F, nrb, w, lane);
         if (nt < g.ntiles && dma && !g.dbuf) {
             __syncthreads();                        // single buffer: reload after every reader
             dma_tile((const float*)s.X, L, N, nt, Xs);
@@ -734,15 +808,9 @@ __global__ __launch_bounds__(kThreads, 1) void k_bpass(Geom g, State s, const fl
 
     const size_t wgi = (size_t)pg * g.nqc + c;
     store_acc<NCB, NRBW, QC>(acc, s.Vpart + wgi * (size_t)L * QC, L, nrb, w, lane);
-    if (lane == 0) {
-#pragma unroll
-        for (int k = 0; k < CPW; ++k) {
-            const int q = w + 4 * k, m = c * R + q / PP;
-            if (q >= QC) continue;
-            const bool ok = m < g.M;
-            s.mpart[(size_t)pg * g.Qp + col0 + q] = ok ? mrun[k] : -INFINITY;
-            s.spart[(size_t)pg * g.Qp + col0 + q] = ok ? srun[k] : 0.f;
-        }
+    if (qin && sub == 0) {
+        s.mpart[(size_t)pg * g.Qp + col0 + sq] = cok ? mrun : -INFINITY;
+        s.spart[(size_t)pg * g.Qp + col0 + sq] = cok ? srun : 0.f;
     }
 }
 
@@ -1084,7 +1152,7 @@ __global__ __launch_bounds__(kThreads) void k_final_B(Geom g, State s, float* B_
     for (size_t e = (size_t)blockIdx.x * kThreads + threadIdx.x; e < n; e += (size_t)gridDim.x * kThreads) {
         const int pix = (int)(e / PP), j = (int)(e % PP);
         const int qp = base + j, tile = pix / kTile;
-        const float b = s.Bst[(size_t)(m * PP + j) * g.N + pix];
+        const float b = s.Bst[(size_t)(m * PP + j) * ((size_t)g.ntiles * kTile) + pix];
         B_out[(size_t)m * n + e] = b * expf(s.tshift[(size_t)tile * g.Qp + qp] - s.colm[qp] - logf(s.cols[qp]));
     }
 }
@@ -1175,9 +1243,15 @@ struct Kernels {
     }
     static hipError_t bpass(const Geom& g, const State& s, int mode, const RunInit& ri, hipStream_t st) {
         const size_t lds = (size_t)pass_lds(PP, R, g.L, g.dbuf).total * sizeof(float);
-        set_max_lds((const void*)k_bpass<PP, R>, (int)lds);
-        hipLaunchKernelGGL((k_bpass<PP, R>), dim3(g.npg * g.nqc), dim3(kThreads), lds, st, g, s, (const float*)s.W, mode,
-                           ri);
+        if (mode == kModeStep) {
+            set_max_lds((const void*)k_bpass<PP, R, true>, (int)lds);
+            hipLaunchKernelGGL((k_bpass<PP, R, true>), dim3(g.npg * g.nqc), dim3(kThreads), lds, st, g, s,
+                               (const float*)s.W, mode, ri);
+        } else {
+            set_max_lds((const void*)k_bpass<PP, R, false>, (int)lds);
+            hipLaunchKernelGGL((k_bpass<PP, R, false>), dim3(g.npg * g.nqc), dim3(kThreads), lds, st, g, s,
+                               (const float*)s.W, mode, ri);
+        }
         return hipGetLastError();
     }
     static hipError_t close(const Geom& g, const State& s, hipStream_t st) {
