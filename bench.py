@@ -25,12 +25,77 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-FP32_VECTOR_FMA_TFLOPS = 78.6     # 256 CU x 64 FMA lanes x 2 flop x 2.4 GHz (no packed FP32)
+FP32_MFMA_TFLOPS = 157.3          # MI355X dense FP32 matrix peak (v_mfma_f32_16x16x4f32: 32 cycles/SIMD)
 HBM_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_bpass_urban_ensemble_traffic.txt")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_2209_11002_amd", "csrc", "edaa_kernels.hip")
 
 
 def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def kernel_source_sha256():
+    import hashlib
+    with open(KERNEL_SOURCE, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def stored_traffic():
+    """HBM bytes per B-pass launch from the committed counter summary, or None
+    when it is missing or was taken from another version of the kernels."""
+    try:
+        fields = {}
+        with open(TRAFFIC_FILE) as f:
+            for line in f:
+                if ":" in line and not line.startswith(" "):
+                    k, v = line.split(":", 1)
+                    fields[k.strip()] = v.strip()
+        if fields.get("kernel_source_sha256") != kernel_source_sha256():
+            return None
+        return int(float(fields["traffic_bytes_per_launch"]))
+    except (OSError, KeyError, ValueError):
+        return None
+
+
+def profile_run(T):
+    """Workload for rocprofv3 counter passes: a plain device copy of known size
+    (the calibration of FETCH_SIZE / WRITE_SIZE) and then a short ensemble on
+    the bench scene (T outer iterations, so 5 T B-pass launches)."""
+    import torch
+    from paper_2209_11002_amd import api, synth
+    dev = torch.device("cuda:0")
+    nbytes = 256 << 20
+    src = torch.ones(nbytes // 4, device=dev)
+    dst = torch.empty_like(src)
+    torch.mul(src, 1.0, out=dst)          # reads and writes exactly nbytes
+    torch.cuda.synchronize()
+    log(f"calibration copy: {nbytes} bytes read, {nbytes} bytes written")
+    scene, cfg = synth.urban_ensemble()
+    X = api.normalize_pixels(torch.from_numpy(scene.X).to(dev))
+    api.ensemble(X, 6, cfg["seeds"], cfg["gammas"], T=T, K1=cfg["K1"], K2=cfg["K2"])
+    torch.cuda.synchronize()
+    log(f"profile run done (T={T})")
+
+
+def summarize(paths):
+    """Per-kernel means of rocprofv3 CSV output: counter collections (one row
+    per dispatch and counter) or kernel traces (durations)."""
+    import csv
+    import collections
+    acc = collections.defaultdict(lambda: collections.defaultdict(list))
+    for path in paths:
+        with open(path) as f:
+            for row in csv.DictReader(f):
+                name = row["Kernel_Name"].replace("edaa::(anonymous namespace)::", "")
+                if "Counter_Name" in row:
+                    acc[name][row["Counter_Name"]].append(float(row["Counter_Value"]))
+                elif "Start_Timestamp" in row:
+                    acc[name]["duration_us"].append((int(row["End_Timestamp"]) - int(row["Start_Timestamp"])) / 1e3)
+    for name, d in acc.items():
+        print(name)
+        for c, v in sorted(d.items()):
+            print(f"    {c:24s} mean {sum(v) / len(v):16.6g}   dispatches {len(v)}")
 
 
 def cpu_baseline(Xraw, p, seed, gamma, T_sample):
@@ -58,11 +123,20 @@ def main():
     ap.add_argument("--plain-runs", type=int, default=5, help="single runs timed for the plain path (0: skip)")
     ap.add_argument("--cpu-sample-T", type=int, default=3, help="oracle outer iterations timed (0: skip)")
     ap.add_argument("--n-seeds", type=int, default=10)
+    ap.add_argument("--profile-run", type=int, default=0, metavar="T",
+                    help="run the counter-profiling workload with T outer iterations and exit")
+    ap.add_argument("--summarize", nargs="+", metavar="CSV", help="summarise rocprofv3 CSV files and exit")
     args = ap.parse_args()
+    if args.summarize:
+        summarize(args.summarize)
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(run it with --gpus 1)", file=sys.stderr)
         sys.exit(2)
+    if args.profile_run > 0:
+        profile_run(args.profile_run)
+        return
 
     import numpy as np
     import torch
@@ -134,8 +208,8 @@ def main():
     b_avg_s = b_ms / max(b_n, 1) / 1e3
     a_avg_s = a_ms / max(a_n, 1) / 1e3
     achieved = bpass_flops / b_avg_s / 1e12
-    roofline = dict(bound="alu", achieved=round(achieved, 3), peak=FP32_VECTOR_FMA_TFLOPS, unit="TFLOP/s",
-                    frac=round(achieved / FP32_VECTOR_FMA_TFLOPS, 4), traffic=None,
+    roofline = dict(bound="mfma", achieved=round(achieved, 3), peak=FP32_MFMA_TFLOPS, unit="TFLOP/s",
+                    frac=round(achieved / FP32_MFMA_TFLOPS, 4), traffic=stored_traffic(),
                     kernel="k_bpass (B-pass)", avg_launch_us=round(b_avg_s * 1e6, 2),
                     algorithmic_bytes_per_launch=bpass_bytes, flops_per_launch=bpass_flops,
                     achieved_gbs=round(bpass_bytes / b_avg_s / 1e9, 1),

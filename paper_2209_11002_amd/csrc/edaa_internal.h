@@ -29,6 +29,7 @@ struct Geom {
     int ntiles;   // ceil(N / 64)
     int npg;      // pixel groups (workgroups per chunk)
     int dbuf;     // pass kernels double-buffer the X tile in LDS
+    int ecs;      // LDS pitch (floats) of the staged projection operand
 };
 
 // Device-side state of a batched problem.  Column q = m * p + j (run m,

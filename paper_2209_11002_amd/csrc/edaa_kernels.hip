@@ -136,6 +136,13 @@ __device__ __forceinline__ float wave_sum_dpp(float v) {
 }
 
 // e^x and ln x from the hardware base-2 instructions (v_exp_f32, v_log_f32).
+// Workgroup barrier for LDS traffic: waits for this wave's LDS operations
+// only.  __syncthreads() would also wait for every outstanding global load,
+// store and direct-to-LDS load (its release fence), which would stall the
+// prefetch of the next tile at every barrier; the pass kernels wait for
+// those explicitly where their data is used.
+__device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
+
 __device__ __forceinline__ float fast_exp(float x) { return __builtin_amdgcn_exp2f(x * 1.4426950408889634f); }
 __device__ __forceinline__ float fast_log(float x) { return __builtin_amdgcn_logf(x) * 0.6931471805599453f; }
 
@@ -276,15 +283,17 @@ struct PassLds {
 };
 // dbuf: a second X tile buffer, so that the next tile loads while the
 // current one is processed.
-__host__ __device__ inline PassLds pass_lds(int PP, int R, int L, int dbuf = 0) {
-    const int QC = PP * R, QCP = (QC + 15) & ~15, WTS = QCP + 1;
+// ecs: LDS pitch of the staged projection operand (QCP + 4 avoids bank
+// conflicts in the projections; QCP + 1 where LDS is short).
+__host__ __device__ inline PassLds pass_lds(int PP, int R, int L, int dbuf, int ecs) {
+    const int QC = PP * R, QCP = (QC + 15) & ~15, WTS = QCP + 1, ECS = ecs;
     const int LP = (L + 15) & ~15;
     PassLds o;
     o.xs = 0;
     o.wt = o.xs + LP * kXS;                    // [64][WTS] or [QCP][kXS] weights / projection results
     o.f = o.wt + (kTile * WTS > QCP * kXS ? kTile * WTS : QCP * kXS);   // [QCP] rescale factors
-    o.ec = o.f + QCP;                          // [LP][WTS] projection operand chunk (E or W)
-    o.gs = o.ec + LP * WTS;                    // [R][PP][PP] Gram matrices (double, 2 floats each)
+    o.ec = o.f + QCP;                          // [LP][ECS] projection operand chunk (E or W)
+    o.gs = o.ec + LP * ECS;                    // [R][PP][PP] Gram matrices (double, 2 floats each)
     o.gs = (o.gs + 1) & ~1;
     o.ps = o.gs + 2 * R * PP * PP;
     o.xx = o.ps;                               // [64] squared pixel norms (double, 2 floats each)
@@ -292,6 +301,20 @@ __host__ __device__ inline PassLds pass_lds(int PP, int R, int L, int dbuf = 0) 
     o.xs2 = o.pd + kTile * WTS;
     o.total = o.xs2 + (dbuf ? LP * kXS : 0);
     return o;
+}
+
+// Scheduling pattern for a block of NMFMA matrix instructions and the LDS
+// reads of the next block's operands: the reads go, up to four at a time,
+// between the first four MFMAs, so they complete while the later MFMAs of
+// the block run instead of stalling the next block.
+template <int NMFMA>
+__device__ __forceinline__ void interleave_loads() {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);   // one MFMA
+        __builtin_amdgcn_sched_group_barrier(0x100, 4, 0);   // up to four LDS reads
+    }
+    if (NMFMA > 4) __builtin_amdgcn_sched_group_barrier(0x008, NMFMA - 4, 0);
 }
 
 // V += X_tile Wt on the matrix cores.  Wave w owns the row blocks
@@ -311,20 +334,42 @@ __device__ __forceinline__ void mfma_accumulate(f4 (&acc)[NRBW][NCB], f4 (&gram)
 #pragma unroll
         for (int cb = 0; cb < NCB; ++cb)
             bop[k][cb] = QMAJOR ? Wt[(16 * cb + m) * kXS + 4 * k + kk] : Wt[(4 * k + kk) * WTS + 16 * cb + m];
+    // the X operands of the next row block are read while the MFMAs of the
+    // current one run (rows past the last block re-read the last one)
+    float xa[16];
+    {
+        const float* xr = Xs + (16 * min(w, nrb - 1) + m) * kXS + kk;
+#pragma unroll
+        for (int k = 0; k < 16; ++k) xa[k] = xr[4 * k];
+    }
+    float fs[NCB];
+    if (SCALE) {
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb) fs[cb] = F[16 * cb + m];
+    }
 #pragma unroll
     for (int j = 0; j < NRBW; ++j) {
         const int rb = w + 4 * j;
         if (rb < nrb) {
             if (SCALE) {
 #pragma unroll
-                for (int cb = 0; cb < NCB; ++cb) acc[j][cb] *= F[16 * cb + m];
+                for (int cb = 0; cb < NCB; ++cb) acc[j][cb] *= fs[cb];
             }
-            const float* xr = Xs + (16 * rb + m) * kXS + kk;
 #pragma unroll
             for (int k = 0; k < 16; ++k) {
-                const float a = xr[4 * k];
 #pragma unroll
-                for (int cb = 0; cb < NCB; ++cb) acc[j][cb] = mfma16(a, bop[k][cb], acc[j][cb]);
+                for (int cb = 0; cb < NCB; ++cb) acc[j][cb] = mfma16(xa[k], bop[k][cb], acc[j][cb]);
+            }
+            float xn[16];
+            if (j + 1 < NRBW) {
+                const float* xr = Xs + (16 * min(rb + 4, nrb - 1) + m) * kXS + kk;
+#pragma unroll
+                for (int k = 0; k < 16; ++k) xn[k] = xr[4 * k];
+                interleave_loads<16 * NCB>();
+            }
+            if (j + 1 < NRBW) {
+#pragma unroll
+                for (int k = 0; k < 16; ++k) xa[k] = xn[k];
             }
         }
     }
@@ -371,32 +416,54 @@ __device__ __forceinline__ void store_acc(const f4 (&acc)[NRBW][NCB], float* Vp,
 
 // Projection of the tile by a chunk operand staged in LDS (R > 1): wave w
 // computes the 16 pixels 16w..16w+15 for all QCP columns, S[q][i] =
-// sum_l Ec[l][q] Xs[l][i]; results go to Sc[i][q].  Also returns, for the
+// sum_l Ec[l][q] Xs[l][i]; results go to Sc[i][q] (or Sc[q][i] with QMAJOR).  Also returns, for the
 // same pixels, the partial sums of x^2 over the bands this lane touched.
 // LP (a multiple of 16) rows of both operands are read; rows L..LP-1 of
-// both are zero.
+// both are zero.  Within a block of 16 bands, MFMA step u takes the bands
+// u, u + 4, u + 8, u + 12 (lane group kk gets u + 4 kk): the four rows a
+// wave reads are then 4 rows apart, which with the pitches kXS = 68 and
+// ECS = QCP + 4 puts the 64 lanes on 64 distinct LDS banks.
 template <int NCB, int WTS, bool QMAJOR = false>
-__device__ __forceinline__ float mfma_project(const float* Ec, const float* Xs, float* Sc, int LP, int w, int lane) {
+__device__ __forceinline__ float mfma_project(const float* Ec, int ECS, const float* Xs, float* Sc, int LP, int w,
+                                              int lane) {
     const int m = lane & 15, kk = lane >> 4;
     f4 s[NCB];
 #pragma unroll
     for (int cb = 0; cb < NCB; ++cb) s[cb] = f4{0.f, 0.f, 0.f, 0.f};
     float xx = 0.f;
-    const float* xb = Xs + kk * kXS + 16 * w + m;
-    const float* eb = Ec + kk * WTS + m;
-    for (int k0 = 0; k0 < LP; k0 += 16) {
-        float b[4], e[4][NCB];
+    const float* xb = Xs + 4 * kk * kXS + 16 * w + m;
+    const float* eb = Ec + 4 * kk * ECS + m;
+    // Software pipeline over blocks of 16 bands with two register sets: the
+    // operands of the next block are read between the first MFMAs of the
+    // current one, so they arrive while the rest of its MFMAs run.
+    float b0[4], e0[4][NCB], b1[4], e1[4][NCB];
+    auto load = [&](float (&b)[4], float (&e)[4][NCB], int k0) {
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-            b[u] = xb[(k0 + 4 * u) * kXS];
+            b[u] = xb[(k0 + u) * kXS];
 #pragma unroll
-            for (int cb = 0; cb < NCB; ++cb) e[u][cb] = eb[(k0 + 4 * u) * WTS + 16 * cb];
+            for (int cb = 0; cb < NCB; ++cb) e[u][cb] = eb[(k0 + u) * ECS + 16 * cb];
         }
+    };
+    auto mma = [&](const float (&b)[4], const float (&e)[4][NCB]) {
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             xx = fmaf(b[u], b[u], xx);
 #pragma unroll
             for (int cb = 0; cb < NCB; ++cb) s[cb] = mfma16(e[u][cb], b[u], s[cb]);
+        }
+    };
+    load(b0, e0, 0);
+    for (int k0 = 0; k0 < LP; k0 += 32) {
+        if (k0 + 16 < LP) {                            // uniform
+            mma(b0, e0);
+            load(b1, e1, k0 + 16);
+            interleave_loads<4 * NCB>();
+            mma(b1, e1);
+            load(b0, e0, (k0 + 32 < LP) ? k0 + 32 : k0);
+            interleave_loads<4 * NCB>();
+        } else {
+            mma(b0, e0);
         }
     }
 #pragma unroll
@@ -419,29 +486,45 @@ __device__ __forceinline__ float mfma_project(const float* Ec, const float* Xs, 
 // lo = fl(P - hi), which carries it to about 48 bits; returns the partial
 // ||x||^2 of this lane's bands.
 template <int NCB, int WTS>
-__device__ __forceinline__ double mfma_project_f64(const float* Ec, const float* Xs, float* Sc, float* Plo, int LP,
-                                                   int w, int lane) {
+__device__ __forceinline__ double mfma_project_f64(const float* Ec, int ECS, const float* Xs, float* Sc, float* Plo,
+                                                   int LP, int w, int lane) {
     const int m = lane & 15, kk = lane >> 4;
     d4 s[NCB];
 #pragma unroll
     for (int cb = 0; cb < NCB; ++cb) s[cb] = d4{0.0, 0.0, 0.0, 0.0};
     double xx = 0.0;
-    const float* xb = Xs + kk * kXS + 16 * w + m;
-    const float* eb = Ec + kk * WTS + m;
-    for (int k0 = 0; k0 < LP; k0 += 16) {
-        float b[4], e[4][NCB];
+    const float* xb = Xs + 4 * kk * kXS + 16 * w + m;
+    const float* eb = Ec + 4 * kk * ECS + m;
+    // same software pipeline as mfma_project
+    float b0[4], e0[4][NCB], b1[4], e1[4][NCB];
+    auto load = [&](float (&b)[4], float (&e)[4][NCB], int k0) {
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-            b[u] = xb[(k0 + 4 * u) * kXS];
+            b[u] = xb[(k0 + u) * kXS];
 #pragma unroll
-            for (int cb = 0; cb < NCB; ++cb) e[u][cb] = eb[(k0 + 4 * u) * WTS + 16 * cb];
+            for (int cb = 0; cb < NCB; ++cb) e[u][cb] = eb[(k0 + u) * ECS + 16 * cb];
         }
+    };
+    auto mma = [&](const float (&b)[4], const float (&e)[4][NCB]) {
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             const double bd = (double)b[u];
             xx = fma(bd, bd, xx);
 #pragma unroll
             for (int cb = 0; cb < NCB; ++cb) s[cb] = mfma16d((double)e[u][cb], bd, s[cb]);
+        }
+    };
+    load(b0, e0, 0);
+    for (int k0 = 0; k0 < LP; k0 += 32) {
+        if (k0 + 16 < LP) {                            // uniform
+            mma(b0, e0);
+            load(b1, e1, k0 + 16);
+            interleave_loads<4 * NCB>();
+            mma(b1, e1);
+            load(b0, e0, (k0 + 32 < LP) ? k0 + 32 : k0);
+            interleave_loads<4 * NCB>();
+        } else {
+            mma(b0, e0);
         }
     }
 #pragma unroll
@@ -456,11 +539,12 @@ __device__ __forceinline__ double mfma_project_f64(const float* Ec, const float*
 }
 
 // Stage U[:, chunk] (rows < L, QCP columns) in LDS with rows L..LP-1 zero.
-template <int QC, int QCP, int WTS>
-__device__ __forceinline__ void stage_chunk(const float* __restrict__ U, int Qp, int col0, int L, int LP, float* Ec) {
+template <int QC, int QCP>
+__device__ __forceinline__ void stage_chunk(const float* __restrict__ U, int Qp, int col0, int L, int LP, float* Ec,
+                                            int ECS) {
     for (int e = threadIdx.x; e < LP * QCP; e += kThreads) {
         const int l = e / QCP, q = e % QCP;
-        Ec[l * WTS + q] = (l < L && q < QC) ? U[(size_t)l * Qp + col0 + q] : 0.f;
+        Ec[l * ECS + q] = (l < L && q < QC) ? U[(size_t)l * Qp + col0 + q] : 0.f;
     }
 }
 
@@ -472,9 +556,10 @@ template <int PP, int R>
 __global__ __launch_bounds__(kThreads, 1) void k_apass(Geom g, State s, const float* __restrict__ E, int K1) {
     using S = Shape<PP, R>;
     constexpr int QC = S::QC, QCP = S::QCP, NCB = S::NCB, WTS = S::WTS, RW = S::RW, NRBW = S::NRBW;
+    const int ECS = g.ecs;
     constexpr int NGBW = S::NGBW;
     extern __shared__ float smem[];
-    const PassLds lo = pass_lds(PP, R, g.L, g.dbuf);
+    const PassLds lo = pass_lds(PP, R, g.L, g.dbuf, g.ecs);
     float* Wt = smem + lo.wt;
     float* Ec = smem + lo.ec;
     double* Gd = (double*)(smem + lo.gs);
@@ -493,13 +578,13 @@ __global__ __launch_bounds__(kThreads, 1) void k_apass(Geom g, State s, const fl
     // Gram matrices of this chunk's runs, in float64 from the float32 E the
     // projection uses (so that the objective formed from P and G below is
     // consistent with that E).
-    stage_chunk<QC, QCP, WTS>(E, g.Qp, col0, L, LP, Ec);
+    stage_chunk<QC, QCP>(E, g.Qp, col0, L, LP, Ec, ECS);
     __syncthreads();
     for (int e = tid; e < R * PP * PP; e += kThreads) {
         const int r = e / (PP * PP), jk = e % (PP * PP), j = jk / PP, k = jk % PP;
         const float* Ek = Ec + r * PP;
         double acc = 0.0;
-        for (int l = 0; l < L; ++l) acc = fma((double)Ek[l * WTS + j], (double)Ek[l * WTS + k], acc);
+        for (int l = 0; l < L; ++l) acc = fma((double)Ek[l * ECS + j], (double)Ek[l * ECS + k], acc);
         Gd[e] = acc;
     }
     __syncthreads();
@@ -544,11 +629,11 @@ __global__ __launch_bounds__(kThreads, 1) void k_apass(Geom g, State s, const fl
     for (int tile = pg; tile < g.ntiles; tile += g.npg, ++it) {
         float* Xs = smem + ((it & 1) ? xo[1] : xo[0]);
         if (!dma) {
-            __syncthreads();
+            lds_barrier();
             load_tile_sync(s.X, s.x_bf16, L, N, tile, Xs);
         }
         __builtin_amdgcn_s_waitcnt(0);
-        __syncthreads();
+        lds_barrier();
         const int pix = tile * kTile + lane;
         const bool pok = pix < N;
         float a[RW][PP];
@@ -566,11 +651,11 @@ __global__ __launch_bounds__(kThreads, 1) void k_apass(Geom g, State s, const fl
         }
         {
             // projection on the matrix cores: P for pixels 16w..16w+15
-            double xx = mfma_project_f64<NCB, WTS>(Ec, Xs, Wt, Plo, LP, w, lane);
+            double xx = mfma_project_f64<NCB, WTS>(Ec, ECS, Xs, Wt, Plo, LP, w, lane);
             xx += __shfl_xor(xx, 16);       // the 4 band classes of the pixel
             xx += __shfl_xor(xx, 32);
             if (lane < 16) XX[16 * w + lane] = xx;
-            __syncthreads();
+            lds_barrier();
             // A-steps: lane = pixel, runs r = w + 4k of the chunk
             const double xnorm = XX[lane];
 #pragma unroll
@@ -603,10 +688,10 @@ __global__ __launch_bounds__(kThreads, 1) void k_apass(Geom g, State s, const fl
                 }
             }
         }
-        __syncthreads();
+        lds_barrier();
         mfma_accumulate<NCB, NRBW, WTS, false, NGBW>(acc, gram, true, Xs, Wt, nullptr, nrb, w, lane);
         if (nt < g.ntiles && dma && !g.dbuf) {
-            __syncthreads();                        // single buffer: reload after every reader
+            lds_barrier();                        // single buffer: reload after every reader
             dma_tile((const float*)s.X, L, N, nt, Xs);
         }
     }
@@ -662,9 +747,10 @@ __global__ __launch_bounds__(kThreads, 1) void k_bpass(Geom g, State s, const fl
                                                        RunInit ri) {
     using S = Shape<PP, R>;
     constexpr int QC = S::QC, QCP = S::QCP, NCB = S::NCB, WTS = S::WTS, NRBW = S::NRBW;
+    const int ECS = g.ecs;
     static_assert(QCP <= kThreads / 4, "one quad of threads per softmax column");
     extern __shared__ float smem[];
-    const PassLds lo = pass_lds(PP, R, g.L, g.dbuf);
+    const PassLds lo = pass_lds(PP, R, g.L, g.dbuf, g.ecs);
     float* Wq = smem + lo.wt;                      // [QCP][kXS]
     float* F = smem + lo.f;
     float* Ec = smem + lo.ec;
@@ -684,7 +770,7 @@ __global__ __launch_bounds__(kThreads, 1) void k_bpass(Geom g, State s, const fl
     }
     for (int e = tid; e < QCP * kXS; e += kThreads) Wq[e] = 0.f;
     for (int e = tid; e < QCP; e += kThreads) F[e] = 0.f;
-    if (STEP) stage_chunk<QC, QCP, WTS>(W, g.Qp, col0, L, LP, Ec);
+    if (STEP) stage_chunk<QC, QCP>(W, g.Qp, col0, L, LP, Ec, ECS);
 
     // this thread's softmax column and pixel segment
     const int sq = tid >> 2, sub = tid & 3;
@@ -727,11 +813,11 @@ __global__ __launch_bounds__(kThreads, 1) void k_bpass(Geom g, State s, const fl
     for (int tile = pg; tile < g.ntiles; tile += g.npg, ++it) {
         float* Xs = smem + ((it & 1) ? xo[1] : xo[0]);
         if (!dma) {
-            __syncthreads();
+            lds_barrier();
             load_tile_sync(s.X, s.x_bf16, L, N, tile, Xs);
         }
         __builtin_amdgcn_s_waitcnt(0);
-        __syncthreads();
+        lds_barrier();
         f4 bv[4];
 #pragma unroll
         for (int u = 0; u < 4; ++u) bv[u] = bn[u];
@@ -743,8 +829,8 @@ __global__ __launch_bounds__(kThreads, 1) void k_bpass(Geom g, State s, const fl
         }
 
         if (STEP) {
-            (void)mfma_project<NCB, WTS, true>(Ec, Xs, Wq, LP, w, lane);
-            __syncthreads();
+            (void)mfma_project<NCB, WTS, true>(Ec, ECS, Xs, Wq, LP, w, lane);
+            lds_barrier();
         }
 
         if (qin) {
@@ -798,10 +884,10 @@ __global__ __launch_bounds__(kThreads, 1) void k_bpass(Geom g, State s, const fl
                 if (cok) s.tshift[(size_t)tile * g.Qp + col0 + sq] = mnew;
             }
         }
-        __syncthreads();
+        lds_barrier();
         mfma_accumulate<NCB, NRBW, WTS, true, 1, true>(acc, gdummy, false, Xs, Wq, F, nrb, w, lane);
         if (nt < g.ntiles && dma && !g.dbuf) {
-            __syncthreads();                        // single buffer: reload after every reader
+            lds_barrier();                        // single buffer: reload after every reader
             dma_tile((const float*)s.X, L, N, nt, Xs);
         }
     }
@@ -1228,7 +1314,8 @@ __global__ __launch_bounds__(kThreads) void k_normalize(const float* __restrict_
 
 size_t pass_lds_bytes(int PP, int R, int L, int kind) {
     if (kind == 2) return ((size_t)L * kXS + 8 * kTile) * sizeof(float);
-    return (size_t)pass_lds(PP, R, L, 0).total * sizeof(float);
+    const int QCP = (PP * R + 15) & ~15;
+    return (size_t)pass_lds(PP, R, L, 0, QCP + 1).total * sizeof(float);
 }
 
 namespace {
@@ -1236,13 +1323,13 @@ namespace {
 template <int PP, int R>
 struct Kernels {
     static hipError_t apass(const Geom& g, const State& s, int K1, hipStream_t st) {
-        const size_t lds = (size_t)pass_lds(PP, R, g.L, g.dbuf).total * sizeof(float);
+        const size_t lds = (size_t)pass_lds(PP, R, g.L, g.dbuf, g.ecs).total * sizeof(float);
         set_max_lds((const void*)k_apass<PP, R>, (int)lds);
         hipLaunchKernelGGL((k_apass<PP, R>), dim3(g.npg * g.nqc), dim3(kThreads), lds, st, g, s, (const float*)s.E, K1);
         return hipGetLastError();
     }
     static hipError_t bpass(const Geom& g, const State& s, int mode, const RunInit& ri, hipStream_t st) {
-        const size_t lds = (size_t)pass_lds(PP, R, g.L, g.dbuf).total * sizeof(float);
+        const size_t lds = (size_t)pass_lds(PP, R, g.L, g.dbuf, g.ecs).total * sizeof(float);
         if (mode == kModeStep) {
             set_max_lds((const void*)k_bpass<PP, R, true>, (int)lds);
             hipLaunchKernelGGL((k_bpass<PP, R, true>), dim3(g.npg * g.nqc), dim3(kThreads), lds, st, g, s,
@@ -1339,7 +1426,7 @@ int runs_per_chunk(int p, int M, int L) {
     if (M <= 1) return 1;
     const int R = (M <= 4) ? 4 : rmax_for(p);
     // the stacked-run kernels keep the projection operand in LDS as well
-    if ((size_t)pass_lds(p, R, L).total * sizeof(float) > kMaxLdsBytes) return 1;
+    if ((size_t)pass_lds(p, R, L, 0, ((p * R + 15) & ~15) + 1).total * sizeof(float) > kMaxLdsBytes) return 1;
     return R;
 }
 
@@ -1355,7 +1442,20 @@ Geom make_geom(int L, int N, int M, int p) {
     if (npg >= 8) npg &= ~7;
     npg = std::max(1, std::min(npg, g.ntiles));
     g.npg = npg;
-    g.dbuf = ((size_t)pass_lds(p, g.R, L, 1).total * sizeof(float) <= kMaxLdsBytes) ? 1 : 0;
+    // prefer the double-buffered X tile, then the conflict-free operand pitch
+    const int QCP = (g.QC + 15) & ~15;
+    auto fits = [&](int db, int ecs) {
+        return (size_t)pass_lds(p, g.R, L, db, ecs).total * sizeof(float) <= kMaxLdsBytes;
+    };
+    if (fits(1, QCP + 4)) {
+        g.dbuf = 1; g.ecs = QCP + 4;
+    } else if (fits(1, QCP + 1)) {
+        g.dbuf = 1; g.ecs = QCP + 1;
+    } else if (fits(0, QCP + 4)) {
+        g.dbuf = 0; g.ecs = QCP + 4;
+    } else {
+        g.dbuf = 0; g.ecs = QCP + 1;
+    }
     return g;
 }
 
