@@ -98,6 +98,70 @@ def summarize(paths):
             print(f"    {c:24s} mean {sum(v) / len(v):16.6g}   dispatches {len(v)}")
 
 
+def bench_ragged(n_images, T):
+    """Ragged batch: single runs (gamma 1, seed = image index) on n_images
+    images of different (L, N, p), batched (one launch per kernel and group of
+    equal p, replayed from a HIP graph) against per-image fits (each replayed
+    from its own graph).  Returns image-iterations/s of both."""
+    import numpy as np
+    import torch
+    from paper_2209_11002_amd import api, synth
+    scenes, _ = synth.ragged_images(n_images)
+    dev = torch.device("cuda:0")
+    X = [api.normalize_pixels(torch.from_numpy(sc.X).to(dev)) for sc in scenes]
+    ps = [sc.M.shape[1] for sc in scenes]
+    seeds = list(range(n_images))
+    gammas = [1.0] * n_images
+    api.fit_ragged(X, ps, seeds, gammas, T=T, graph=True)            # capture
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rb = api.fit_ragged(X, ps, seeds, gammas, T=T, graph=True)
+    torch.cuda.synchronize()
+    tb = time.perf_counter() - t0
+    for k in range(n_images):                                         # capture
+        api.fit(X[k], ps[k], T=T, gamma=1.0, seed=k, graph=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rs = [api.fit(X[k], ps[k], T=T, gamma=1.0, seed=k, graph=True) for k in range(n_images)]
+    torch.cuda.synchronize()
+    ts = time.perf_counter() - t0
+    same = all(np.array_equal(a["loss"], b["loss"]) for a, b in zip(rb, rs))
+    pixels = sum(sc.X.shape[1] for sc in scenes)
+    return dict(unit="image-iterations/s", images=n_images, T=T, pixels=pixels,
+                batched=round(n_images * T / tb, 2), per_image=round(n_images * T / ts, 2),
+                speedup=round(ts / tb, 3), identical_to_per_image=bool(same))
+
+
+def bench_bf16_large(T):
+    """BF16 X on the large smooth scene (L=224, N=512x614, p=12, M=20): the
+    batched ensemble with X stored in bf16, against the same ensemble with
+    float32 X (run-iterations/s of both, and the largest relative difference
+    of the final objective between them)."""
+    import numpy as np
+    import torch
+    from paper_2209_11002_amd import api, synth
+    scene, cfg = synth.large_smooth()
+    dev = torch.device("cuda:0")
+    Xraw = torch.from_numpy(scene.X).to(dev)
+    X32 = api.normalize_pixels(Xraw)
+    X16 = api.normalize_pixels(Xraw, out_dtype=torch.bfloat16)
+    del Xraw
+    seeds, gammas = cfg["seeds"], cfg["gammas"]
+    M, p = len(seeds), 12
+    res = {}
+    for name, X in (("bf16", X16), ("f32", X32)):
+        api.ensemble(X, p, seeds, gammas, T=T, graph=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = api.ensemble(X, p, seeds, gammas, T=T, graph=True)
+        torch.cuda.synchronize()
+        res[name] = (M * T / (time.perf_counter() - t0), r["loss"][:, -1].copy())
+    rel = float(np.max(np.abs(res["bf16"][1] - res["f32"][1]) / res["f32"][1]))
+    L, N = X32.shape
+    return dict(unit="run-iterations/s", L=L, N=N, p=p, M=M, T=T, bf16=round(res["bf16"][0], 2),
+                f32=round(res["f32"][0], 2), final_loss_max_rel_diff_bf16_vs_f32=rel)
+
+
 def cpu_baseline(Xraw, p, seed, gamma, T_sample):
     """The float64 oracle as it stands, on the same scene, for T_sample outer
     iterations of one run; returns run-iterations/s and the threads used."""
@@ -123,6 +187,8 @@ def main():
     ap.add_argument("--plain-runs", type=int, default=5, help="single runs timed for the plain path (0: skip)")
     ap.add_argument("--cpu-sample-T", type=int, default=3, help="oracle outer iterations timed (0: skip)")
     ap.add_argument("--n-seeds", type=int, default=10)
+    ap.add_argument("--ragged-images", type=int, default=64, help="images of the ragged batch (0: skip)")
+    ap.add_argument("--bf16-T", type=int, default=100, help="outer iterations of the BF16 large-scene runs (0: skip)")
     ap.add_argument("--profile-run", type=int, default=0, metavar="T",
                     help="run the counter-profiling workload with T outer iterations and exit")
     ap.add_argument("--summarize", nargs="+", metavar="CSV", help="summarise rocprofv3 CSV files and exit")
@@ -236,6 +302,17 @@ def main():
                      batched_speedup=round(value / pval, 2), final_loss_max_rel_diff=rel)
         log(f"plain: {pval:.1f} run-it/s (speedup {value / pval:.2f}x, final-loss rel diff {rel:.2e})")
 
+    ragged = None
+    if args.ragged_images > 0:
+        log(f"ragged batch: {args.ragged_images} images")
+        ragged = bench_ragged(args.ragged_images, T)
+        log(f"ragged: batched {ragged['batched']} vs per-image {ragged['per_image']} image-it/s")
+    bf16 = None
+    if args.bf16_T > 0:
+        log("bf16 X, large smooth scene")
+        bf16 = bench_bf16_large(args.bf16_T)
+        log(f"bf16: {bf16['bf16']} run-it/s (f32 {bf16['f32']}), final-loss rel diff {bf16['final_loss_max_rel_diff_bf16_vs_f32']:.2e}")
+
     cpu = None
     if args.cpu_sample_T > 0:
         log("timing the float64 oracle on the host")
@@ -266,6 +343,8 @@ def main():
         "value_graph_replay": round(value_graph, 2),
         "roofline": roofline,
         "plain": plain,
+        "ragged": ragged,
+        "bf16_large": bf16,
         "cpu_baseline": cpu,
         "selected_run": int(r["selected"]),
     }

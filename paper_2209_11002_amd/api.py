@@ -138,10 +138,11 @@ def ensemble(X, p, seeds, gammas, T=100, K1=5, K2=5, coherence="cosine", thresho
                 selected=sel.value, launches=lib.edaa_last_launch_count(_ctx(dev)))
 
 
-def fit_ragged(images, ps, seeds, gammas, T=100, K1=5, K2=5, init_scale=0.1):
-    """Independent runs of Algorithm 1 on images of different (L, N, p).
+def fit_ragged(images, ps, seeds, gammas, T=100, K1=5, K2=5, init_scale=0.1, graph=False):
+    """Independent runs of Algorithm 1 on images of different (L, N, p), all
+    advanced together (one launch per kernel and group of equal p).
     images: list of l2-normalised [L_k, N_k] GPU tensors (one dtype).
-    Returns a list of dicts like fit()."""
+    Returns a list of dicts with A, B, E (tensors) and loss (numpy)."""
     n = len(images)
     descs = (L_.EdaaImageDesc * n)()
     outs, traces = [], []
@@ -159,7 +160,7 @@ def fit_ragged(images, ps, seeds, gammas, T=100, K1=5, K2=5, init_scale=0.1):
         d.loss_trace = tr
         outs.append(o)
         traces.append(tr)
-    P = _params(T, K1, K2, 1.0, None, init_scale, 1.05, _x_dtype(images[0]), "cosine", False)
+    P = _params(T, K1, K2, 1.0, None, init_scale, 1.05, _x_dtype(images[0]), "cosine", graph)
     check(L_.load().edaa_fit_ragged(_ctx(images[0].device), n, descs, byref(P)))
     for o, tr in zip(outs, traces):
         o["loss"] = np.array(tr[:])

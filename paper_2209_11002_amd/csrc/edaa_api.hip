@@ -286,12 +286,13 @@ std::string graph_key(const Seq& q, const void* X, const void* ws) {
     return buf;
 }
 
-// Run (or replay) the sequence on the caller's stream.
-edaa_status run_sequence(edaa_ctx* ctx, const Seq& q, const void* X, int use_graph) {
-    ctx->timer.used = 0;
+// Run an enqueue function eagerly, or capture it once into a HIP graph kept
+// under `key` and replay that graph.
+template <typename F>
+edaa_status run_captured(edaa_ctx* ctx, const std::string& key, bool use_graph, F&& enqueue) {
     if (!use_graph) {
         long long n = 0;
-        hipError_t e = enqueue_sequence(q, ctx->stream, &n);
+        hipError_t e = enqueue(ctx->stream, &n);
         if (e != hipSuccess) {
             ctx->poisoned = true;
             return fail(EDAA_EDEVICE, "kernel launch failed: %s", hipGetErrorString(e));
@@ -299,10 +300,6 @@ edaa_status run_sequence(edaa_ctx* ctx, const Seq& q, const void* X, int use_gra
         ctx->last_launches = n;
         return EDAA_OK;
     }
-    // Events recorded inside a captured graph carry no timestamps on this
-    // runtime: pass timing is taken in eager mode only.
-    q.timer->enabled = false;
-    const std::string key = graph_key(q, X, ctx->ws);
     for (size_t i = 0; i < ctx->graphs.size(); ++i) {
         if (ctx->graphs[i].key == key) {
             EDAA_HIP(ctx, hipGraphLaunch(ctx->graphs[i].exec, ctx->stream));
@@ -313,7 +310,7 @@ edaa_status run_sequence(edaa_ctx* ctx, const Seq& q, const void* X, int use_gra
     if (!ctx->cap_stream) EDAA_HIP(ctx, hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
     EDAA_HIP(ctx, hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal));
     long long n = 0;
-    hipError_t e = enqueue_sequence(q, ctx->cap_stream, &n);
+    hipError_t e = enqueue(ctx->cap_stream, &n);
     hipGraph_t graph = nullptr;
     hipError_t e2 = hipStreamEndCapture(ctx->cap_stream, &graph);
     if (e != hipSuccess || e2 != hipSuccess) {
@@ -336,6 +333,17 @@ edaa_status run_sequence(edaa_ctx* ctx, const Seq& q, const void* X, int use_gra
     EDAA_HIP(ctx, hipGraphLaunch(exec, ctx->stream));
     ctx->last_launches = n;
     return EDAA_OK;
+}
+
+// Run (or replay) the sequence on the caller's stream.
+edaa_status run_sequence(edaa_ctx* ctx, const Seq& q, const void* X, int use_graph) {
+    ctx->timer.used = 0;
+    // Events recorded inside a captured graph carry no timestamps on this
+    // runtime: pass timing is taken in eager mode only.
+    if (use_graph) q.timer->enabled = false;
+    const std::string key = use_graph ? graph_key(q, X, ctx->ws) : std::string();
+    return run_captured(ctx, key, use_graph != 0,
+                        [&](hipStream_t st, long long* n) { return enqueue_sequence(q, st, n); });
 }
 
 // Shared implementation of edaa_fit (M = 1) and edaa_ensemble.
@@ -392,6 +400,186 @@ edaa_status run_batch(edaa_ctx* ctx, const void* X, int L, int N, int p, const e
     if (eta_out)
         EDAA_HIP(ctx, hipMemcpyAsync(eta_out, s.etad, sizeof(double) * 2 * M, hipMemcpyDeviceToHost, ctx->stream));
     if (loss || fit || mu || eta_out) EDAA_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    return EDAA_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Ragged batch: single runs on images of different (L, N, p).  Images of equal
+// p form a group; every kernel of Algorithm 1 is one launch per group, whose
+// workgroups look up their image in a device table (ImageJob) through a map
+// workgroup -> (image, workgroup within the image).
+// ---------------------------------------------------------------------------
+struct RaggedGroup {
+    int p;
+    int nb[kMapKinds];
+    const int2* map[kMapKinds];   // device
+    size_t lds_a, lds_b, lds_c;
+};
+
+hipError_t enqueue_ragged(const std::vector<RaggedGroup>& groups, const ImageJob* jobs, int T, int K1, int K2,
+                          int cosine, hipStream_t st, long long* launches) {
+    long long n = 0;
+    hipError_t e;
+    auto L_ = [&](int kernel, int mapk, size_t lds, int arg) -> hipError_t {
+        for (const RaggedGroup& G : groups) {
+            hipError_t r = launch_multi(kernel, G.p, jobs, G.map[mapk], G.nb[mapk], lds ? lds : 0, arg, st);
+            if (r != hipSuccess) return r;
+            ++n;
+        }
+        return hipSuccess;
+    };
+    // the LDS size differs per group: pass it per group through a second loop
+    auto Lp = [&](int kernel, size_t RaggedGroup::*lds, int arg) -> hipError_t {
+        for (const RaggedGroup& G : groups) {
+            hipError_t r = launch_multi(kernel, G.p, jobs, G.map[kMapPass], G.nb[kMapPass], G.*lds, arg, st);
+            if (r != hipSuccess) return r;
+            ++n;
+        }
+        return hipSuccess;
+    };
+    if ((e = L_(kMultiPrep, kMapElem, 0, 0)) != hipSuccess) return e;
+    if ((e = Lp(kMultiBpassInit, &RaggedGroup::lds_b, 0)) != hipSuccess) return e;
+    if ((e = L_(kMultiRedB, kMapRows, 0, 0)) != hipSuccess) return e;
+    if ((e = L_(kMultiEta, kMapOne, 0, 0)) != hipSuccess) return e;
+    for (int t = 0; t < T; ++t) {
+        if ((e = Lp(kMultiApass, &RaggedGroup::lds_a, K1)) != hipSuccess) return e;
+        if ((e = L_(kMultiRedAA, kMapOne, 0, t)) != hipSuccess) return e;
+        if ((e = L_(kMultiRedA, kMapRows, 0, t)) != hipSuccess) return e;
+        for (int k = 0; k < K2; ++k) {
+            if ((e = Lp(kMultiBpassStep, &RaggedGroup::lds_b, 0)) != hipSuccess) return e;
+            if ((e = L_(kMultiRedB, kMapRows, 0, k + 1 < K2 ? 1 : 0)) != hipSuccess) return e;
+        }
+    }
+    if ((e = Lp(kMultiClose, &RaggedGroup::lds_c, 0)) != hipSuccess) return e;
+    if ((e = L_(kMultiCloseReduce, kMapOne, 0, 0)) != hipSuccess) return e;
+    if ((e = L_(kMultiFinal, kMapElem, 0, cosine)) != hipSuccess) return e;
+    *launches = n;
+    return hipSuccess;
+}
+
+edaa_status run_ragged(edaa_ctx* ctx, int n, const edaa_image_desc* images, const edaa_params* P) {
+    const int T = P->T;
+    // groups of equal p, in order of first appearance
+    std::vector<int> ps;
+    std::vector<std::vector<int>> members;
+    for (int k = 0; k < n; ++k) {
+        size_t gi = 0;
+        while (gi < ps.size() && ps[gi] != images[k].p) ++gi;
+        if (gi == ps.size()) {
+            ps.push_back(images[k].p);
+            members.emplace_back();
+        }
+        members[gi].push_back(k);
+    }
+    // workspace: per-image state, then the job table and the maps
+    std::vector<Geom> geoms(n);
+    std::vector<size_t> off(n);
+    Arena a;
+    for (int k = 0; k < n; ++k) {
+        geoms[k] = make_geom(images[k].L, images[k].N, 1, images[k].p);
+        const size_t bytes = layout(geoms[k], T, nullptr, nullptr);
+        off[k] = a.take<char>(bytes);
+    }
+    const size_t o_jobs = a.take<ImageJob>(n);
+    std::vector<std::vector<int2>> maps(ps.size() * kMapKinds);
+    for (size_t gi = 0; gi < ps.size(); ++gi)
+        for (int k : members[gi]) {
+            const Geom& g = geoms[k];
+            for (int b = 0; b < g.npg * g.nqc; ++b) maps[gi * kMapKinds + kMapPass].push_back(make_int2(k, b));
+            for (int b = 0; b < g.L; ++b) maps[gi * kMapKinds + kMapRows].push_back(make_int2(k, b));
+            maps[gi * kMapKinds + kMapOne].push_back(make_int2(k, 0));
+            for (int b = 0; b < kElemBlocks; ++b) maps[gi * kMapKinds + kMapElem].push_back(make_int2(k, b));
+        }
+    std::vector<size_t> o_maps(maps.size());
+    for (size_t i = 0; i < maps.size(); ++i) o_maps[i] = a.take<int2>(maps[i].size());
+    edaa_status st = ensure_ws(ctx, a.off + 256);
+    if (st != EDAA_OK) return st;
+    char* base = (char*)ctx->ws;
+
+    std::vector<ImageJob> jobs(n);
+    std::vector<uint64_t> seeds(n);
+    std::vector<double> gammas(n);
+    std::vector<RunBuffers> rbs(n);
+    for (int k = 0; k < n; ++k) {
+        const edaa_image_desc& d = images[k];
+        RunBuffers& rb = rbs[k];
+        memset(&rb, 0, sizeof(rb));
+        layout(geoms[k], T, base + off[k], &rb);
+        rb.s.X = d.X;
+        rb.s.x_bf16 = P->x_dtype == EDAA_X_BF16 ? 1 : 0;
+        rb.s.A = d.A;
+        ImageJob& J = jobs[k];
+        memset(&J, 0, sizeof(J));
+        J.g = geoms[k];
+        J.s = rb.s;
+        J.ri.seeds = rb.seeds;
+        J.ri.gammas = rb.gammas;
+        J.ri.init_scale = (float)P->init_scale;
+        J.ri.B0 = nullptr;
+        J.ri.A0 = nullptr;
+        J.ri.eta1 = P->eta1;
+        J.ri.eta2 = P->eta2;
+        J.B_out = d.B;
+        J.E_out = d.E;
+        seeds[k] = d.seed;
+        gammas[k] = d.gamma;
+    }
+    // host -> device copies happen outside any graph
+    for (int k = 0; k < n; ++k) {
+        EDAA_HIP(ctx, hipMemcpyAsync(rbs[k].seeds, &seeds[k], sizeof(uint64_t), hipMemcpyHostToDevice, ctx->stream));
+        EDAA_HIP(ctx, hipMemcpyAsync(rbs[k].gammas, &gammas[k], sizeof(double), hipMemcpyHostToDevice, ctx->stream));
+    }
+    const ImageJob* jobs_dev = (const ImageJob*)(base + o_jobs);
+    EDAA_HIP(ctx, hipMemcpyAsync(base + o_jobs, jobs.data(), sizeof(ImageJob) * n, hipMemcpyHostToDevice, ctx->stream));
+    std::vector<RaggedGroup> groups(ps.size());
+    for (size_t gi = 0; gi < ps.size(); ++gi) {
+        RaggedGroup& G = groups[gi];
+        G.p = ps[gi];
+        for (int mk = 0; mk < kMapKinds; ++mk) {
+            const std::vector<int2>& m = maps[gi * kMapKinds + mk];
+            G.nb[mk] = (int)m.size();
+            G.map[mk] = (const int2*)(base + o_maps[gi * kMapKinds + mk]);
+            EDAA_HIP(ctx, hipMemcpyAsync(base + o_maps[gi * kMapKinds + mk], m.data(), sizeof(int2) * m.size(),
+                                         hipMemcpyHostToDevice, ctx->stream));
+        }
+        G.lds_a = G.lds_b = G.lds_c = 0;
+        for (int k : members[gi]) {
+            const Geom& g = geoms[k];
+            G.lds_a = std::max(G.lds_a, launch_lds_bytes(g, 0));
+            G.lds_b = std::max(G.lds_b, launch_lds_bytes(g, 1));
+            G.lds_c = std::max(G.lds_c, launch_lds_bytes(g, 2));
+        }
+    }
+    // the copies read host vectors of this frame: finish them before any
+    // return path releases those vectors
+    EDAA_HIP(ctx, hipStreamSynchronize(ctx->stream));
+
+    std::string key = "ragged";
+    {
+        char buf[160];
+        snprintf(buf, sizeof(buf), "|%d,%d,%d,%d,%d,%a,%p", T, P->K1, P->K2, P->coherence_mode, P->x_dtype,
+                 P->init_scale, ctx->ws);
+        key += buf;
+        for (int k = 0; k < n; ++k) {
+            const edaa_image_desc& d = images[k];
+            snprintf(buf, sizeof(buf), "|%d,%d,%d,%p,%p,%p,%p", d.L, d.N, d.p, d.X, (void*)d.A, (void*)d.B,
+                     (void*)d.E);
+            key += buf;
+        }
+    }
+    const int K1 = P->K1, K2 = P->K2, cosine = P->coherence_mode == EDAA_COHERENCE_COSINE ? 1 : 0;
+    st = run_captured(ctx, key, (P->flags & EDAA_FLAG_GRAPH) != 0, [&](hipStream_t s, long long* nl) {
+        return enqueue_ragged(groups, jobs_dev, T, K1, K2, cosine, s, nl);
+    });
+    if (st != EDAA_OK) return st;
+    bool any = false;
+    for (int k = 0; k < n; ++k)
+        if (images[k].loss_trace) {
+            EDAA_HIP(ctx, hipMemcpyAsync(images[k].loss_trace, rbs[k].s.trace, sizeof(double) * (T + 1),
+                                         hipMemcpyDeviceToHost, ctx->stream));
+            any = true;
+        }
+    if (any) EDAA_HIP(ctx, hipStreamSynchronize(ctx->stream));
     return EDAA_OK;
 }
 
@@ -573,19 +761,12 @@ edaa_status edaa_fit_ragged(edaa_ctx* ctx, int n_images, const edaa_image_desc* 
         if ((st = check_shape(d.L, d.N, d.p, 1)) != EDAA_OK) return st;
         EDAA_REQUIRE(d.X && d.A && d.B, "image %d: X, A and B must not be null", k);
         EDAA_REQUIRE(params->eta1 > 0.0 || (isfinite(d.gamma) && d.gamma > 0.0), "image %d: gamma must be > 0", k);
+        for (int kind = 0; kind < 3; ++kind)
+            if (pass_lds_bytes(d.p, 1, d.L, kind) > kMaxLdsBytes)
+                return fail(EDAA_EUNSUPPORTED, "image %d: L=%d with p=%d needs %zu bytes of LDS (limit %zu)", k,
+                            d.L, d.p, pass_lds_bytes(d.p, 1, d.L, kind), kMaxLdsBytes);
     }
-    long long launches = 0;
-    for (int k = 0; k < n_images; ++k) {
-        const edaa_image_desc& d = images[k];
-        const double gamma = d.gamma;
-        const uint64_t seed = d.seed;
-        st = run_batch(ctx, d.X, d.L, d.N, d.p, params, 1, &seed, &gamma, nullptr, nullptr, d.A, d.B, d.E,
-                       d.loss_trace, nullptr, nullptr, nullptr);
-        if (st != EDAA_OK) return st;
-        launches += ctx->last_launches;
-    }
-    ctx->last_launches = launches;
-    return EDAA_OK;
+    return run_ragged(ctx, n_images, images, params);
 }
 
 namespace {

@@ -72,6 +72,39 @@ struct RunInit {
     double eta1, eta2;       // > 0: overrides
 };
 
+// One image of a ragged batch (single run, R = 1): its geometry, state,
+// start values and outputs.  Multi-image launches read a table of these in
+// device memory and a map from workgroup to (image, workgroup within the
+// image), so one launch serves every image of a group of equal p.
+struct ImageJob {
+    Geom g;
+    State s;
+    RunInit ri;
+    float* B_out;       // device [N][p]
+    float* E_out;       // device [L][p] or null
+};
+
+// Multi-image launch maps; per image: kMapPass: npg workgroups; kMapRows:
+// L (one per band); kMapOne: 1; kMapElem: kElemBlocks.
+enum MultiMap { kMapPass = 0, kMapRows = 1, kMapOne = 2, kMapElem = 3, kMapKinds = 4 };
+constexpr int kElemBlocks = 32;
+enum MultiKernel {
+    kMultiPrep = 0,        // zero E, W, X A^T, E (f64); A = 1/p            (kMapElem)
+    kMultiBpassInit,       // B-pass from the seeded start values         (kMapPass)
+    kMultiBpassStep,       // B-step pass                                 (kMapPass)
+    kMultiRedB,            // column statistics, E, W (arg: need_w)       (kMapRows)
+    kMultiEta,             // step sizes                                  (kMapOne)
+    kMultiApass,           // A-pass (arg: K1)                            (kMapPass)
+    kMultiRedAA,           // A A^T and the objective (arg: t)            (kMapOne)
+    kMultiRedA,            // X A^T and W (arg: t)                        (kMapRows)
+    kMultiClose,           // closing pass                                (kMapPass)
+    kMultiCloseReduce,     // final objective and l1 fit                  (kMapOne)
+    kMultiFinal,           // B and E outputs, coherence (arg: cosine)    (kMapElem)
+};
+// Enqueue one multi-image kernel for the images of one p (all R = 1).
+hipError_t launch_multi(int kernel, int p, const ImageJob* jobs, const int2* map, int nblocks, size_t lds_bytes,
+                        int arg, hipStream_t st);
+
 // Launchers (edaa_kernels.hip).  All enqueue on `st` and return the HIP error
 // of the last launch.
 hipError_t launch_fill(float* dst, size_t n, float value, hipStream_t st);
@@ -119,6 +152,9 @@ int grad_blocks(int N);
 
 // Dynamic LDS bytes of a pass kernel (kind 0: A-pass, 1: B-pass, 2: closing).
 size_t pass_lds_bytes(int PP, int R, int L, int kind);
+// Dynamic LDS bytes the launchers give a pass kernel for geometry g (with its
+// double-buffer and operand-pitch choices); kind as above.
+size_t launch_lds_bytes(const Geom& g, int kind);
 constexpr size_t kMaxLdsBytes = 160 * 1024;
 
 // Geometry helpers (edaa_kernels.hip).

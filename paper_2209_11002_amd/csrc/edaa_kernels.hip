@@ -182,8 +182,7 @@ __device__ __forceinline__ float uniform_u(uint64_t seed, int i, int j) {
 // the 8 XCDs (block b runs on XCD b % 8); all chunks of one pixel group are
 // placed on one XCD, at consecutive dispatch slots, so they share the X tiles
 // in that XCD's L2.
-__device__ __forceinline__ void wg_coords(const Geom& g, int& pg, int& c) {
-    const int b = blockIdx.x;
+__device__ __forceinline__ void wg_coords(const Geom& g, int b, int& pg, int& c) {
     if ((g.npg & 7) == 0) {
         const int xcd = b & 7, k = b >> 3;
         c = k % g.nqc;
@@ -279,7 +278,7 @@ struct Shape {
 
 // LDS layout of a pass kernel, in floats.  LP = L rounded up to 16.
 struct PassLds {
-    int xs, wt, f, ec, gs, ps, xx, pd, xs2, total;
+    int xs, wt, f, fg, ec, gs, ps, xx, pd, xs2, total;
 };
 // dbuf: a second X tile buffer, so that the next tile loads while the
 // current one is processed.
@@ -292,7 +291,8 @@ __host__ __device__ inline PassLds pass_lds(int PP, int R, int L, int dbuf, int 
     o.xs = 0;
     o.wt = o.xs + LP * kXS;                    // [64][WTS] or [QCP][kXS] weights / projection results
     o.f = o.wt + (kTile * WTS > QCP * kXS ? kTile * WTS : QCP * kXS);   // [QCP] rescale factors
-    o.ec = o.f + QCP;                          // [LP][ECS] projection operand chunk (E or W)
+    o.fg = o.f + QCP;                          // [QCP] factors of the tile's weights
+    o.ec = o.fg + QCP;                         // [LP][ECS] projection operand chunk (E or W)
     o.gs = o.ec + LP * ECS;                    // [R][PP][PP] Gram matrices (double, 2 floats each)
     o.gs = (o.gs + 1) & ~1;
     o.ps = o.gs + 2 * R * PP * PP;
@@ -317,16 +317,21 @@ __device__ __forceinline__ void interleave_loads() {
     if (NMFMA > 4) __builtin_amdgcn_sched_group_barrier(0x008, NMFMA - 4, 0);
 }
 
-// V += X_tile Wt on the matrix cores.  Wave w owns the row blocks
+// V += X_tile Wt on the matrix cores: each tile's 64-pixel sums are formed
+// in float32 by the MFMAs and folded into float64 running sums, so that the
+// partial of a workgroup carries no error that grows with its tile count
+// (W = E A A^T - X A^T cancels and would amplify it).  Wave w owns the row blocks
 // rb = w + 4 j (16 bands each) and every column block; with SCALE the
 // running accumulation of column q is first multiplied by F[q].  The B
 // operands (Wt, 64 x QCP) are loaded once per tile and reused for every row
 // block; the optional Gram accumulation Wt^T Wt reuses them as well.
 // QMAJOR: the weights are stored column-major, Wt[q * kXS + pixel].
+// With SCALE the running sums of column q are first multiplied by F[q] and
+// the tile's sums by G[q].
 template <int NCB, int NRBW, int WTS, bool SCALE, int NGBW, bool QMAJOR = false>
-__device__ __forceinline__ void mfma_accumulate(f4 (&acc)[NRBW][NCB], f4 (&gram)[NGBW], bool do_gram,
-                                                const float* Xs, const float* Wt, const float* F, int nrb, int w,
-                                                int lane) {
+__device__ __forceinline__ void mfma_accumulate(d4 (&acc)[NRBW][NCB], d4 (&gram)[NGBW], bool do_gram,
+                                                const float* Xs, const float* Wt, const float* F, const float* G,
+                                                int nrb, int w, int lane) {
     const int m = lane & 15, kk = lane >> 4;
     float bop[16][NCB];
 #pragma unroll
@@ -342,23 +347,25 @@ __device__ __forceinline__ void mfma_accumulate(f4 (&acc)[NRBW][NCB], f4 (&gram)
 #pragma unroll
         for (int k = 0; k < 16; ++k) xa[k] = xr[4 * k];
     }
-    float fs[NCB];
+    float fs[NCB], gs[NCB];
     if (SCALE) {
 #pragma unroll
-        for (int cb = 0; cb < NCB; ++cb) fs[cb] = F[16 * cb + m];
+        for (int cb = 0; cb < NCB; ++cb) {
+            fs[cb] = F[16 * cb + m];
+            gs[cb] = G[16 * cb + m];
+        }
     }
 #pragma unroll
     for (int j = 0; j < NRBW; ++j) {
         const int rb = w + 4 * j;
         if (rb < nrb) {
-            if (SCALE) {
+            f4 t[NCB];
 #pragma unroll
-                for (int cb = 0; cb < NCB; ++cb) acc[j][cb] *= fs[cb];
-            }
+            for (int cb = 0; cb < NCB; ++cb) t[cb] = f4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
             for (int k = 0; k < 16; ++k) {
 #pragma unroll
-                for (int cb = 0; cb < NCB; ++cb) acc[j][cb] = mfma16(xa[k], bop[k][cb], acc[j][cb]);
+                for (int cb = 0; cb < NCB; ++cb) t[cb] = mfma16(xa[k], bop[k][cb], t[cb]);
             }
             float xn[16];
             if (j + 1 < NRBW) {
@@ -371,6 +378,14 @@ __device__ __forceinline__ void mfma_accumulate(f4 (&acc)[NRBW][NCB], f4 (&gram)
 #pragma unroll
                 for (int k = 0; k < 16; ++k) xa[k] = xn[k];
             }
+            // fold the tile's sums into the float64 running sums (rescaled
+            // first with SCALE)
+#pragma unroll
+            for (int cb = 0; cb < NCB; ++cb)
+#pragma unroll
+                for (int v = 0; v < 4; ++v)
+                    acc[j][cb][v] = SCALE ? fma(acc[j][cb][v], (double)fs[cb], (double)t[cb][v] * (double)gs[cb])
+                                          : acc[j][cb][v] + (double)t[cb][v];
         }
     }
     if (do_gram) {
@@ -379,6 +394,7 @@ __device__ __forceinline__ void mfma_accumulate(f4 (&acc)[NRBW][NCB], f4 (&gram)
             const int gb = w + 4 * gi;                 // (qb, qb) for even gb, (qb, qb+1) for odd
             if (gb < 2 * NCB - 1) {
                 const int q1 = gb >> 1, q2 = q1 + (gb & 1);
+                f4 tg = f4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
                 for (int k = 0; k < 16; ++k) {
                     float a = 0.f, b = 0.f;
@@ -387,8 +403,10 @@ __device__ __forceinline__ void mfma_accumulate(f4 (&acc)[NRBW][NCB], f4 (&gram)
                         if (cb == q1) a = bop[k][cb];
                         if (cb == q2) b = bop[k][cb];
                     }
-                    gram[gi] = mfma16(a, b, gram[gi]);
+                    tg = mfma16(a, b, tg);
                 }
+#pragma unroll
+                for (int v = 0; v < 4; ++v) gram[gi][v] += (double)tg[v];
             }
         }
     }
@@ -396,7 +414,7 @@ __device__ __forceinline__ void mfma_accumulate(f4 (&acc)[NRBW][NCB], f4 (&gram)
 
 // Write the accumulated V (rows < L, columns < QC) of this workgroup.
 template <int NCB, int NRBW, int QC>
-__device__ __forceinline__ void store_acc(const f4 (&acc)[NRBW][NCB], float* Vp, int L, int nrb, int w, int lane) {
+__device__ __forceinline__ void store_acc(const d4 (&acc)[NRBW][NCB], float* Vp, int L, int nrb, int w, int lane) {
     const int m = lane & 15, kk = lane >> 4;
 #pragma unroll
     for (int j = 0; j < NRBW; ++j) {
@@ -408,7 +426,7 @@ __device__ __forceinline__ void store_acc(const f4 (&acc)[NRBW][NCB], float* Vp,
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
                     const int l = 16 * rb + 4 * kk + v;
-                    if (l < L && q < QC) Vp[(size_t)l * QC + q] = acc[j][cb][v];
+                    if (l < L && q < QC) Vp[(size_t)l * QC + q] = (float)acc[j][cb][v];
                 }
             }
     }
@@ -553,7 +571,7 @@ __device__ __forceinline__ void stage_chunk(const float* __restrict__ U, int Qp,
 // P = E^T x, K1 A-steps, write A, accumulate X A^T and A A^T partials.
 // --------------------------------------------------------------------------
 template <int PP, int R>
-__global__ __launch_bounds__(kThreads, 1) void k_apass(Geom g, State s, const float* __restrict__ E, int K1) {
+__device__ __forceinline__ void apass_body(const Geom& g, const State& s, int bid, const float* __restrict__ E, int K1) {
     using S = Shape<PP, R>;
     constexpr int QC = S::QC, QCP = S::QCP, NCB = S::NCB, WTS = S::WTS, RW = S::RW, NRBW = S::NRBW;
     const int ECS = g.ecs;
@@ -568,7 +586,7 @@ __global__ __launch_bounds__(kThreads, 1) void k_apass(Geom g, State s, const fl
     float* Plo = smem + lo.pd;
 
     int pg, c;
-    wg_coords(g, pg, c);
+    wg_coords(g, bid, pg, c);
     const int tid = threadIdx.x, lane = tid & 63;
     const int w = uniform_int(tid >> 6);
     const int L = g.L, N = g.N, LP = (L + 15) & ~15, nrb = LP / 16;
@@ -595,13 +613,13 @@ __global__ __launch_bounds__(kThreads, 1) void k_apass(Geom g, State s, const fl
     }
     for (int e = tid; e < kTile * WTS; e += kThreads) Wt[e] = 0.f;
 
-    f4 acc[NRBW][NCB], gram[NGBW];
+    d4 acc[NRBW][NCB], gram[NGBW];
 #pragma unroll
     for (int j = 0; j < NRBW; ++j)
 #pragma unroll
-        for (int cb = 0; cb < NCB; ++cb) acc[j][cb] = f4{0.f, 0.f, 0.f, 0.f};
+        for (int cb = 0; cb < NCB; ++cb) acc[j][cb] = d4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-    for (int j = 0; j < NGBW; ++j) gram[j] = f4{0.f, 0.f, 0.f, 0.f};
+    for (int j = 0; j < NGBW; ++j) gram[j] = d4{0.0, 0.0, 0.0, 0.0};
     double lacc[RW];
 #pragma unroll
     for (int r = 0; r < RW; ++r) lacc[r] = 0.0;
@@ -689,7 +707,7 @@ __global__ __launch_bounds__(kThreads, 1) void k_apass(Geom g, State s, const fl
             }
         }
         lds_barrier();
-        mfma_accumulate<NCB, NRBW, WTS, false, NGBW>(acc, gram, true, Xs, Wt, nullptr, nrb, w, lane);
+        mfma_accumulate<NCB, NRBW, WTS, false, NGBW>(acc, gram, true, Xs, Wt, nullptr, nullptr, nrb, w, lane);
         if (nt < g.ntiles && dma && !g.dbuf) {
             lds_barrier();                        // single buffer: reload after every reader
             dma_tile((const float*)s.X, L, N, nt, Xs);
@@ -713,8 +731,8 @@ __global__ __launch_bounds__(kThreads, 1) void k_apass(Geom g, State s, const fl
                     const int q1 = 16 * qb1 + 4 * kk + v, q2 = 16 * qb2 + m16;
                     if (q1 < QC && q2 < QC && q1 / PP == q2 / PP) {
                         const int r = q1 / PP, j = q1 % PP, k = q2 % PP;
-                        AAp[r * PP * PP + j * PP + k] = gram[gi][v];
-                        if (qb1 != qb2) AAp[r * PP * PP + k * PP + j] = gram[gi][v];
+                        AAp[r * PP * PP + j * PP + k] = (float)gram[gi][v];
+                        if (qb1 != qb2) AAp[r * PP * PP + k * PP + j] = (float)gram[gi][v];
                     }
                 }
             }
@@ -727,6 +745,18 @@ __global__ __launch_bounds__(kThreads, 1) void k_apass(Geom g, State s, const fl
         const double tot = wave_sum(lacc[k]);
         if (lane == 0 && m < g.M) s.lpart[(size_t)pg * g.M + m] = tot;
     }
+}
+
+template <int PP, int R>
+__global__ __launch_bounds__(kThreads, 1) void k_apass(Geom g, State s, const float* __restrict__ E, int K1) {
+    apass_body<PP, R>(g, s, blockIdx.x, E, K1);
+}
+template <int PP, int R>
+__global__ __launch_bounds__(kThreads, 1) void k_apass_multi(const ImageJob* __restrict__ jobs, const int2* __restrict__ map,
+                                                             int K1) {
+    const int2 jl = map[blockIdx.x];
+    const ImageJob& J = jobs[jl.x];
+    apass_body<PP, R>(J.g, J.s, jl.y, J.s.E, K1);
 }
 
 // --------------------------------------------------------------------------
@@ -743,8 +773,8 @@ __global__ __launch_bounds__(kThreads, 1) void k_apass(Geom g, State s, const fl
 // 16-pixel segments are read and written as float4 without bounds checks.
 // --------------------------------------------------------------------------
 template <int PP, int R, bool STEP>
-__global__ __launch_bounds__(kThreads, 1) void k_bpass(Geom g, State s, const float* __restrict__ W, int mode,
-                                                       RunInit ri) {
+__device__ __forceinline__ void bpass_body(const Geom& g, const State& s, int bid, const float* __restrict__ W, int mode,
+                                           const RunInit& ri) {
     using S = Shape<PP, R>;
     constexpr int QC = S::QC, QCP = S::QCP, NCB = S::NCB, WTS = S::WTS, NRBW = S::NRBW;
     const int ECS = g.ecs;
@@ -753,11 +783,12 @@ __global__ __launch_bounds__(kThreads, 1) void k_bpass(Geom g, State s, const fl
     const PassLds lo = pass_lds(PP, R, g.L, g.dbuf, g.ecs);
     float* Wq = smem + lo.wt;                      // [QCP][kXS]
     float* F = smem + lo.f;
+    float* FG = smem + lo.fg;
     float* Ec = smem + lo.ec;
     const int xo[2] = {lo.xs, g.dbuf ? lo.xs2 : lo.xs};
 
     int pg, c;
-    wg_coords(g, pg, c);
+    wg_coords(g, bid, pg, c);
     const int tid = threadIdx.x, lane = tid & 63;
     const int w = uniform_int(tid >> 6);
     const int L = g.L, N = g.N, LP = (L + 15) & ~15, nrb = LP / 16;
@@ -769,7 +800,7 @@ __global__ __launch_bounds__(kThreads, 1) void k_bpass(Geom g, State s, const fl
         smem[xo[1] + L * kXS + e] = 0.f;
     }
     for (int e = tid; e < QCP * kXS; e += kThreads) Wq[e] = 0.f;
-    for (int e = tid; e < QCP; e += kThreads) F[e] = 0.f;
+    for (int e = tid; e < QCP; e += kThreads) F[e] = FG[e] = 0.f;
     if (STEP) stage_chunk<QC, QCP>(W, g.Qp, col0, L, LP, Ec, ECS);
 
     // this thread's softmax column and pixel segment
@@ -778,17 +809,18 @@ __global__ __launch_bounds__(kThreads, 1) void k_bpass(Geom g, State s, const fl
     const bool qin = sq < QC;                      // a column of the chunk
     const bool cok = qin && sm < g.M;              // ... of an existing run
     float* bcol = s.Bst + (size_t)(cok ? col0 + sq : 0) * Np + 16 * sub;
-    float mrun = -INFINITY, srun = 0.f, lzc = 0.f, eta2 = 0.f;
+    float mrun = -INFINITY, lzc = 0.f, eta2 = 0.f;
+    double srun = 0.0;                             // float64: it runs over every tile of the workgroup
     if (STEP && cok) {
         lzc = -s.colm[col0 + sq] - logf(s.cols[col0 + sq]);
         eta2 = s.eta[2 * sm + 1];
     }
 
-    f4 acc[NRBW][NCB], gdummy[1];
+    d4 acc[NRBW][NCB], gdummy[1];
 #pragma unroll
     for (int jb = 0; jb < NRBW; ++jb)
 #pragma unroll
-        for (int cb = 0; cb < NCB; ++cb) acc[jb][cb] = f4{0.f, 0.f, 0.f, 0.f};
+        for (int cb = 0; cb < NCB; ++cb) acc[jb][cb] = d4{0.0, 0.0, 0.0, 0.0};
 
     // Pipeline: the X tile (direct-to-LDS loads) and this thread's B segment
     // and shift (registers) of tile t + npg are requested while tile t is
@@ -861,17 +893,23 @@ __global__ __launch_bounds__(kThreads, 1) void k_bpass(Geom g, State s, const fl
             }
             mx = fmaxf(mx, dpp<0xB1>(mx));             // the quad of this column
             mx = fmaxf(mx, dpp<0x4E>(mx));
+            // The tile's weights are stored relative to the tile's own max
+            // (its largest weight is 1, so none underflows for being far
+            // below a larger tile of this workgroup); the running sums are
+            // relative to the running max: factors f (old sums) and fg
+            // (this tile).
             const float mnew = fmaxf(mrun, mx);
             const float f = (mrun == -INFINITY) ? 0.f : fast_exp(mrun - mnew);
+            const float fg = (mx == -INFINITY) ? 0.f : fast_exp(mx - mnew);
             float wv[16], sum = 0.f;
 #pragma unroll
             for (int i = 0; i < 16; ++i) {
-                wv[i] = (v[i] == -INFINITY) ? 0.f : fast_exp(v[i] - mnew);
+                wv[i] = (v[i] == -INFINITY) ? 0.f : fast_exp(v[i] - mx);
                 sum += wv[i];
             }
             sum += dpp<0xB1>(sum);
             sum += dpp<0x4E>(sum);
-            srun = srun * f + sum;
+            srun = fma(srun, (double)f, (double)sum * (double)fg);
             mrun = mnew;
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
@@ -881,11 +919,12 @@ __global__ __launch_bounds__(kThreads, 1) void k_bpass(Geom g, State s, const fl
             }
             if (sub == 0) {
                 F[sq] = f;
-                if (cok) s.tshift[(size_t)tile * g.Qp + col0 + sq] = mnew;
+                FG[sq] = fg;
+                if (cok) s.tshift[(size_t)tile * g.Qp + col0 + sq] = mx;
             }
         }
         lds_barrier();
-        mfma_accumulate<NCB, NRBW, WTS, true, 1, true>(acc, gdummy, false, Xs, Wq, F, nrb, w, lane);
+        mfma_accumulate<NCB, NRBW, WTS, true, 1, true>(acc, gdummy, false, Xs, Wq, F, FG, nrb, w, lane);
         if (nt < g.ntiles && dma && !g.dbuf) {
             lds_barrier();                        // single buffer: reload after every reader
             dma_tile((const float*)s.X, L, N, nt, Xs);
@@ -896,8 +935,21 @@ __global__ __launch_bounds__(kThreads, 1) void k_bpass(Geom g, State s, const fl
     store_acc<NCB, NRBW, QC>(acc, s.Vpart + wgi * (size_t)L * QC, L, nrb, w, lane);
     if (qin && sub == 0) {
         s.mpart[(size_t)pg * g.Qp + col0 + sq] = cok ? mrun : -INFINITY;
-        s.spart[(size_t)pg * g.Qp + col0 + sq] = cok ? srun : 0.f;
+        s.spart[(size_t)pg * g.Qp + col0 + sq] = cok ? (float)srun : 0.f;
     }
+}
+
+template <int PP, int R, bool STEP>
+__global__ __launch_bounds__(kThreads, 1) void k_bpass(Geom g, State s, const float* __restrict__ W, int mode,
+                                                       RunInit ri) {
+    bpass_body<PP, R, STEP>(g, s, blockIdx.x, W, mode, ri);
+}
+template <int PP, int R, bool STEP>
+__global__ __launch_bounds__(kThreads, 1) void k_bpass_multi(const ImageJob* __restrict__ jobs,
+                                                             const int2* __restrict__ map, int mode) {
+    const int2 jl = map[blockIdx.x];
+    const ImageJob& J = jobs[jl.x];
+    bpass_body<PP, R, STEP>(J.g, J.s, jl.y, J.s.W, mode, J.ri);
 }
 
 // --------------------------------------------------------------------------
@@ -905,7 +957,7 @@ __global__ __launch_bounds__(kThreads, 1) void k_bpass(Geom g, State s, const fl
 // the per-band residual (the l1 fit needs it band by band).
 // --------------------------------------------------------------------------
 template <int PP, int R>
-__global__ __launch_bounds__(kThreads, 2) void k_close(Geom g, State s, const float* __restrict__ E) {
+__device__ __forceinline__ void close_body(const Geom& g, const State& s, int bid, const float* __restrict__ E) {
     constexpr int QC = PP * R;
     constexpr int RW = (R == 1) ? 1 : R / 4;
     extern __shared__ float smem[];
@@ -913,7 +965,7 @@ __global__ __launch_bounds__(kThreads, 2) void k_close(Geom g, State s, const fl
     float* Ls = Xs + g.L * kXS;                        // R == 1: [2][4][kTile]
 
     int pg, c;
-    wg_coords(g, pg, c);
+    wg_coords(g, bid, pg, c);
     const int tid = threadIdx.x, lane = tid & 63;
     const int w = uniform_int(tid >> 6);
     const int L = g.L, N = g.N, col0 = c * QC;
@@ -1002,6 +1054,18 @@ __global__ __launch_bounds__(kThreads, 2) void k_close(Geom g, State s, const fl
     }
 }
 
+template <int PP, int R>
+__global__ __launch_bounds__(kThreads, 2) void k_close(Geom g, State s, const float* __restrict__ E) {
+    close_body<PP, R>(g, s, blockIdx.x, E);
+}
+template <int PP, int R>
+__global__ __launch_bounds__(kThreads, 2) void k_close_multi(const ImageJob* __restrict__ jobs,
+                                                             const int2* __restrict__ map) {
+    const int2 jl = map[blockIdx.x];
+    const ImageJob& J = jobs[jl.x];
+    close_body<PP, R>(J.g, J.s, jl.y, J.s.E);
+}
+
 
 // --------------------------------------------------------------------------
 // Reductions of the per-workgroup partials, in a fixed order.  Grid:
@@ -1036,11 +1100,11 @@ __device__ __forceinline__ void sliced_sum(const float* __restrict__ src, size_t
 // A A^T of run m (blockIdx.x) and its objective at the incoming state
 // (trace[t]), each summed over the npg workgroup partials in fixed slices.
 template <int PP, int R>
-__global__ __launch_bounds__(kThreads) void k_reduce_aa(Geom g, State s, int t) {
+__device__ __forceinline__ void reduce_aa_body(const Geom& g, const State& s, int bx, int t) {
     constexpr int P2 = PP * PP;
     __shared__ double red[kThreads];
     __shared__ double out[P2 > 1 ? P2 : 1];
-    const int m = blockIdx.x, tid = threadIdx.x;
+    const int m = bx, tid = threadIdx.x;
     sliced_sum(s.AApart + (size_t)m * P2, (size_t)g.nqc * R * P2, g.npg, P2, red, out);   // [npg][nqc R][p][p]
     if (tid < P2) s.AAtd[(size_t)m * P2 + tid] = out[tid];
     double acc = 0.0;
@@ -1054,13 +1118,18 @@ __global__ __launch_bounds__(kThreads) void k_reduce_aa(Geom g, State s, int t) 
     }
 }
 
+template <int PP, int R>
+__global__ __launch_bounds__(kThreads) void k_reduce_aa(Geom g, State s, int t) {
+    reduce_aa_body<PP, R>(g, s, blockIdx.x, t);
+}
+
 // Row l of chunk c: X A^T[l][:] and W[l][:] = E[l][:] A A^T - X A^T[l][:].
 template <int PP, int R>
-__global__ __launch_bounds__(kThreads) void k_reduce_a(Geom g, State s, int t) {
+__device__ __forceinline__ void reduce_a_body(const Geom& g, const State& s, int bx, int by, int t) {
     constexpr int QC = PP * R;
     __shared__ double red[kThreads];
     __shared__ double xa[QC];
-    const int l = blockIdx.x, c = blockIdx.y, tid = threadIdx.x;
+    const int l = bx, c = by, tid = threadIdx.x;
     const int col0 = c * QC, L = g.L;
     (void)t;
     sliced_sum(s.Vpart + ((size_t)c * L + l) * QC, (size_t)g.nqc * L * QC, g.npg, QC, red, xa);
@@ -1081,16 +1150,37 @@ __global__ __launch_bounds__(kThreads) void k_reduce_a(Geom g, State s, int t) {
     }
 }
 
+template <int PP, int R>
+__global__ __launch_bounds__(kThreads) void k_reduce_a(Geom g, State s, int t) {
+    reduce_a_body<PP, R>(g, s, blockIdx.x, blockIdx.y, t);
+}
+// Single-run images (R = 1, one chunk): the objective and A A^T of the run
+// (one block per image), then, in a second launch since W needs A A^T, the
+// rows of X A^T and W (L blocks per image).
+template <int PP>
+__global__ __launch_bounds__(kThreads) void k_reduce_aa_multi(const ImageJob* __restrict__ jobs,
+                                                              const int2* __restrict__ map, int t) {
+    const ImageJob& J = jobs[map[blockIdx.x].x];
+    reduce_aa_body<PP, 1>(J.g, J.s, 0, t);
+}
+template <int PP>
+__global__ __launch_bounds__(kThreads) void k_reduce_a_multi(const ImageJob* __restrict__ jobs,
+                                                             const int2* __restrict__ map, int t) {
+    const int2 jl = map[blockIdx.x];
+    const ImageJob& J = jobs[jl.x];
+    reduce_a_body<PP, 1>(J.g, J.s, jl.y, 0, t);
+}
+
 // Row l of chunk c after a B-pass: column statistics (max, sum relative to
 // the max) of the softmax over all N pixels, E[l][:] = X B_new, and W for the
 // next B-step.
 template <int PP, int R>
-__global__ __launch_bounds__(kThreads) void k_reduce_b(Geom g, State s, int need_w) {
+__device__ __forceinline__ void reduce_b_body(const Geom& g, const State& s, int bx, int by, int need_w) {
     constexpr int QC = PP * R;
     __shared__ double red[kThreads];
     __shared__ float Ms[QC];
     __shared__ double Ss[QC], Ev[QC];
-    const int l = blockIdx.x, c = blockIdx.y, tid = threadIdx.x;
+    const int l = bx, c = by, tid = threadIdx.x;
     const int col0 = c * QC, L = g.L;
     const int S = kThreads / QC, o = tid % QC, sl = tid / QC;
     const bool act = sl < S;
@@ -1154,8 +1244,20 @@ __global__ __launch_bounds__(kThreads) void k_reduce_b(Geom g, State s, int need
     }
 }
 
-__global__ void k_reduce_close(Geom g, State s) {
-    for (int m = threadIdx.x + blockIdx.x * blockDim.x; m < g.M; m += blockDim.x * gridDim.x) {
+template <int PP, int R>
+__global__ __launch_bounds__(kThreads) void k_reduce_b(Geom g, State s, int need_w) {
+    reduce_b_body<PP, R>(g, s, blockIdx.x, blockIdx.y, need_w);
+}
+template <int PP>
+__global__ __launch_bounds__(kThreads) void k_reduce_b_multi(const ImageJob* __restrict__ jobs,
+                                                             const int2* __restrict__ map, int need_w) {
+    const int2 jl = map[blockIdx.x];
+    const ImageJob& J = jobs[jl.x];
+    reduce_b_body<PP, 1>(J.g, J.s, jl.y, 0, need_w);
+}
+
+__device__ __forceinline__ void reduce_close_body(const Geom& g, const State& s, int first, int stride) {
+    for (int m = first; m < g.M; m += stride) {
         double la = 0.0, fa = 0.0;
         for (int pg = 0; pg < g.npg; ++pg) {
             la += s.lpart[(size_t)pg * g.M + m];
@@ -1164,6 +1266,10 @@ __global__ void k_reduce_close(Geom g, State s) {
         s.trace[(size_t)m * (s.T + 1) + s.T] = 0.5 * la;
         s.fit[m] = fa;
     }
+}
+
+__global__ void k_reduce_close(Geom g, State s) {
+    reduce_close_body(g, s, threadIdx.x + blockIdx.x * blockDim.x, blockDim.x * gridDim.x);
 }
 
 // --------------------------------------------------------------------------
@@ -1204,9 +1310,9 @@ __device__ double jacobi_max_eig(double* a, int n) {
 }
 
 template <int PP>
-__global__ __launch_bounds__(kThreads) void k_eta(Geom g, State s, RunInit ri) {
+__device__ __forceinline__ void eta_body(const Geom& g, const State& s, int bx, const RunInit& ri) {
     __shared__ double Gd[PP * PP];
-    const int m = blockIdx.x, tid = threadIdx.x;
+    const int m = bx, tid = threadIdx.x;
     const int c = m / g.R, col0 = c * g.QC + (m % g.R) * PP;
     for (int e = tid; e < PP * PP; e += kThreads) {
         const int j = e / PP, k = e % PP;
@@ -1227,15 +1333,20 @@ __global__ __launch_bounds__(kThreads) void k_eta(Geom g, State s, RunInit ri) {
     }
 }
 
+template <int PP>
+__global__ __launch_bounds__(kThreads) void k_eta(Geom g, State s, RunInit ri) {
+    eta_body<PP>(g, s, blockIdx.x, ri);
+}
+
 // --------------------------------------------------------------------------
 // Outputs: normalised B in [M][N][p], E in [M][L][p], coherence per run.
 // --------------------------------------------------------------------------
 template <int PP>
-__global__ __launch_bounds__(kThreads) void k_final_B(Geom g, State s, float* B_out) {
-    const int m = blockIdx.y;
+__device__ __forceinline__ void final_B_body(const Geom& g, const State& s, int bx, int by, int nbx, float* B_out) {
+    const int m = by;
     const size_t n = (size_t)g.N * PP;
     const int c = m / g.R, base = c * g.QC + (m % g.R) * PP;
-    for (size_t e = (size_t)blockIdx.x * kThreads + threadIdx.x; e < n; e += (size_t)gridDim.x * kThreads) {
+    for (size_t e = (size_t)bx * kThreads + threadIdx.x; e < n; e += (size_t)nbx * kThreads) {
         const int pix = (int)(e / PP), j = (int)(e % PP);
         const int qp = base + j, tile = pix / kTile;
         const float b = s.Bst[(size_t)(m * PP + j) * ((size_t)g.ntiles * kTile) + pix];
@@ -1244,9 +1355,14 @@ __global__ __launch_bounds__(kThreads) void k_final_B(Geom g, State s, float* B_
 }
 
 template <int PP>
-__global__ __launch_bounds__(kThreads) void k_final_E(Geom g, State s, float* E_out, int cosine) {
+__global__ __launch_bounds__(kThreads) void k_final_B(Geom g, State s, float* B_out) {
+    final_B_body<PP>(g, s, blockIdx.x, blockIdx.y, gridDim.x, B_out);
+}
+
+template <int PP>
+__device__ __forceinline__ void final_E_body(const Geom& g, const State& s, int bx, float* E_out, int cosine) {
     __shared__ double Gd[PP * PP];
-    const int m = blockIdx.x, tid = threadIdx.x;
+    const int m = bx, tid = threadIdx.x;
     const int c = m / g.R, base = c * g.QC + (m % g.R) * PP;
     if (E_out)
         for (int e = tid; e < g.L * PP; e += kThreads) {
@@ -1275,6 +1391,54 @@ __global__ __launch_bounds__(kThreads) void k_final_E(Geom g, State s, float* E_
             }
         s.mu[m] = mu;
     }
+}
+
+template <int PP>
+__global__ __launch_bounds__(kThreads) void k_final_E(Geom g, State s, float* E_out, int cosine) {
+    final_E_body<PP>(g, s, blockIdx.x, E_out, cosine);
+}
+
+// Multi-image helpers (single-run images of one p).
+template <int PP>
+__global__ __launch_bounds__(kThreads) void k_prep_multi(const ImageJob* __restrict__ jobs,
+                                                         const int2* __restrict__ map) {
+    const int2 jl = map[blockIdx.x];
+    const ImageJob& J = jobs[jl.x];
+    const Geom& g = J.g;
+    const State& s = J.s;
+    const size_t i0 = (size_t)jl.y * kThreads + threadIdx.x, st = (size_t)kElemBlocks * kThreads;
+    const size_t nf = (size_t)(g.L + kPadRows) * g.Qp, nd = (size_t)g.L * g.Qp;
+    for (size_t i = i0; i < nf; i += st) {
+        s.E[i] = 0.f;
+        s.W[i] = 0.f;
+    }
+    for (size_t i = i0; i < nd; i += st) {
+        s.XAtd[i] = 0.0;
+        s.Ed[i] = 0.0;
+    }
+    const size_t na = (size_t)PP * g.N;
+    for (size_t i = i0; i < na; i += st) s.A[i] = 1.f / (float)PP;
+}
+
+template <int PP>
+__global__ __launch_bounds__(kThreads) void k_eta_multi(const ImageJob* __restrict__ jobs, const int2* __restrict__ map) {
+    const ImageJob& J = jobs[map[blockIdx.x].x];
+    eta_body<PP>(J.g, J.s, 0, J.ri);
+}
+
+__global__ __launch_bounds__(kThreads) void k_reduce_close_multi(const ImageJob* __restrict__ jobs,
+                                                                 const int2* __restrict__ map) {
+    const ImageJob& J = jobs[map[blockIdx.x].x];
+    reduce_close_body(J.g, J.s, threadIdx.x, kThreads);
+}
+
+template <int PP>
+__global__ __launch_bounds__(kThreads) void k_final_multi(const ImageJob* __restrict__ jobs,
+                                                          const int2* __restrict__ map, int cosine) {
+    const int2 jl = map[blockIdx.x];
+    const ImageJob& J = jobs[jl.x];
+    final_B_body<PP>(J.g, J.s, jl.y, 0, kElemBlocks, J.B_out);
+    if (jl.y == 0) final_E_body<PP>(J.g, J.s, 0, J.E_out, cosine);
 }
 
 __global__ void k_fill(float* __restrict__ dst, size_t n, float v) {
@@ -1311,6 +1475,11 @@ __global__ __launch_bounds__(kThreads) void k_normalize(const float* __restrict_
 // Host-side dispatch over the (p, runs-per-chunk) instantiations.
 // --------------------------------------------------------------------------
 }  // namespace
+
+size_t launch_lds_bytes(const Geom& g, int kind) {
+    if (kind == 2) return pass_lds_bytes(g.p, g.R, g.L, 2);
+    return (size_t)pass_lds(g.p, g.R, g.L, g.dbuf, g.ecs).total * sizeof(float);
+}
 
 size_t pass_lds_bytes(int PP, int R, int L, int kind) {
     if (kind == 2) return ((size_t)L * kXS + 8 * kTile) * sizeof(float);
@@ -1457,6 +1626,74 @@ Geom make_geom(int L, int N, int M, int p) {
         g.dbuf = 0; g.ecs = QCP + 1;
     }
     return g;
+}
+
+namespace {
+template <int PP>
+struct MultiKernels {
+    static hipError_t run(int kernel, const ImageJob* jobs, const int2* map, int nb, size_t lds, int arg,
+                          hipStream_t st) {
+        const dim3 grid(nb), block(kThreads);
+        switch (kernel) {
+            case kMultiPrep:
+                hipLaunchKernelGGL((k_prep_multi<PP>), grid, block, 0, st, jobs, map);
+                break;
+            case kMultiBpassInit:
+                set_max_lds((const void*)k_bpass_multi<PP, 1, false>, (int)lds);
+                hipLaunchKernelGGL((k_bpass_multi<PP, 1, false>), grid, block, lds, st, jobs, map, (int)kModeInitRng);
+                break;
+            case kMultiBpassStep:
+                set_max_lds((const void*)k_bpass_multi<PP, 1, true>, (int)lds);
+                hipLaunchKernelGGL((k_bpass_multi<PP, 1, true>), grid, block, lds, st, jobs, map, (int)kModeStep);
+                break;
+            case kMultiRedB:
+                hipLaunchKernelGGL((k_reduce_b_multi<PP>), grid, block, 0, st, jobs, map, arg);
+                break;
+            case kMultiEta:
+                hipLaunchKernelGGL((k_eta_multi<PP>), grid, block, 0, st, jobs, map);
+                break;
+            case kMultiApass:
+                set_max_lds((const void*)k_apass_multi<PP, 1>, (int)lds);
+                hipLaunchKernelGGL((k_apass_multi<PP, 1>), grid, block, lds, st, jobs, map, arg);
+                break;
+            case kMultiRedAA:
+                hipLaunchKernelGGL((k_reduce_aa_multi<PP>), grid, block, 0, st, jobs, map, arg);
+                break;
+            case kMultiRedA:
+                hipLaunchKernelGGL((k_reduce_a_multi<PP>), grid, block, 0, st, jobs, map, arg);
+                break;
+            case kMultiClose:
+                set_max_lds((const void*)k_close_multi<PP, 1>, (int)lds);
+                hipLaunchKernelGGL((k_close_multi<PP, 1>), grid, block, lds, st, jobs, map);
+                break;
+            case kMultiCloseReduce:
+                hipLaunchKernelGGL(k_reduce_close_multi, grid, block, 0, st, jobs, map);
+                break;
+            case kMultiFinal:
+                hipLaunchKernelGGL((k_final_multi<PP>), grid, block, 0, st, jobs, map, arg);
+                break;
+            default:
+                return hipErrorInvalidValue;
+        }
+        return hipGetLastError();
+    }
+};
+}  // namespace
+
+hipError_t launch_multi(int kernel, int p, const ImageJob* jobs, const int2* map, int nblocks, size_t lds_bytes,
+                        int arg, hipStream_t st) {
+    if (nblocks <= 0) return hipSuccess;
+    switch (p) {
+#define EDAA_MULTI_P(PPV) \
+    case PPV:             \
+        return MultiKernels<PPV>::run(kernel, jobs, map, nblocks, lds_bytes, arg, st);
+        EDAA_MULTI_P(1) EDAA_MULTI_P(2) EDAA_MULTI_P(3) EDAA_MULTI_P(4) EDAA_MULTI_P(5) EDAA_MULTI_P(6)
+        EDAA_MULTI_P(7) EDAA_MULTI_P(8) EDAA_MULTI_P(9) EDAA_MULTI_P(10) EDAA_MULTI_P(11) EDAA_MULTI_P(12)
+        EDAA_MULTI_P(13) EDAA_MULTI_P(14) EDAA_MULTI_P(15) EDAA_MULTI_P(16)
+#undef EDAA_MULTI_P
+        default:
+            return hipErrorInvalidValue;
+    }
 }
 
 hipError_t launch_fill(float* dst, size_t n, float value, hipStream_t st) {

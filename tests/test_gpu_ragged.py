@@ -1,0 +1,86 @@
+"""Ragged batch (single runs on images of different L, N, p, advanced
+together): every image must give exactly what a single-image fit gives (the
+multi-image launches run the same kernel bodies on the same geometry), and
+agree with the float64 oracle to the float32 tolerances."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import edaa as O
+from paper_2209_11002_amd import synth
+
+gpu = pytest.mark.gpu
+
+
+def _say(*a):
+    print("[case]", *a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def api():
+    if not torch.cuda.is_available():
+        pytest.skip("needs a GPU")
+    from paper_2209_11002_amd import api as A
+    return A
+
+
+# (L, N, p): two groups share p = 4, tails of 1..63 pixels, p from 1 to 16
+SHAPES = [(40, 333, 4), (57, 1000, 3), (31, 64, 1), (64, 777, 4), (20, 130, 16), (156, 2500, 6)]
+
+
+def _images(dtype=torch.float32):
+    out = []
+    for k, (L, N, p) in enumerate(SHAPES):
+        s = synth.small_case(seed=100 + k, L=L, N=N, p=min(p, 8))
+        Xn, _ = O.normalize_pixels(s.X)
+        Xt = torch.from_numpy(Xn.astype(np.float32)).to(dtype)
+        out.append((Xt.cuda().contiguous(), Xt.to(torch.float64).numpy(), p))
+    return out
+
+
+@gpu
+def test_ragged_equals_single_image_fits(api):
+    _say("ragged vs single fits:", SHAPES)
+    imgs = _images()
+    seeds = [11 * k + 1 for k in range(len(imgs))]
+    gammas = [0.5, 1.0, 2.0, 1.0, 0.25, 1.0]
+    rr = api.fit_ragged([x for x, _, _ in imgs], [p for _, _, p in imgs], seeds, gammas, T=12)
+    for k, ((Xg, _, p), r) in enumerate(zip(imgs, rr)):
+        single = api.fit(Xg, p, T=12, gamma=gammas[k], seed=seeds[k])
+        assert torch.equal(r["A"], single["A"]), k
+        assert torch.equal(r["B"], single["B"]), k
+        assert torch.equal(r["E"], single["E"]), k
+        assert np.array_equal(r["loss"], single["loss"]), k
+
+
+@gpu
+def test_ragged_vs_oracle(api):
+    _say("ragged vs oracle T=8")
+    imgs = _images()
+    seeds = list(range(len(imgs)))
+    gammas = [1.0] * len(imgs)
+    rr = api.fit_ragged([x for x, _, _ in imgs], [p for _, _, p in imgs], seeds, gammas, T=8)
+    for k, ((_, X, p), r) in enumerate(zip(imgs, rr)):
+        ref = O.edaa_fit(X, p, T=8, gamma=1.0, seed=seeds[k])
+        rel = np.max(np.abs(r["loss"] - ref["loss"]) / ref["loss"])
+        A_err = np.max(np.abs(r["A"].cpu().numpy() - ref["A"]))
+        NB_err = X.shape[1] * np.max(np.abs(r["B"].cpu().numpy() - ref["B"]))
+        _say(f"image {k} {SHAPES[k]}: loss rel {rel:.2e} A {A_err:.2e} N*B {NB_err:.2e}")
+        assert rel <= 1e-4 and A_err <= 1e-3 and NB_err <= 1e-2, k
+
+
+@gpu
+def test_ragged_graph_replay(api):
+    _say("ragged graph replay x3")
+    imgs = _images()
+    args = ([x for x, _, _ in imgs], [p for _, _, p in imgs], list(range(len(imgs))), [1.0] * len(imgs))
+    eager = api.fit_ragged(*args, T=6)
+    for rep in range(3):
+        rg = api.fit_ragged(*args, T=6, graph=True)
+        torch.cuda.synchronize()
+        for k in range(len(imgs)):
+            assert torch.equal(rg[k]["A"], eager[k]["A"]) and torch.equal(rg[k]["B"], eager[k]["B"]), (rep, k)
+            assert np.array_equal(rg[k]["loss"], eager[k]["loss"]), (rep, k)
+        _ = (imgs[0][0] * 2.0).sum().item()      # eager work between replays
