@@ -185,7 +185,7 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--plain-runs", type=int, default=5, help="single runs timed for the plain path (0: skip)")
-    ap.add_argument("--cpu-sample-T", type=int, default=3, help="oracle outer iterations timed (0: skip)")
+    ap.add_argument("--cpu-sample-T", type=int, default=40, help="oracle outer iterations timed (0: skip)")
     ap.add_argument("--n-seeds", type=int, default=10)
     ap.add_argument("--ragged-images", type=int, default=64, help="images of the ragged batch (0: skip)")
     ap.add_argument("--bf16-T", type=int, default=100, help="outer iterations of the BF16 large-scene runs (0: skip)")

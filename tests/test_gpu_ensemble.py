@@ -1,5 +1,6 @@
 """GPU parity of the batched ensemble (Algorithm 2 over runs advanced together)
 against the float64 oracle, run by run."""
+import os
 import sys
 
 import numpy as np
@@ -147,3 +148,31 @@ def test_urban_shaped_ensemble_vs_oracle(api):
         assert rel < 1e-4 and a_err < 1e-3 and nb_err < 1e-2
         one = api.fit(Xg, 6, T=10, gamma=gammas[m], seed=seeds[m])
         assert np.max(np.abs(one["loss"] - r["loss"][m]) / ref["loss"]) < 1e-4
+
+
+GOLD_URBAN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "urban_fp64_traces.txt")
+
+
+@gpu
+def test_urban_long_horizon_vs_fp64_traces(api):
+    """T = 100 on the benchmark workload: runs 0 (gamma 0.25) and 4 (gamma 4)
+    of the batched M = 50 ensemble, and the same runs as single fits, against
+    the float64 oracle traces in tests/golden (written by
+    make_urban_traces.py).  Over 100 iterations the float32 path cannot stay
+    within the 1e-4 one-step tolerance of a float64 trajectory (a plain
+    float32 NumPy run of the oracle drifts to 4.4e-4 at gamma 0.25 and 1.6e-2
+    at gamma 4); the gates are 3e-4 and 5e-3 on the whole trace, and the
+    batched and single-run paths must agree to 1e-3 at the end."""
+    gold = np.loadtxt(GOLD_URBAN)
+    s, cfg = synth.urban_ensemble()
+    _say("urban M=50 T=100 vs float64 traces (runs 0 and 4)")
+    Xg, _ = _prep(s.X)
+    r = api.ensemble(Xg, 6, cfg["seeds"], cfg["gammas"], T=100)
+    for col, m, tol in ((1, 0, 3e-4), (2, 4, 5e-3)):
+        ref = gold[:, col]
+        one = api.fit(Xg, 6, T=100, gamma=cfg["gammas"][m], seed=cfg["seeds"][m])
+        rel_b = np.max(np.abs(r["loss"][m] - ref) / ref)
+        rel_s = np.max(np.abs(one["loss"] - ref) / ref)
+        rel_bs = abs(r["loss"][m][-1] - one["loss"][-1]) / one["loss"][-1]
+        _say(f"run {m}: batched {rel_b:.2e} single {rel_s:.2e} batched-vs-single final {rel_bs:.2e}")
+        assert rel_b <= tol and rel_s <= tol and rel_bs <= 1e-3
