@@ -451,7 +451,7 @@ __device__ __forceinline__ float mfma_project(const float* Ec, int ECS, const fl
     float xx = 0.f;
     const float* xb = Xs + 4 * kk * kXS + 16 * w + m;
     const float* eb = Ec + 4 * kk * ECS + m;
-    // Software pipeline over blocks of 16 bands with two register sets: the
+    // Software pipeline over blocks of 16 bands with two operand sets: the
     // operands of the next block are read between the first MFMAs of the
     // current one, so they arrive while the rest of its MFMAs run.
     float b0[4], e0[4][NCB], b1[4], e1[4][NCB];
@@ -471,19 +471,23 @@ __device__ __forceinline__ float mfma_project(const float* Ec, int ECS, const fl
             for (int cb = 0; cb < NCB; ++cb) s[cb] = mfma16(e[u][cb], b[u], s[cb]);
         }
     };
+    // One block per trip, no branch in the body: a branch (or a body that
+    // alternates two accumulation orders) made the compiler copy the
+    // accumulators out of and back into AGPRs on every trip, which drains
+    // the MFMA pipeline.  Only the operands are copied between sets.
     load(b0, e0, 0);
-    for (int k0 = 0; k0 < LP; k0 += 32) {
-        if (k0 + 16 < LP) {                            // uniform
-            mma(b0, e0);
-            load(b1, e1, k0 + 16);
-            interleave_loads<4 * NCB>();
-            mma(b1, e1);
-            load(b0, e0, (k0 + 32 < LP) ? k0 + 32 : k0);
-            interleave_loads<4 * NCB>();
-        } else {
-            mma(b0, e0);
-        }
+    int k0 = 0;
+    for (; k0 + 16 < LP; k0 += 32) {
+        load(b1, e1, k0 + 16);
+        __builtin_amdgcn_sched_barrier(0);
+        mma(b0, e0);
+        __builtin_amdgcn_sched_barrier(0);
+        load(b0, e0, (k0 + 32 < LP) ? k0 + 32 : k0);
+        __builtin_amdgcn_sched_barrier(0);
+        mma(b1, e1);
+        __builtin_amdgcn_sched_barrier(0);
     }
+    if (k0 < LP) mma(b0, e0);
 #pragma unroll
     for (int cb = 0; cb < NCB; ++cb)
 #pragma unroll
@@ -532,19 +536,23 @@ __device__ __forceinline__ double mfma_project_f64(const float* Ec, int ECS, con
             for (int cb = 0; cb < NCB; ++cb) s[cb] = mfma16d((double)e[u][cb], bd, s[cb]);
         }
     };
+    // One block per trip, no branch in the body: a branch (or a body that
+    // alternates two accumulation orders) made the compiler copy the
+    // accumulators out of and back into AGPRs on every trip, which drains
+    // the MFMA pipeline.  Only the operands are copied between sets.
     load(b0, e0, 0);
-    for (int k0 = 0; k0 < LP; k0 += 32) {
-        if (k0 + 16 < LP) {                            // uniform
-            mma(b0, e0);
-            load(b1, e1, k0 + 16);
-            interleave_loads<4 * NCB>();
-            mma(b1, e1);
-            load(b0, e0, (k0 + 32 < LP) ? k0 + 32 : k0);
-            interleave_loads<4 * NCB>();
-        } else {
-            mma(b0, e0);
-        }
+    int k0 = 0;
+    for (; k0 + 16 < LP; k0 += 32) {
+        load(b1, e1, k0 + 16);
+        __builtin_amdgcn_sched_barrier(0);
+        mma(b0, e0);
+        __builtin_amdgcn_sched_barrier(0);
+        load(b0, e0, (k0 + 32 < LP) ? k0 + 32 : k0);
+        __builtin_amdgcn_sched_barrier(0);
+        mma(b1, e1);
+        __builtin_amdgcn_sched_barrier(0);
     }
+    if (k0 < LP) mma(b0, e0);
 #pragma unroll
     for (int cb = 0; cb < NCB; ++cb)
 #pragma unroll
