@@ -161,9 +161,12 @@ struct RunBuffers {
     double* gammas;
 };
 
-size_t layout(const Geom& g, int T, char* base, RunBuffers* rb) {
+// x_bytes: bytes per element of X (4 or 2) for the padded copy.
+size_t layout(const Geom& g, int T, int x_bytes, char* base, RunBuffers* rb) {
     Arena a;
     const size_t Q = (size_t)g.M * g.p;
+    const size_t ldx = (size_t)g.ntiles * kTile;
+    const size_t o_Xp = a.take<char>((size_t)g.L * ldx * x_bytes);
     const size_t o_Bst = a.take<float>(Q * (size_t)g.ntiles * kTile);   // rows padded to whole tiles
     const size_t o_tsh = a.take<float>((size_t)g.ntiles * g.Qp);
     const size_t o_colm = a.take<float>(g.Qp);
@@ -188,6 +191,9 @@ size_t layout(const Geom& g, int T, char* base, RunBuffers* rb) {
     const size_t o_gam = a.take<double>(g.M);
     if (rb) {
         State& s = rb->s;
+        s.X = base + o_Xp;
+        s.ldx = ldx;
+        s.x_bf16 = x_bytes == 2 ? 1 : 0;
         s.Bst = (float*)(base + o_Bst);
         s.tshift = (float*)(base + o_tsh);
         s.colm = (float*)(base + o_colm);
@@ -221,6 +227,7 @@ struct Seq {
     PassTimer* timer;   // mutable: capture switches timing off
     const Geom* g;
     const State* s;
+    const void* X;      // the caller's X [L][N], copied into s->X (padded)
     RunInit ri;
     int mode;          // kModeInitRng or kModeInitB0
     const float* A0;
@@ -241,6 +248,7 @@ hipError_t enqueue_sequence(const Seq& q, hipStream_t st, long long* launches) {
         if (e != hipSuccess) return e;        \
         ++n;                                  \
     } while (0)
+    EDAA_L(launch_pad_x(q.X, const_cast<void*>(s.X), g.L, g.N, s.ldx, s.x_bf16, st));
     // zero the padded [L][Qp] arrays (pad columns must read as zero)
     EDAA_L(launch_fill(s.E, (size_t)(g.L + kPadRows) * g.Qp, 0.f, st));
     EDAA_L(launch_fill(s.W, (size_t)(g.L + kPadRows) * g.Qp, 0.f, st));
@@ -355,15 +363,14 @@ edaa_status run_batch(edaa_ctx* ctx, const void* X, int L, int N, int p, const e
         if (pass_lds_bytes(p, g.R, L, kind) > kMaxLdsBytes)
             return fail(EDAA_EUNSUPPORTED, "L=%d with p=%d needs %zu bytes of LDS (limit %zu)", L, p,
                         pass_lds_bytes(p, g.R, L, kind), kMaxLdsBytes);
-    const size_t need = layout(g, P->T, nullptr, nullptr);
+    const int x_bytes = P->x_dtype == EDAA_X_BF16 ? 2 : 4;
+    const size_t need = layout(g, P->T, x_bytes, nullptr, nullptr);
     edaa_status st = ensure_ws(ctx, need);
     if (st != EDAA_OK) return st;
     RunBuffers rb;
     memset(&rb, 0, sizeof(rb));
-    layout(g, P->T, (char*)ctx->ws, &rb);
+    layout(g, P->T, x_bytes, (char*)ctx->ws, &rb);
     State& s = rb.s;
-    s.X = X;
-    s.x_bf16 = P->x_dtype == EDAA_X_BF16 ? 1 : 0;
     s.A = A_all;
 
     // Host -> device copies of the per-run scalars happen outside any graph.
@@ -375,6 +382,7 @@ edaa_status run_batch(edaa_ctx* ctx, const void* X, int L, int N, int p, const e
     ctx->timer.enabled = (P->flags & EDAA_FLAG_TIME_PASSES) != 0;
     q.g = &g;
     q.s = &s;
+    q.X = X;
     q.ri.seeds = rb.seeds;
     q.ri.gammas = rb.gammas;
     q.ri.init_scale = (float)P->init_scale;
@@ -416,10 +424,24 @@ struct RaggedGroup {
     size_t lds_a, lds_b, lds_c;
 };
 
-hipError_t enqueue_ragged(const std::vector<RaggedGroup>& groups, const ImageJob* jobs, int T, int K1, int K2,
-                          int cosine, hipStream_t st, long long* launches) {
+// Padded copy of one ragged image's X.
+struct PadJob {
+    const void* X;
+    void* Xp;
+    int L, N;
+    size_t ldx;
+    int bf16;
+};
+
+hipError_t enqueue_ragged(const std::vector<RaggedGroup>& groups, const std::vector<PadJob>& pads,
+                          const ImageJob* jobs, int T, int K1, int K2, int cosine, hipStream_t st,
+                          long long* launches) {
     long long n = 0;
     hipError_t e;
+    for (const PadJob& pj : pads) {
+        if ((e = launch_pad_x(pj.X, pj.Xp, pj.L, pj.N, pj.ldx, pj.bf16, st)) != hipSuccess) return e;
+        ++n;
+    }
     auto L_ = [&](int kernel, int mapk, size_t lds, int arg) -> hipError_t {
         for (const RaggedGroup& G : groups) {
             hipError_t r = launch_multi(kernel, G.p, jobs, G.map[mapk], G.nb[mapk], lds ? lds : 0, arg, st);
@@ -459,6 +481,7 @@ hipError_t enqueue_ragged(const std::vector<RaggedGroup>& groups, const ImageJob
 
 edaa_status run_ragged(edaa_ctx* ctx, int n, const edaa_image_desc* images, const edaa_params* P) {
     const int T = P->T;
+    const int x_bytes = P->x_dtype == EDAA_X_BF16 ? 2 : 4;
     // groups of equal p, in order of first appearance
     std::vector<int> ps;
     std::vector<std::vector<int>> members;
@@ -477,7 +500,7 @@ edaa_status run_ragged(edaa_ctx* ctx, int n, const edaa_image_desc* images, cons
     Arena a;
     for (int k = 0; k < n; ++k) {
         geoms[k] = make_geom(images[k].L, images[k].N, 1, images[k].p);
-        const size_t bytes = layout(geoms[k], T, nullptr, nullptr);
+        const size_t bytes = layout(geoms[k], T, x_bytes, nullptr, nullptr);
         off[k] = a.take<char>(bytes);
     }
     const size_t o_jobs = a.take<ImageJob>(n);
@@ -497,6 +520,7 @@ edaa_status run_ragged(edaa_ctx* ctx, int n, const edaa_image_desc* images, cons
     char* base = (char*)ctx->ws;
 
     std::vector<ImageJob> jobs(n);
+    std::vector<PadJob> pads(n);
     std::vector<uint64_t> seeds(n);
     std::vector<double> gammas(n);
     std::vector<RunBuffers> rbs(n);
@@ -504,9 +528,7 @@ edaa_status run_ragged(edaa_ctx* ctx, int n, const edaa_image_desc* images, cons
         const edaa_image_desc& d = images[k];
         RunBuffers& rb = rbs[k];
         memset(&rb, 0, sizeof(rb));
-        layout(geoms[k], T, base + off[k], &rb);
-        rb.s.X = d.X;
-        rb.s.x_bf16 = P->x_dtype == EDAA_X_BF16 ? 1 : 0;
+        layout(geoms[k], T, x_bytes, base + off[k], &rb);
         rb.s.A = d.A;
         ImageJob& J = jobs[k];
         memset(&J, 0, sizeof(J));
@@ -521,6 +543,7 @@ edaa_status run_ragged(edaa_ctx* ctx, int n, const edaa_image_desc* images, cons
         J.ri.eta2 = P->eta2;
         J.B_out = d.B;
         J.E_out = d.E;
+        pads[k] = PadJob{d.X, const_cast<void*>(rb.s.X), d.L, d.N, rb.s.ldx, rb.s.x_bf16};
         seeds[k] = d.seed;
         gammas[k] = d.gamma;
     }
@@ -569,7 +592,7 @@ edaa_status run_ragged(edaa_ctx* ctx, int n, const edaa_image_desc* images, cons
     }
     const int K1 = P->K1, K2 = P->K2, cosine = P->coherence_mode == EDAA_COHERENCE_COSINE ? 1 : 0;
     st = run_captured(ctx, key, (P->flags & EDAA_FLAG_GRAPH) != 0, [&](hipStream_t s, long long* nl) {
-        return enqueue_ragged(groups, jobs_dev, T, K1, K2, cosine, s, nl);
+        return enqueue_ragged(groups, pads, jobs_dev, T, K1, K2, cosine, s, nl);
     });
     if (st != EDAA_OK) return st;
     bool any = false;

@@ -36,7 +36,8 @@ struct Geom {
 // endmember j) in the unpadded [Q][N] arrays; padded column c * QC + qq in the
 // [L][Qp] arrays.
 struct State {
-    const void* X;      // [L][N] float32 or bf16 bits
+    const void* X;      // [L][ldx] padded copy of the caller's X (float32 or bf16 bits), pixels >= N zero
+    size_t ldx;         // ntiles * 64
     int x_bf16;
     float* A;           // [Q][N] abundances (the caller's A_all)
     float* Bst;         // [Q][ntiles * 64] unnormalised pixel weights (pixels >= N: zero)
@@ -107,6 +108,7 @@ hipError_t launch_multi(int kernel, int p, const ImageJob* jobs, const int2* map
 
 // Launchers (edaa_kernels.hip).  All enqueue on `st` and return the HIP error
 // of the last launch.
+hipError_t launch_pad_x(const void* X, void* Xp, int L, int N, size_t ldx, int bf16, hipStream_t st);
 hipError_t launch_fill(float* dst, size_t n, float value, hipStream_t st);
 hipError_t launch_init_A(const Geom& g, const State& s, const float* A0, hipStream_t st);
 hipError_t launch_bpass(const Geom& g, const State& s, int mode, const RunInit& ri, hipStream_t st);

@@ -193,41 +193,98 @@ __device__ __forceinline__ void wg_coords(const Geom& g, int b, int& pg, int& c)
     }
 }
 
-// X tile staging.  dma_tile issues direct global->LDS loads
-// (global_load_lds_dword, no registers involved) of X[:, tile*64 : +64] into
-// rows [0, L) of an LDS tile: wave w loads the rows w, w + 4, ..., one
-// 64-pixel row per instruction.  Lanes past N load pixel N-1; those columns
-// only ever meet a zero weight.  The loads complete asynchronously: the
-// caller waits (s_waitcnt) and synchronises the workgroup before reading.
-// load_tile_sync is the register path used for bf16 X (converted to float).
-__device__ __forceinline__ void dma_tile(const float* X, int L, int N, int tile, float* Xs) {
+// X tile staging.  X here is the library's padded copy, [L][ldx] with
+// ldx = ntiles * 64 and zero pixels past N, so every tile is whole and
+// aligned.  Three ways to put X[:, tile*64 : +64] into rows [0, L) of an LDS
+// tile (pitch kXS):
+//  - dma_tile (float32 X): direct global->LDS loads, one 64-pixel row per
+//    instruction, issued one tile ahead (measured faster than the register
+//    staging below for float32);
+//  - XRegs (bf16 X): register staging; wave w loads the row groups
+//    4w + 16i .. +3, each lane 4 consecutive pixels of one row (8 B) per
+//    instruction, one tile ahead, and store() widens them to float and
+//    writes 16 B per lane to LDS once the loads have landed (float32 X
+//    through the same path loads 16 B per lane);
+//  - load_tile_sync: synchronous loads through registers (bf16 kernels
+//    without room for the staging registers, and the closing pass).
+constexpr int kRegXGroups = 16;     // row groups per wave: L <= 4 * 4 * 16 = 256
+
+// ON = false compiles to nothing (kernels without room for the registers).
+template <bool ON>
+struct XRegs {
+    uint4 v[kRegXGroups];                        // bf16 uses the first two words
+
+    __device__ __forceinline__ void issue(const void* X, int bf16, size_t ldx, int L, int tile) {
+        const int lane = threadIdx.x & 63, w = uniform_int(threadIdx.x >> 6);
+        const int rsub = lane >> 4, col = 4 * (lane & 15);
+#pragma unroll
+        for (int i = 0; i < kRegXGroups; ++i) {
+            const int row = 16 * i + 4 * w + rsub;
+            if (16 * i + 4 * w < L) {                      // uniform per wave
+                const size_t off = (size_t)min(row, L - 1) * ldx + (size_t)tile * kTile + col;
+                if (bf16) {
+                    const uint2 t = *(const uint2*)((const uint16_t*)X + off);
+                    v[i] = make_uint4(t.x, t.y, 0u, 0u);
+                } else {
+                    v[i] = *(const uint4*)((const float*)X + off);
+                }
+            }
+        }
+    }
+    __device__ __forceinline__ void store(float* Xs, int bf16, int L) const {
+        const int lane = threadIdx.x & 63, w = uniform_int(threadIdx.x >> 6);
+        const int rsub = lane >> 4, col = 4 * (lane & 15);
+#pragma unroll
+        for (int i = 0; i < kRegXGroups; ++i) {
+            const int row = 16 * i + 4 * w + rsub;
+            if (16 * i + 4 * w < L && row < L) {
+                f4 o;
+                if (bf16) {
+                    o = f4{__uint_as_float(v[i].x << 16), __uint_as_float(v[i].x & 0xffff0000u),
+                           __uint_as_float(v[i].y << 16), __uint_as_float(v[i].y & 0xffff0000u)};
+                } else {
+                    o = f4{__uint_as_float(v[i].x), __uint_as_float(v[i].y), __uint_as_float(v[i].z),
+                           __uint_as_float(v[i].w)};
+                }
+                *(f4*)(Xs + row * kXS + col) = o;
+            }
+        }
+    }
+};
+template <>
+struct XRegs<false> {
+    __device__ __forceinline__ void issue(const void*, int, size_t, int, int) {}
+    __device__ __forceinline__ void store(float*, int, int) const {}
+};
+
+__device__ __forceinline__ void dma_tile(const float* X, size_t ldx, int L, int tile, float* Xs) {
     const int lane = threadIdx.x & 63, w = uniform_int(threadIdx.x >> 6);
-    const float* src = X + min(tile * kTile + lane, N - 1);
-    for (int l = w; l < L; l += 4) __builtin_amdgcn_global_load_lds(src + (size_t)l * N, Xs + l * kXS, 4, 0, 0);
+    const float* src = X + (size_t)tile * kTile + lane;
+    for (int l = w; l < L; l += 4) __builtin_amdgcn_global_load_lds(src + (size_t)l * ldx, Xs + l * kXS, 4, 0, 0);
 }
 
-__device__ __forceinline__ void load_tile_sync(const void* X, int x_bf16, int L, int N, int tile, float* Xs) {
+__device__ __forceinline__ void load_tile_sync(const void* X, int x_bf16, int L, size_t ldx, int tile, float* Xs) {
     const int i = threadIdx.x & 63, r0 = threadIdx.x >> 6;
-    const int pix = tile * kTile + i;
-    const bool ok = pix < N;
-    const size_t pc = (size_t)min(pix, N - 1);
+    const size_t pc = (size_t)tile * kTile + i;
     constexpr int B = 16;
     for (int l0 = r0; l0 < L; l0 += 4 * B) {
         float v[B];
 #pragma unroll
         for (int b = 0; b < B; ++b) {
-            const size_t off = (size_t)min(l0 + 4 * b, L - 1) * N + pc;
+            const size_t off = (size_t)min(l0 + 4 * b, L - 1) * ldx + pc;
             v[b] = x_bf16 ? bf16_to_f32(((const uint16_t*)X)[off]) : ((const float*)X)[off];
         }
 #pragma unroll
         for (int b = 0; b < B; ++b)
-            if (l0 + 4 * b < L) Xs[(l0 + 4 * b) * kXS + i] = ok ? v[b] : 0.f;
+            if (l0 + 4 * b < L) Xs[(l0 + 4 * b) * kXS + i] = v[b];
     }
 }
 
-__device__ __forceinline__ void load_tile(const void* X, int x_bf16, int L, int N, int tile, float* Xs) {
-    load_tile_sync(X, x_bf16, L, N, tile, Xs);
-}
+// Whether a pass kernel has room for the staging registers (compile time);
+// at run time L must also fit the row groups.
+template <int PP, int R, bool APASS>
+constexpr bool kRegX = PP * R <= 48 && (!APASS || PP <= 12);
+constexpr int kRegXMaxL = 4 * 4 * kRegXGroups;
 
 // K1 entropic steps of eq. update_A for one pixel: a <- softmax(log a -
 // eta1 (G a - P)), P = E^T x.  The logarithm is carried between steps.
@@ -632,10 +689,13 @@ __device__ __forceinline__ void apass_body(const Geom& g, const State& s, int bi
 #pragma unroll
     for (int r = 0; r < RW; ++r) lacc[r] = 0.0;
 
-    // Pipeline: the X tile (direct-to-LDS loads) and this thread's
-    // abundances (registers) of tile t + npg are requested while tile t is
-    // processed.
-    const bool dma = !s.x_bf16;
+    // Pipeline: the X tile and this thread's abundances (registers) of tile
+    // t + npg are requested while tile t is processed.
+    constexpr bool kRX = kRegX<PP, R, true>;
+    const bool regx = kRX && L <= kRegXMaxL && s.x_bf16;      // float32 X: direct-to-LDS loads
+    const bool dma = !regx && !s.x_bf16;
+    XRegs<kRX> xr;
+
     float an[RW][PP];
     auto load_a = [&](int tile) {
         const size_t pixc = (size_t)min(tile * kTile + lane, N - 1);
@@ -648,15 +708,21 @@ __device__ __forceinline__ void apass_body(const Geom& g, const State& s, int bi
     };
     __syncthreads();
     if (pg < g.ntiles) {
-        if (dma) dma_tile((const float*)s.X, L, N, pg, smem + xo[0]);
+        if (regx) {
+            xr.issue(s.X, s.x_bf16, s.ldx, L, pg);
+            xr.store(smem + xo[0], s.x_bf16, L);
+        } else if (dma) {
+            dma_tile((const float*)s.X, s.ldx, L, pg, smem + xo[0]);
+        }
         load_a(pg);
     }
     int it = 0;
     for (int tile = pg; tile < g.ntiles; tile += g.npg, ++it) {
         float* Xs = smem + ((it & 1) ? xo[1] : xo[0]);
-        if (!dma) {
+        float* Xn = smem + ((it & 1) ? xo[0] : xo[1]);     // == Xs when single-buffered
+        if (!dma && !regx) {
             lds_barrier();
-            load_tile_sync(s.X, s.x_bf16, L, N, tile, Xs);
+            load_tile_sync(s.X, s.x_bf16, L, s.ldx, tile, Xs);
         }
         __builtin_amdgcn_s_waitcnt(0);
         lds_barrier();
@@ -673,7 +739,8 @@ __device__ __forceinline__ void apass_body(const Geom& g, const State& s, int bi
         const int nt = tile + g.npg;
         if (nt < g.ntiles) {
             load_a(nt);
-            if (dma && g.dbuf) dma_tile((const float*)s.X, L, N, nt, smem + ((it & 1) ? xo[0] : xo[1]));
+            if (regx) xr.issue(s.X, s.x_bf16, s.ldx, L, nt);
+            if (dma && g.dbuf) dma_tile((const float*)s.X, s.ldx, L, nt, Xn);
         }
         {
             // projection on the matrix cores: P for pixels 16w..16w+15
@@ -716,9 +783,12 @@ __device__ __forceinline__ void apass_body(const Geom& g, const State& s, int bi
         }
         lds_barrier();
         mfma_accumulate<NCB, NRBW, WTS, false, NGBW>(acc, gram, true, Xs, Wt, nullptr, nullptr, nrb, w, lane);
-        if (nt < g.ntiles && dma && !g.dbuf) {
-            lds_barrier();                        // single buffer: reload after every reader
-            dma_tile((const float*)s.X, L, N, nt, Xs);
+        if (nt < g.ntiles && (regx || dma)) {
+            if (!g.dbuf) lds_barrier();           // single buffer: overwrite after every reader
+            if (regx)
+                xr.store(Xn, s.x_bf16, L);
+            else if (!g.dbuf)
+                dma_tile((const float*)s.X, s.ldx, L, nt, Xs);
         }
     }
 
@@ -830,10 +900,13 @@ __device__ __forceinline__ void bpass_body(const Geom& g, const State& s, int bi
 #pragma unroll
         for (int cb = 0; cb < NCB; ++cb) acc[jb][cb] = d4{0.0, 0.0, 0.0, 0.0};
 
-    // Pipeline: the X tile (direct-to-LDS loads) and this thread's B segment
-    // and shift (registers) of tile t + npg are requested while tile t is
-    // processed.
-    const bool dma = !s.x_bf16;
+    // Pipeline: the X tile and this thread's B segment and shift (registers)
+    // of tile t + npg are requested while tile t is processed.
+    constexpr bool kRX = kRegX<PP, R, false>;
+    const bool regx = kRX && L <= kRegXMaxL && s.x_bf16;      // float32 X: direct-to-LDS loads
+    const bool dma = !regx && !s.x_bf16;
+    XRegs<kRX> xr;
+
     f4 bn[4];
     float tn = 0.f;
     auto load_b = [&](int tile) {
@@ -846,15 +919,21 @@ __device__ __forceinline__ void bpass_body(const Geom& g, const State& s, int bi
     };
     __syncthreads();
     if (pg < g.ntiles) {
-        if (dma) dma_tile((const float*)s.X, L, N, pg, smem + xo[0]);
+        if (regx) {
+            xr.issue(s.X, s.x_bf16, s.ldx, L, pg);
+            xr.store(smem + xo[0], s.x_bf16, L);
+        } else if (dma) {
+            dma_tile((const float*)s.X, s.ldx, L, pg, smem + xo[0]);
+        }
         load_b(pg);
     }
     int it = 0;
     for (int tile = pg; tile < g.ntiles; tile += g.npg, ++it) {
         float* Xs = smem + ((it & 1) ? xo[1] : xo[0]);
-        if (!dma) {
+        float* Xn = smem + ((it & 1) ? xo[0] : xo[1]);     // == Xs when single-buffered
+        if (!dma && !regx) {
             lds_barrier();
-            load_tile_sync(s.X, s.x_bf16, L, N, tile, Xs);
+            load_tile_sync(s.X, s.x_bf16, L, s.ldx, tile, Xs);
         }
         __builtin_amdgcn_s_waitcnt(0);
         lds_barrier();
@@ -865,7 +944,8 @@ __device__ __forceinline__ void bpass_body(const Geom& g, const State& s, int bi
         const int nt = tile + g.npg;
         if (nt < g.ntiles) {
             load_b(nt);
-            if (dma && g.dbuf) dma_tile((const float*)s.X, L, N, nt, smem + ((it & 1) ? xo[0] : xo[1]));
+            if (regx) xr.issue(s.X, s.x_bf16, s.ldx, L, nt);
+            if (dma && g.dbuf) dma_tile((const float*)s.X, s.ldx, L, nt, Xn);
         }
 
         if (STEP) {
@@ -933,9 +1013,12 @@ __device__ __forceinline__ void bpass_body(const Geom& g, const State& s, int bi
         }
         lds_barrier();
         mfma_accumulate<NCB, NRBW, WTS, true, 1, true>(acc, gdummy, false, Xs, Wq, F, FG, nrb, w, lane);
-        if (nt < g.ntiles && dma && !g.dbuf) {
-            lds_barrier();                        // single buffer: reload after every reader
-            dma_tile((const float*)s.X, L, N, nt, Xs);
+        if (nt < g.ntiles && (regx || dma)) {
+            if (!g.dbuf) lds_barrier();           // single buffer: overwrite after every reader
+            if (regx)
+                xr.store(Xn, s.x_bf16, L);
+            else if (!g.dbuf)
+                dma_tile((const float*)s.X, s.ldx, L, nt, Xs);
         }
     }
 
@@ -983,7 +1066,7 @@ __device__ __forceinline__ void close_body(const Geom& g, const State& s, int bi
 
     for (int tile = pg; tile < g.ntiles; tile += g.npg) {
         __syncthreads();
-        load_tile(s.X, s.x_bf16, L, N, tile, Xs);
+        load_tile_sync(s.X, s.x_bf16, L, s.ldx, tile, Xs);
         const int pix = tile * kTile + lane;
         const bool pok = pix < N;
         __syncthreads();
@@ -1449,6 +1532,18 @@ __global__ __launch_bounds__(kThreads) void k_final_multi(const ImageJob* __rest
     if (jl.y == 0) final_E_body<PP>(J.g, J.s, 0, J.E_out, cosine);
 }
 
+// The padded copy of X the pass kernels read: [L][ldx], pixels >= N zero.
+__global__ void k_pad_x(const void* __restrict__ X, void* __restrict__ Xp, int L, int N, size_t ldx, int bf16) {
+    const size_t n = (size_t)L * ldx;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        const size_t l = i / ldx, pix = i % ldx;
+        if (bf16)
+            ((uint16_t*)Xp)[i] = pix < (size_t)N ? ((const uint16_t*)X)[l * N + pix] : (uint16_t)0;
+        else
+            ((float*)Xp)[i] = pix < (size_t)N ? ((const float*)X)[l * N + pix] : 0.f;
+    }
+}
+
 __global__ void k_fill(float* __restrict__ dst, size_t n, float v) {
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) dst[i] = v;
 }
@@ -1702,6 +1797,13 @@ hipError_t launch_multi(int kernel, int p, const ImageJob* jobs, const int2* map
         default:
             return hipErrorInvalidValue;
     }
+}
+
+hipError_t launch_pad_x(const void* X, void* Xp, int L, int N, size_t ldx, int bf16, hipStream_t st) {
+    const size_t n = (size_t)L * ldx;
+    const int bx = (int)std::min<size_t>((n + 255) / 256, 16384);
+    hipLaunchKernelGGL(k_pad_x, dim3(bx), dim3(256), 0, st, X, Xp, L, N, ldx, bf16);
+    return hipGetLastError();
 }
 
 hipError_t launch_fill(float* dst, size_t n, float value, hipStream_t st) {
