@@ -30,6 +30,7 @@ struct Geom {
     int npg;      // pixel groups (workgroups per chunk)
     int dbuf;     // pass kernels double-buffer the X tile in LDS
     int ecs;      // LDS pitch (floats) of the staged projection operand
+    int gf;       // the A-pass keeps a float copy of the Gram matrices in LDS
 };
 
 // Device-side state of a batched problem.  Column q = m * p + j (run m,

@@ -335,13 +335,14 @@ struct Shape {
 
 // LDS layout of a pass kernel, in floats.  LP = L rounded up to 16.
 struct PassLds {
-    int xs, wt, f, fg, ec, gs, ps, xx, pd, xs2, total;
+    int xs, wt, f, fg, ec, gs, gf, xx, pd, xs2, total;
 };
 // dbuf: a second X tile buffer, so that the next tile loads while the
 // current one is processed.
 // ecs: LDS pitch of the staged projection operand (QCP + 4 avoids bank
 // conflicts in the projections; QCP + 1 where LDS is short).
-__host__ __device__ inline PassLds pass_lds(int PP, int R, int L, int dbuf, int ecs) {
+// gf: room for a float copy of the Gram matrices (A-steps).
+__host__ __device__ inline PassLds pass_lds(int PP, int R, int L, int dbuf, int ecs, int gf) {
     const int QC = PP * R, QCP = (QC + 15) & ~15, WTS = QCP + 1, ECS = ecs;
     const int LP = (L + 15) & ~15;
     PassLds o;
@@ -352,8 +353,8 @@ __host__ __device__ inline PassLds pass_lds(int PP, int R, int L, int dbuf, int 
     o.ec = o.fg + QCP;                         // [LP][ECS] projection operand chunk (E or W)
     o.gs = o.ec + LP * ECS;                    // [R][PP][PP] Gram matrices (double, 2 floats each)
     o.gs = (o.gs + 1) & ~1;
-    o.ps = o.gs + 2 * R * PP * PP;
-    o.xx = o.ps;                               // [64] squared pixel norms (double, 2 floats each)
+    o.gf = o.gs + 2 * R * PP * PP;             // [R][PP][PP] the same Gram matrices in float (A-steps)
+    o.xx = (o.gf + (gf ? R * PP * PP : 0) + 1) & ~1;   // [64] squared pixel norms (double, 2 floats each)
     o.pd = o.xx + 2 * kTile;                   // [64][WTS] low part of the A-pass projection
     o.xs2 = o.pd + kTile * WTS;
     o.total = o.xs2 + (dbuf ? LP * kXS : 0);
@@ -642,10 +643,11 @@ __device__ __forceinline__ void apass_body(const Geom& g, const State& s, int bi
     const int ECS = g.ecs;
     constexpr int NGBW = S::NGBW;
     extern __shared__ float smem[];
-    const PassLds lo = pass_lds(PP, R, g.L, g.dbuf, g.ecs);
+    const PassLds lo = pass_lds(PP, R, g.L, g.dbuf, g.ecs, g.gf);
     float* Wt = smem + lo.wt;
     float* Ec = smem + lo.ec;
     double* Gd = (double*)(smem + lo.gs);
+    float* Gf = smem + lo.gf;                  // used when g.gf
     const int xo[2] = {lo.xs, g.dbuf ? lo.xs2 : lo.xs};
     double* XX = (double*)(smem + lo.xx);
     float* Plo = smem + lo.pd;
@@ -669,6 +671,7 @@ __device__ __forceinline__ void apass_body(const Geom& g, const State& s, int bi
         double acc = 0.0;
         for (int l = 0; l < L; ++l) acc = fma((double)Ek[l * ECS + j], (double)Ek[l * ECS + k], acc);
         Gd[e] = acc;
+        if (g.gf) Gf[e] = (float)acc;
     }
     __syncthreads();
     // zero the X rows beyond L and the weight padding (never written later)
@@ -773,7 +776,12 @@ __device__ __forceinline__ void apass_body(const Geom& g, const State& s, int bi
                     }
                     lacc[k] += q;
                 }
-                if (mok) a_steps<PP>(a[k], P, Gr, s.eta[2 * m], K1);
+                if (mok) {
+                    if (g.gf)
+                        a_steps<PP>(a[k], P, Gf + r * PP * PP, s.eta[2 * m], K1);
+                    else
+                        a_steps<PP>(a[k], P, Gr, s.eta[2 * m], K1);
+                }
 #pragma unroll
                 for (int j = 0; j < PP; ++j) {
                     if (mok && pok) A[(size_t)(m * PP + j) * N + pix] = a[k][j];
@@ -858,7 +866,7 @@ __device__ __forceinline__ void bpass_body(const Geom& g, const State& s, int bi
     const int ECS = g.ecs;
     static_assert(QCP <= kThreads / 4, "one quad of threads per softmax column");
     extern __shared__ float smem[];
-    const PassLds lo = pass_lds(PP, R, g.L, g.dbuf, g.ecs);
+    const PassLds lo = pass_lds(PP, R, g.L, g.dbuf, g.ecs, g.gf);
     float* Wq = smem + lo.wt;                      // [QCP][kXS]
     float* F = smem + lo.f;
     float* FG = smem + lo.fg;
@@ -1581,13 +1589,13 @@ __global__ __launch_bounds__(kThreads) void k_normalize(const float* __restrict_
 
 size_t launch_lds_bytes(const Geom& g, int kind) {
     if (kind == 2) return pass_lds_bytes(g.p, g.R, g.L, 2);
-    return (size_t)pass_lds(g.p, g.R, g.L, g.dbuf, g.ecs).total * sizeof(float);
+    return (size_t)pass_lds(g.p, g.R, g.L, g.dbuf, g.ecs, g.gf).total * sizeof(float);
 }
 
 size_t pass_lds_bytes(int PP, int R, int L, int kind) {
     if (kind == 2) return ((size_t)L * kXS + 8 * kTile) * sizeof(float);
     const int QCP = (PP * R + 15) & ~15;
-    return (size_t)pass_lds(PP, R, L, 0, QCP + 1).total * sizeof(float);
+    return (size_t)pass_lds(PP, R, L, 0, QCP + 1, 0).total * sizeof(float);
 }
 
 namespace {
@@ -1595,13 +1603,13 @@ namespace {
 template <int PP, int R>
 struct Kernels {
     static hipError_t apass(const Geom& g, const State& s, int K1, hipStream_t st) {
-        const size_t lds = (size_t)pass_lds(PP, R, g.L, g.dbuf, g.ecs).total * sizeof(float);
+        const size_t lds = (size_t)pass_lds(PP, R, g.L, g.dbuf, g.ecs, g.gf).total * sizeof(float);
         set_max_lds((const void*)k_apass<PP, R>, (int)lds);
         hipLaunchKernelGGL((k_apass<PP, R>), dim3(g.npg * g.nqc), dim3(kThreads), lds, st, g, s, (const float*)s.E, K1);
         return hipGetLastError();
     }
     static hipError_t bpass(const Geom& g, const State& s, int mode, const RunInit& ri, hipStream_t st) {
-        const size_t lds = (size_t)pass_lds(PP, R, g.L, g.dbuf, g.ecs).total * sizeof(float);
+        const size_t lds = (size_t)pass_lds(PP, R, g.L, g.dbuf, g.ecs, g.gf).total * sizeof(float);
         if (mode == kModeStep) {
             set_max_lds((const void*)k_bpass<PP, R, true>, (int)lds);
             hipLaunchKernelGGL((k_bpass<PP, R, true>), dim3(g.npg * g.nqc), dim3(kThreads), lds, st, g, s,
@@ -1698,7 +1706,7 @@ int runs_per_chunk(int p, int M, int L) {
     if (M <= 1) return 1;
     const int R = (M <= 4) ? 4 : rmax_for(p);
     // the stacked-run kernels keep the projection operand in LDS as well
-    if ((size_t)pass_lds(p, R, L, 0, ((p * R + 15) & ~15) + 1).total * sizeof(float) > kMaxLdsBytes) return 1;
+    if ((size_t)pass_lds(p, R, L, 0, ((p * R + 15) & ~15) + 1, 0).total * sizeof(float) > kMaxLdsBytes) return 1;
     return R;
 }
 
@@ -1716,8 +1724,8 @@ Geom make_geom(int L, int N, int M, int p) {
     g.npg = npg;
     // prefer the double-buffered X tile, then the conflict-free operand pitch
     const int QCP = (g.QC + 15) & ~15;
-    auto fits = [&](int db, int ecs) {
-        return (size_t)pass_lds(p, g.R, L, db, ecs).total * sizeof(float) <= kMaxLdsBytes;
+    auto fits = [&](int db, int ecs, int gf = 0) {
+        return (size_t)pass_lds(p, g.R, L, db, ecs, gf).total * sizeof(float) <= kMaxLdsBytes;
     };
     if (fits(1, QCP + 4)) {
         g.dbuf = 1; g.ecs = QCP + 4;
@@ -1728,6 +1736,7 @@ Geom make_geom(int L, int N, int M, int p) {
     } else {
         g.dbuf = 0; g.ecs = QCP + 1;
     }
+    g.gf = fits(g.dbuf, g.ecs, 1) ? 1 : 0;
     return g;
 }
 
