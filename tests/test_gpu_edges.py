@@ -1,0 +1,108 @@
+"""Edge shapes and the BF16 row at the large scene's (L, p).
+
+BF16 storage: the oracle runs on exactly the bf16 values the GPU reads, so
+the float32 arithmetic is gated at the float32 tolerances; the effect of the
+bf16 rounding itself (against the same runs on the float32 X) is reported
+and only loosely bounded, since it is a property of the data, not of the
+kernels."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import edaa as O
+from paper_2209_11002_amd import synth
+
+gpu = pytest.mark.gpu
+
+
+def _say(*a):
+    print("[case]", *a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def api():
+    if not torch.cuda.is_available():
+        pytest.skip("needs a GPU")
+    from paper_2209_11002_amd import api as A
+    return A
+
+
+def _prep(X, dtype=torch.float32):
+    Xn, _ = O.normalize_pixels(X)
+    Xt = torch.from_numpy(Xn.astype(np.float32)).to(dtype)
+    return Xt.cuda().contiguous(), Xt.to(torch.float64).numpy()
+
+
+def _np(t):
+    return t.detach().float().cpu().numpy().astype(np.float64)
+
+
+@gpu
+def test_bf16_large_scene_shape_vs_oracle(api):
+    """L = 224, p = 12, spatially smooth Dirichlet(1) abundances at SNR 30 dB
+    (the large scene's recipe) on a 32 x 64 crop; M = 4 runs, T = 10."""
+    s = synth.scene(5, 224, 32 * 64, 12, alpha=1.0, snr_db=30.0, shape=(32, 64), smooth_sigma_px=4.0)
+    _say("bf16 X L=224 N=2048 p=12 M=4 T=10")
+    X16g, X16 = _prep(s.X, torch.bfloat16)
+    X32g, X32 = _prep(s.X, torch.float32)
+    seeds, gammas = [0, 0, 1, 1], [0.5, 2.0, 1.0, 4.0]
+    r16 = api.ensemble(X16g, 12, seeds, gammas, T=10)
+    r32 = api.ensemble(X32g, 12, seeds, gammas, T=10)
+    N = X16.shape[1]
+    for m in range(4):
+        ref = O.edaa_fit(X16, 12, T=10, gamma=gammas[m], seed=seeds[m])
+        rel = np.max(np.abs(r16["loss"][m] - ref["loss"]) / ref["loss"])
+        A_err = np.max(np.abs(_np(r16["A"][m]) - ref["A"]))
+        NB_err = N * np.max(np.abs(_np(r16["B"][m]) - ref["B"]))
+        q = np.max(np.abs(r16["loss"][m] - r32["loss"][m]) / r32["loss"][m])
+        _say(f"run {m}: bf16 vs oracle on the bf16 X: loss {rel:.2e} A {A_err:.2e} N*B {NB_err:.2e}; "
+             f"bf16 vs float32 X: loss {q:.2e}")
+        assert rel <= 1e-4 and A_err <= 1e-3 and NB_err <= 1e-2
+        assert q <= 5e-2
+
+
+@gpu
+@pytest.mark.parametrize("L,N,p,M,T", [
+    (1, 100, 2, 1, 6),       # a single band
+    (30, 50, 3, 10, 6),      # fewer pixels than one tile, 20 runs per chunk
+    (25, 200, 3, 21, 5),     # the last chunk holds a single run
+    (17, 64, 6, 9, 5),       # exactly one tile, two chunks (8 + 1 runs)
+])
+def test_edge_shapes_vs_oracle(api, L, N, p, M, T):
+    _say(f"edge shape L={L} N={N} p={p} M={M} T={T}")
+    s = synth.small_case(seed=40 + L, L=L, N=N, p=min(p, max(1, L)))
+    Xg, X = _prep(s.X)
+    seeds = [m // 2 for m in range(M)]
+    gammas = [(0.5, 2.0)[m % 2] for m in range(M)]
+    r = api.ensemble(Xg, p, seeds, gammas, T=T)
+    # objectives near zero (L = 1: every normalised pixel is 1 and X B A
+    # reproduces it exactly) are compared against a floor of 1e-7 x
+    # 1/2 ||X||^2, the float32 resolution of the objective
+    floor = 1e-7 * 0.5 * float(np.sum(X * X))
+    for m in sorted({0, M // 2, M - 1}):
+        ref = O.edaa_fit(X, p, T=T, gamma=gammas[m], seed=seeds[m])
+        rel = np.max(np.abs(r["loss"][m] - ref["loss"]) / np.maximum(ref["loss"], floor))
+        A_err = np.max(np.abs(_np(r["A"][m]) - ref["A"]))
+        NB_err = N * np.max(np.abs(_np(r["B"][m]) - ref["B"]))
+        _say(f"run {m}: loss {rel:.2e} A {A_err:.2e} N*B {NB_err:.2e}")
+        assert rel <= 1e-4 and A_err <= 1e-3 and NB_err <= 1e-2
+        A = _np(r["A"][m])
+        B = _np(r["B"][m])
+        assert np.max(np.abs(A.sum(axis=0) - 1)) < 1e-5 and np.max(np.abs(B.sum(axis=0) - 1)) < 1e-5
+
+
+@gpu
+def test_ragged_bf16_equals_single_fits(api):
+    _say("ragged bf16: 3 images vs single fits")
+    shapes = [(40, 333, 4), (64, 700, 5), (31, 129, 4)]
+    imgs = []
+    for k, (L, N, p) in enumerate(shapes):
+        s = synth.small_case(seed=60 + k, L=L, N=N, p=p)
+        imgs.append((_prep(s.X, torch.bfloat16)[0], p))
+    rr = api.fit_ragged([x for x, _ in imgs], [p for _, p in imgs], [1, 2, 3], [1.0, 0.5, 2.0], T=8)
+    for k, ((Xg, p), r) in enumerate(zip(imgs, rr)):
+        one = api.fit(Xg, p, T=8, gamma=[1.0, 0.5, 2.0][k], seed=k + 1)
+        assert torch.equal(r["A"], one["A"]) and torch.equal(r["B"], one["B"]), k
+        assert np.array_equal(r["loss"], one["loss"]), k
