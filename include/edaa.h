@@ -170,6 +170,24 @@ edaa_status edaa_ensemble(edaa_ctx* ctx, const void* X, int L, int N, int p,
 edaa_status edaa_fit_ragged(edaa_ctx* ctx, int n_images, const edaa_image_desc* images,
                             const edaa_params* params);
 
+/* Abundance estimation with the endmembers given: minimise
+ * 1/2 ||X - E A||_F^2 over A [p][N] with every column on the simplex (the
+ * non-negativity and sum-to-one constraints of abundance estimation once the
+ * endmembers are known, as the paper's Introduction states it) by the
+ * entropic A-steps of eq. update_A with E in place of X B: params->T outer
+ * iterations of params->K1 steps (K2 is ignored), step eta1 = gamma /
+ * sigma_max^2(E) (the rule of eq. eta0A applied to E) unless params->eta1 > 0.
+ *   X          [L][N], dtype params->x_dtype (device)
+ *   E          [L][p] float32 (device), the given endmembers
+ *   A0         [p][N] start (device) or NULL for eq. initA0 (1/p)
+ *   A          out [p][N] float32 (device)
+ *   loss_trace out, host, T+1 objectives (loss[0] at A0), may be NULL
+ *   eta_out    out, host, 2 values (eta1 and sqrt(p/N) eta1), may be NULL
+ * Errors as edaa_fit. */
+edaa_status edaa_abundances(edaa_ctx* ctx, const void* X, int L, int N, int p,
+                            const edaa_params* params, const float* E, const float* A0,
+                            float* A, double* loss_trace, double* eta_out);
+
 /* Objective 1/2||X - X B A||_F^2 (eq. AA) for X [L][N] float32, A [p][N],
  * B [N][p] (all device); the float32 result is written to loss_dev (device,
  * one float). */

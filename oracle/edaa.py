@@ -177,6 +177,40 @@ def edaa_fit(X, p, T=DEFAULT_T, K1=DEFAULT_K1, K2=DEFAULT_K2, gamma=1.0,
     return dict(E=X @ B, A=A, B=B, loss=np.array(trace), eta1=eta1, eta2=eta2)
 
 
+def abundances(X, E, T=DEFAULT_T, K1=DEFAULT_K1, gamma=1.0, A0=None, eta1=None):
+    """Abundance estimation with the endmembers E (L x p) given: minimise
+    1/2 ||X - E A||_F^2 over A with every column on the simplex (the
+    non-negativity and sum-to-one constraints of the Introduction's
+    abundance estimation once endmembers are known), by the entropic steps
+    of eq. update_A with the given E in place of X B:
+        A <- softmax(log A + eta1 E^T (X - E A)).
+
+    Readings (the paper runs this step only inside Algorithm 1): A0 as in
+    eq. initA0; eta1 = gamma / sigma_max^2(E), the rule of eq. eta0A applied
+    to the given E; T outer iterations of K1 steps each, loss[0] at A0 and
+    loss[t] after outer iteration t.
+
+    Returns a dict with A, loss (T+1 values) and eta1."""
+    X = np.asarray(X, dtype=np.float64)
+    E = np.asarray(E, dtype=np.float64)
+    p = E.shape[1]
+    N = X.shape[1]
+    A = init_A(p, N) if A0 is None else np.array(A0, dtype=np.float64)
+    if eta1 is None:
+        eta1 = gamma / float(np.linalg.eigvalsh(E.T @ E)[-1])
+
+    def obj(A):
+        R = X - E @ A
+        return 0.5 * float(np.sum(R * R))
+
+    trace = [obj(A)]
+    for t in range(1, T + 1):
+        for _ in range(K1):
+            A = mirror_step(A, -(E.T @ (X - E @ A)), eta1)
+        trace.append(obj(A))
+    return dict(A=A, loss=np.array(trace), eta1=eta1)
+
+
 def fit_l1(X, E, A):
     """l1 fit of Algorithm 2: ||X - E A||_1, read as the entrywise sum of
     absolute values over the L x N residual (Section "Model selection

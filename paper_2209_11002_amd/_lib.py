@@ -45,6 +45,8 @@ SIGNATURES = {
     "edaa_fit": (c_int, [c_void_p, c_void_p, c_int, c_int, c_int, POINTER(EdaaParams), c_uint64,
                          c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
                          POINTER(c_double), POINTER(c_double)]),
+    "edaa_abundances": (c_int, [c_void_p, c_void_p, c_int, c_int, c_int, POINTER(EdaaParams),
+                                c_void_p, c_void_p, c_void_p, POINTER(c_double), POINTER(c_double)]),
     "edaa_ensemble": (c_int, [c_void_p, c_void_p, c_int, c_int, c_int, POINTER(EdaaParams), c_int,
                               POINTER(c_uint64), POINTER(c_double), c_void_p, c_void_p, c_void_p,
                               POINTER(c_double), POINTER(c_double), POINTER(c_double),

@@ -105,6 +105,28 @@ def fit(X, p, T=100, K1=5, K2=5, gamma=1.0, seed=0, A0=None, B0=None, eta=None,
                 status=st, launches=lib.edaa_last_launch_count(_ctx(dev)))
 
 
+def abundances(X, E, T=100, K1=5, gamma=1.0, A0=None, eta1=None, graph=False):
+    """Abundances for given endmembers E [L, p] (float32, GPU): T outer
+    iterations of K1 entropic A-steps (eq. update_A with E fixed) on
+    l2-normalised X [L, N].  Returns a dict: A [p, N] (tensor), loss (numpy,
+    T+1), eta1."""
+    Lb, N = _check_x(X)
+    if not (E.is_cuda and E.dtype == torch.float32 and E.dim() == 2 and E.shape[0] == Lb and E.is_contiguous()):
+        raise ValueError("E must be a contiguous float32 [L, p] GPU tensor")
+    p = E.shape[1]
+    if A0 is not None and (A0.dtype != torch.float32 or tuple(A0.shape) != (p, N) or not A0.is_contiguous()):
+        raise ValueError(f"A0 must be a contiguous float32 tensor of shape {(p, N)}")
+    A = torch.empty((p, N), dtype=torch.float32, device=X.device)
+    trace = (c_double * (T + 1))()
+    eta_out = (c_double * 2)()
+    P = _params(T, K1, 0, gamma, None if eta1 is None else (eta1, 1.0), 0.1, 1.05, _x_dtype(X), "cosine", graph)
+    st = L_.load().edaa_abundances(_ctx(X.device), _ptr(X), Lb, N, p, byref(P), _ptr(E), _ptr(A0), _ptr(A),
+                                   trace, eta_out)
+    if st not in (L_.EDAA_OK, L_.EDAA_ENUMERIC):
+        check(st)
+    return dict(A=A, loss=np.array(trace[:]), eta1=eta_out[0], status=st)
+
+
 def ensemble(X, p, seeds, gammas, T=100, K1=5, K2=5, coherence="cosine", threshold=1.05,
              init_scale=0.1, graph=False, out=None, time_passes=False):
     """M runs of Algorithm 1 advanced together plus Algorithm 2.  Returns a

@@ -235,6 +235,7 @@ struct Seq {
     float* B_out;
     float* E_out;
     int coherence_mode;
+    const float* E_given;   // abundance estimation with E fixed (A-passes only), else null
 };
 
 hipError_t enqueue_sequence(const Seq& q, hipStream_t st, long long* launches) {
@@ -255,10 +256,25 @@ hipError_t enqueue_sequence(const Seq& q, hipStream_t st, long long* launches) {
     EDAA_L(launch_fill((float*)s.XAtd, 2 * (size_t)g.L * g.Qp, 0.f, st));
     EDAA_L(launch_fill((float*)s.Ed, 2 * (size_t)g.L * g.Qp, 0.f, st));
     EDAA_L(launch_init_A(g, s, q.A0, st));
+    PassTimer* tm = q.timer;
+    if (q.E_given) {
+        // A-phase only with the given endmembers: eq. update_A with E fixed
+        EDAA_L(launch_set_e(q.E_given, g, s, st));
+        EDAA_L(launch_eta(g, s, q.ri, st));
+        for (int t = 0; t < q.T; ++t) {
+            if ((e = tm->mark(st, 0, false)) != hipSuccess) return e;
+            EDAA_L(launch_apass(g, s, q.K1, t, st));
+            if ((e = tm->mark(st, 0, true)) != hipSuccess) return e;
+            EDAA_L(launch_reduce_aa(g, s, t, st));
+        }
+        EDAA_L(launch_close(g, s, st));
+        EDAA_L(launch_reduce_close(g, s, st));
+        *launches = n;
+        return hipSuccess;
+    }
     EDAA_L(launch_bpass(g, s, q.mode, q.ri, st));
     EDAA_L(launch_reduce_b(g, s, 0, st));
     EDAA_L(launch_eta(g, s, q.ri, st));
-    PassTimer* tm = q.timer;
     for (int t = 0; t < q.T; ++t) {
         if ((e = tm->mark(st, 0, false)) != hipSuccess) return e;
         EDAA_L(launch_apass(g, s, q.K1, t, st));
@@ -289,7 +305,8 @@ std::string graph_key(const Seq& q, const void* X, const void* ws) {
     snprintf(buf, sizeof(buf),
              "%d,%d,%d,%d,%d,%d,%d,%d,%d|%d,%d,%d|%p,%p,%p,%p,%p,%p,%p|%a,%a,%a|%d,%d", g.L, g.N, g.M, g.p, g.R,
              g.npg, g.nqc, q.mode, q.coherence_mode, q.T, q.K1, q.K2, X, (const void*)q.s->A, (const void*)q.B_out,
-             (const void*)q.E_out, (const void*)q.A0, (const void*)q.ri.B0, ws, (double)q.ri.init_scale, q.ri.eta1,
+             (const void*)q.E_out, (const void*)q.A0, (const void*)(q.E_given ? q.E_given : q.ri.B0), ws,
+             (double)q.ri.init_scale, q.ri.eta1,
              q.ri.eta2, q.s->x_bf16, q.timer->enabled ? 1 : 0);
     return buf;
 }
@@ -357,7 +374,8 @@ edaa_status run_sequence(edaa_ctx* ctx, const Seq& q, const void* X, int use_gra
 // Shared implementation of edaa_fit (M = 1) and edaa_ensemble.
 edaa_status run_batch(edaa_ctx* ctx, const void* X, int L, int N, int p, const edaa_params* P, int M,
                       const uint64_t* seeds, const double* gammas, const float* A0, const float* B0, float* A_all,
-                      float* B_all, float* E_all, double* loss, double* fit, double* mu, double* eta_out) {
+                      float* B_all, float* E_all, double* loss, double* fit, double* mu, double* eta_out,
+                      const float* E_given = nullptr) {
     const Geom g = make_geom(L, N, M, p);
     for (int kind = 0; kind < 3; ++kind)
         if (pass_lds_bytes(p, g.R, L, kind) > kMaxLdsBytes)
@@ -398,6 +416,7 @@ edaa_status run_batch(edaa_ctx* ctx, const void* X, int L, int N, int p, const e
     q.B_out = B_all;
     q.E_out = E_all;
     q.coherence_mode = P->coherence_mode;
+    q.E_given = E_given;
     st = run_sequence(ctx, q, X, (P->flags & EDAA_FLAG_GRAPH) ? 1 : 0);
     if (st != EDAA_OK) return st;
 
@@ -714,6 +733,25 @@ edaa_status edaa_fit(edaa_ctx* ctx, const void* X, int L, int N, int p, const ed
     const double gamma = params->gamma;
     st = run_batch(ctx, X, L, N, p, params, 1, &seed, &gamma, A0, B0, A, B, E, loss_trace, nullptr, nullptr,
                    eta_out);
+    if (st != EDAA_OK) return st;
+    if (loss_trace && !isfinite(loss_trace[params->T]))
+        return fail(EDAA_ENUMERIC, "the objective is not finite after %d outer iterations", params->T);
+    return EDAA_OK;
+}
+
+edaa_status edaa_abundances(edaa_ctx* ctx, const void* X, int L, int N, int p, const edaa_params* params,
+                            const float* E, const float* A0, float* A, double* loss_trace, double* eta_out) {
+    edaa_status st = check_ctx(ctx);
+    if (st != EDAA_OK) return st;
+    if ((st = check_params(params)) != EDAA_OK) return st;
+    if ((st = check_shape(L, N, p, 1)) != EDAA_OK) return st;
+    EDAA_REQUIRE(X && E && A, "X, E and A must not be null");
+    EDAA_REQUIRE(params->eta1 > 0.0 || (isfinite(params->gamma) && params->gamma > 0.0),
+                 "gamma must be finite and > 0 (got %g)", params->gamma);
+    const double gamma = params->gamma;
+    const uint64_t seed = 0;
+    st = run_batch(ctx, X, L, N, p, params, 1, &seed, &gamma, A0, nullptr, A, nullptr, nullptr, loss_trace, nullptr,
+                   nullptr, eta_out, E);
     if (st != EDAA_OK) return st;
     if (loss_trace && !isfinite(loss_trace[params->T]))
         return fail(EDAA_ENUMERIC, "the objective is not finite after %d outer iterations", params->T);

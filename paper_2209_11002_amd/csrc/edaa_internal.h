@@ -117,6 +117,8 @@ hipError_t launch_reduce_b(const Geom& g, const State& s, int need_w, hipStream_
 hipError_t launch_eta(const Geom& g, const State& s, const RunInit& ri, hipStream_t st);
 hipError_t launch_apass(const Geom& g, const State& s, int K1, int t, hipStream_t st);
 hipError_t launch_reduce_a(const Geom& g, const State& s, int t, hipStream_t st);
+hipError_t launch_reduce_aa(const Geom& g, const State& s, int t, hipStream_t st);
+hipError_t launch_set_e(const float* E_given, const Geom& g, const State& s, hipStream_t st);
 hipError_t launch_close(const Geom& g, const State& s, hipStream_t st);
 hipError_t launch_reduce_close(const Geom& g, const State& s, hipStream_t st);
 hipError_t launch_finalize(const Geom& g, const State& s, float* B_out, float* E_out,

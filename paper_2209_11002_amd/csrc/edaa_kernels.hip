@@ -1636,6 +1636,10 @@ struct Kernels {
         hipLaunchKernelGGL((k_reduce_a<PP, R>), dim3(g.L, g.nqc), dim3(kThreads), 0, st, g, s, t);
         return hipGetLastError();
     }
+    static hipError_t reduce_aa(const Geom& g, const State& s, int t, hipStream_t st) {
+        hipLaunchKernelGGL((k_reduce_aa<PP, R>), dim3(g.M), dim3(kThreads), 0, st, g, s, t);
+        return hipGetLastError();
+    }
 };
 
 template <int PP>
@@ -1678,6 +1682,7 @@ template <int PP, int R> struct ApassOp { static hipError_t run(const Geom& g, c
 template <int PP, int R> struct BpassOp { static hipError_t run(const Geom& g, const State& s, int mode, const RunInit& ri, hipStream_t st) { return Kernels<PP, R>::bpass(g, s, mode, ri, st); } };
 template <int PP, int R> struct CloseOp { static hipError_t run(const Geom& g, const State& s, hipStream_t st) { return Kernels<PP, R>::close(g, s, st); } };
 template <int PP, int R> struct RedBOp { static hipError_t run(const Geom& g, const State& s, int need_w, hipStream_t st) { return Kernels<PP, R>::reduce_b(g, s, need_w, st); } };
+template <int PP, int R> struct RedAAOp { static hipError_t run(const Geom& g, const State& s, int t, hipStream_t st) { return Kernels<PP, R>::reduce_aa(g, s, t, st); } };
 template <int PP, int R> struct RedAOp { static hipError_t run(const Geom& g, const State& s, int t, hipStream_t st) { return Kernels<PP, R>::reduce_a(g, s, t, st); } };
 
 template <template <int, int> class Op, typename... Args>
@@ -1841,6 +1846,26 @@ hipError_t launch_apass(const Geom& g, const State& s, int K1, int t, hipStream_
 }
 hipError_t launch_reduce_a(const Geom& g, const State& s, int t, hipStream_t st) {
     return run_pr<RedAOp>(g.p, g.R, g, s, t, st);
+}
+hipError_t launch_reduce_aa(const Geom& g, const State& s, int t, hipStream_t st) {
+    return run_pr<RedAAOp>(g.p, g.R, g, s, t, st);
+}
+
+// Given endmembers (abundance estimation with E fixed): E [L][p] of run 0
+// into the padded float and float64 state arrays.
+__global__ void k_set_e(const float* __restrict__ Eg, float* __restrict__ E, double* __restrict__ Ed, int L, int p,
+                        int Qp) {
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < L * p; e += gridDim.x * blockDim.x) {
+        const int l = e / p, j = e % p;
+        E[(size_t)l * Qp + j] = Eg[e];
+        Ed[(size_t)l * Qp + j] = (double)Eg[e];
+    }
+}
+hipError_t launch_set_e(const float* E_given, const Geom& g, const State& s, hipStream_t st) {
+    const int n = g.L * g.p;
+    hipLaunchKernelGGL(k_set_e, dim3(std::max(1, std::min((n + 255) / 256, 1024))), dim3(256), 0, st, E_given, s.E,
+                       s.Ed, g.L, g.p, g.Qp);
+    return hipGetLastError();
 }
 hipError_t launch_close(const Geom& g, const State& s, hipStream_t st) {
     return run_pr<CloseOp>(g.p, g.R, g, s, st);

@@ -452,3 +452,36 @@ def test_ensemble_selects_per_algorithm_2():
     for r, s_, g in zip(e["runs"], seeds, gammas):
         assert np.allclose(r["E"], X @ r["B"])
         assert r["eta1"] == pytest.approx(g / O.sigma_max_sq(X, O.init_B_from_seed(s_, 300, 3)))
+
+
+# --------------------------------------------------------------------------
+# Abundance estimation with given endmembers (the A-step of eq. update_A
+# with E fixed): its limit is the simplex-constrained least-squares solution
+# of every pixel, found here by enumerating supports; and p = 2 reduces to the
+# clipped projection onto the segment [e2, e1].
+# --------------------------------------------------------------------------
+def test_abundances_given_E_reach_bruteforce_optimum():
+    rng = np.random.default_rng(11)
+    L, N, p = 12, 40, 3
+    E = rng.uniform(0.1, 1.0, size=(L, p))              # endmembers not taken from X
+    A_true = rng.dirichlet(np.ones(p) * 0.7, size=N).T
+    X = E @ A_true + 0.02 * rng.normal(size=(L, N))
+    r = O.abundances(X, E, T=4000, K1=5, gamma=1.0)
+    assert np.all(np.diff(r["loss"]) <= 1e-12 * r["loss"][:-1])   # eta1 max_j ||e_j||^2 <= 1 here
+    for i in range(N):
+        fbest, abest = _bruteforce_simplex_ls(E, X[:, i])
+        fe = float(np.sum((X[:, i] - E @ r["A"][:, i]) ** 2))
+        assert fe >= fbest - 1e-12
+        assert fe - fbest <= 1e-6 * fbest + 1e-8
+        assert np.max(np.abs(r["A"][:, i] - abest)) < 1e-2
+
+
+def test_abundances_given_E_p2_closed_form():
+    rng = np.random.default_rng(12)
+    L, N = 8, 30
+    E = rng.uniform(0.1, 1.0, size=(L, 2))
+    X = E @ rng.dirichlet([1.0, 1.0], size=N).T + 0.05 * rng.normal(size=(L, N))
+    d = E[:, 0] - E[:, 1]
+    a1 = np.clip(((X - E[:, [1]]).T @ d) / (d @ d), 0.0, 1.0)
+    r = O.abundances(X, E, T=4000, K1=5, gamma=1.0)
+    assert np.max(np.abs(r["A"][0] - a1)) < 2e-3
