@@ -176,3 +176,30 @@ def test_urban_long_horizon_vs_fp64_traces(api):
         rel_bs = abs(r["loss"][m][-1] - one["loss"][-1]) / one["loss"][-1]
         _say(f"run {m}: batched {rel_b:.2e} single {rel_s:.2e} batched-vs-single final {rel_bs:.2e}")
         assert rel_b <= tol and rel_s <= tol and rel_bs <= 1e-3
+
+
+@gpu
+def test_hundred_runs_gamma_drawn_from_S(api):
+    """M = 100 runs with gamma drawn uniformly from the paper's set S (one
+    draw per run, seeded) and seeds 0..99, T = 10: every run against the
+    oracle, and the selection of Algorithm 2 against the oracle's fits and
+    coherences (allowing the ties float32 cannot separate)."""
+    s = synth.small_case(seed=90, L=40, N=333, p=3)
+    Xg, X = _prep(s.X)
+    rng = np.random.default_rng(2209)
+    gammas = [float(g) for g in rng.choice(O.GAMMA_SET, size=100)]
+    seeds = list(range(100))
+    _say("M=100, gamma ~ U(S), T=10")
+    r = api.ensemble(Xg, 3, seeds, gammas, T=10)
+    fit_ref, mu_ref = np.zeros(100), np.zeros(100)
+    worst = 0.0
+    for m in range(100):
+        ref = O.edaa_fit(X, 3, T=10, gamma=gammas[m], seed=seeds[m])
+        worst = max(worst, float(np.max(np.abs(r["loss"][m] - ref["loss"]) / ref["loss"])))
+        fit_ref[m] = O.fit_l1(X, ref["E"], ref["A"])
+        mu_ref[m] = O.coherence(ref["E"])
+    _say(f"worst loss rel over 100 runs {worst:.2e}; selected {r['selected']} (oracle {O.select(fit_ref, mu_ref)})")
+    assert worst <= 1e-4
+    assert np.max(np.abs(r["fit"] - fit_ref) / fit_ref) <= 1e-4
+    assert np.max(np.abs(r["mu"] - mu_ref)) <= 1e-4
+    _check_selection(r["selected"], fit_ref, mu_ref)
