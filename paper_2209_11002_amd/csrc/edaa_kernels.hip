@@ -50,11 +50,6 @@ __device__ __forceinline__ d4 mfma16d(double a, double b, d4 c) {
 
 __device__ __forceinline__ int uniform_int(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
-__device__ __forceinline__ float wave_max(float v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o));
-    return v;
-}
 __device__ __forceinline__ float wave_sum(float v) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
@@ -66,73 +61,12 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
-// Wave-wide max / sum: within each row of 16 lanes by DPP (quad permutes,
-// then row rotations by 4 and 8), then across the 4 rows from lanes 0, 16,
-// 32, 48.  The result is the same in every lane.
+// A DPP lane permutation within rows of 16 lanes (all rows and banks
+// enabled); the B-step softmax uses the quad permutes 0xB1 (lane ^ 1) and
+// 0x4E (lane ^ 2).
 template <int CTRL>
 __device__ __forceinline__ float dpp(float v) {
     return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
-}
-__device__ __forceinline__ float lane_f(float v, int l) {
-    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
-}
-// Reductions of several values at once, step by step, so the independent
-// DPP chains overlap: within rows of 16 lanes (quad permutes, row rotations
-// by 4 and 8), then row_bcast:15 (rows 1, 3 take row 0 / row 2) and
-// row_bcast:31 (rows 2, 3 take lane 31); lane 63 ends with the wave result,
-// which is returned in every lane.
-template <int CTRL, int ROWMASK>
-__device__ __forceinline__ float dpp_rm(float old, float v) {
-    return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(old), __float_as_int(v), CTRL, ROWMASK, 0xF, false));
-}
-template <int K>
-__device__ __forceinline__ void wave_max_k(float (&r)[K]) {
-#pragma unroll
-    for (int k = 0; k < K; ++k) r[k] = fmaxf(r[k], dpp<0xB1>(r[k]));
-#pragma unroll
-    for (int k = 0; k < K; ++k) r[k] = fmaxf(r[k], dpp<0x4E>(r[k]));
-#pragma unroll
-    for (int k = 0; k < K; ++k) r[k] = fmaxf(r[k], dpp<0x124>(r[k]));
-#pragma unroll
-    for (int k = 0; k < K; ++k) r[k] = fmaxf(r[k], dpp<0x128>(r[k]));
-#pragma unroll
-    for (int k = 0; k < K; ++k) r[k] = fmaxf(r[k], dpp_rm<0x142, 0xA>(r[k], r[k]));
-#pragma unroll
-    for (int k = 0; k < K; ++k) r[k] = fmaxf(r[k], dpp_rm<0x143, 0xC>(r[k], r[k]));
-#pragma unroll
-    for (int k = 0; k < K; ++k) r[k] = lane_f(r[k], 63);
-}
-template <int K>
-__device__ __forceinline__ void wave_sum_k(float (&r)[K]) {
-#pragma unroll
-    for (int k = 0; k < K; ++k) r[k] += dpp<0xB1>(r[k]);
-#pragma unroll
-    for (int k = 0; k < K; ++k) r[k] += dpp<0x4E>(r[k]);
-#pragma unroll
-    for (int k = 0; k < K; ++k) r[k] += dpp<0x124>(r[k]);
-#pragma unroll
-    for (int k = 0; k < K; ++k) r[k] += dpp<0x128>(r[k]);
-#pragma unroll
-    for (int k = 0; k < K; ++k) r[k] += dpp_rm<0x142, 0xA>(0.f, r[k]);
-#pragma unroll
-    for (int k = 0; k < K; ++k) r[k] += dpp_rm<0x143, 0xC>(0.f, r[k]);
-#pragma unroll
-    for (int k = 0; k < K; ++k) r[k] = lane_f(r[k], 63);
-}
-
-__device__ __forceinline__ float wave_max_dpp(float v) {
-    v = fmaxf(v, dpp<0xB1>(v));
-    v = fmaxf(v, dpp<0x4E>(v));
-    v = fmaxf(v, dpp<0x124>(v));
-    v = fmaxf(v, dpp<0x128>(v));
-    return fmaxf(fmaxf(lane_f(v, 0), lane_f(v, 16)), fmaxf(lane_f(v, 32), lane_f(v, 48)));
-}
-__device__ __forceinline__ float wave_sum_dpp(float v) {
-    v += dpp<0xB1>(v);
-    v += dpp<0x4E>(v);
-    v += dpp<0x124>(v);
-    v += dpp<0x128>(v);
-    return (lane_f(v, 0) + lane_f(v, 16)) + (lane_f(v, 32) + lane_f(v, 48));
 }
 
 // e^x and ln x from the hardware base-2 instructions (v_exp_f32, v_log_f32).
@@ -203,8 +137,7 @@ __device__ __forceinline__ void wg_coords(const Geom& g, int b, int& pg, int& c)
 //  - XRegs (bf16 X): register staging; wave w loads the row groups
 //    4w + 16i .. +3, each lane 4 consecutive pixels of one row (8 B) per
 //    instruction, one tile ahead, and store() widens them to float and
-//    writes 16 B per lane to LDS once the loads have landed (float32 X
-//    through the same path loads 16 B per lane);
+//    writes 16 B per lane to LDS once the loads have landed;
 //  - load_tile_sync: synchronous loads through registers (bf16 kernels
 //    without room for the staging registers, and the closing pass).
 constexpr int kRegXGroups = 16;     // row groups per wave: L <= 4 * 4 * 16 = 256
@@ -212,9 +145,9 @@ constexpr int kRegXGroups = 16;     // row groups per wave: L <= 4 * 4 * 16 = 25
 // ON = false compiles to nothing (kernels without room for the registers).
 template <bool ON>
 struct XRegs {
-    uint4 v[kRegXGroups];                        // bf16 uses the first two words
+    uint2 v[kRegXGroups];                        // 4 bf16 per lane and row group
 
-    __device__ __forceinline__ void issue(const void* X, int bf16, size_t ldx, int L, int tile) {
+    __device__ __forceinline__ void issue(const void* X, size_t ldx, int L, int tile) {
         const int lane = threadIdx.x & 63, w = uniform_int(threadIdx.x >> 6);
         const int rsub = lane >> 4, col = 4 * (lane & 15);
 #pragma unroll
@@ -222,39 +155,27 @@ struct XRegs {
             const int row = 16 * i + 4 * w + rsub;
             if (16 * i + 4 * w < L) {                      // uniform per wave
                 const size_t off = (size_t)min(row, L - 1) * ldx + (size_t)tile * kTile + col;
-                if (bf16) {
-                    const uint2 t = *(const uint2*)((const uint16_t*)X + off);
-                    v[i] = make_uint4(t.x, t.y, 0u, 0u);
-                } else {
-                    v[i] = *(const uint4*)((const float*)X + off);
-                }
+                v[i] = *(const uint2*)((const uint16_t*)X + off);
             }
         }
     }
-    __device__ __forceinline__ void store(float* Xs, int bf16, int L) const {
+    __device__ __forceinline__ void store(float* Xs, int L) const {
         const int lane = threadIdx.x & 63, w = uniform_int(threadIdx.x >> 6);
         const int rsub = lane >> 4, col = 4 * (lane & 15);
 #pragma unroll
         for (int i = 0; i < kRegXGroups; ++i) {
             const int row = 16 * i + 4 * w + rsub;
-            if (16 * i + 4 * w < L && row < L) {
-                f4 o;
-                if (bf16) {
-                    o = f4{__uint_as_float(v[i].x << 16), __uint_as_float(v[i].x & 0xffff0000u),
-                           __uint_as_float(v[i].y << 16), __uint_as_float(v[i].y & 0xffff0000u)};
-                } else {
-                    o = f4{__uint_as_float(v[i].x), __uint_as_float(v[i].y), __uint_as_float(v[i].z),
-                           __uint_as_float(v[i].w)};
-                }
-                *(f4*)(Xs + row * kXS + col) = o;
-            }
+            if (16 * i + 4 * w < L && row < L)
+                *(f4*)(Xs + row * kXS + col) =
+                    f4{__uint_as_float(v[i].x << 16), __uint_as_float(v[i].x & 0xffff0000u),
+                       __uint_as_float(v[i].y << 16), __uint_as_float(v[i].y & 0xffff0000u)};
         }
     }
 };
 template <>
 struct XRegs<false> {
-    __device__ __forceinline__ void issue(const void*, int, size_t, int, int) {}
-    __device__ __forceinline__ void store(float*, int, int) const {}
+    __device__ __forceinline__ void issue(const void*, size_t, int, int) {}
+    __device__ __forceinline__ void store(float*, int) const {}
 };
 
 __device__ __forceinline__ void dma_tile(const float* X, size_t ldx, int L, int tile, float* Xs) {
@@ -712,8 +633,8 @@ __device__ __forceinline__ void apass_body(const Geom& g, const State& s, int bi
     __syncthreads();
     if (pg < g.ntiles) {
         if (regx) {
-            xr.issue(s.X, s.x_bf16, s.ldx, L, pg);
-            xr.store(smem + xo[0], s.x_bf16, L);
+            xr.issue(s.X, s.ldx, L, pg);
+            xr.store(smem + xo[0], L);
         } else if (dma) {
             dma_tile((const float*)s.X, s.ldx, L, pg, smem + xo[0]);
         }
@@ -742,7 +663,7 @@ __device__ __forceinline__ void apass_body(const Geom& g, const State& s, int bi
         const int nt = tile + g.npg;
         if (nt < g.ntiles) {
             load_a(nt);
-            if (regx) xr.issue(s.X, s.x_bf16, s.ldx, L, nt);
+            if (regx) xr.issue(s.X, s.ldx, L, nt);
             if (dma && g.dbuf) dma_tile((const float*)s.X, s.ldx, L, nt, Xn);
         }
         {
@@ -794,7 +715,7 @@ __device__ __forceinline__ void apass_body(const Geom& g, const State& s, int bi
         if (nt < g.ntiles && (regx || dma)) {
             if (!g.dbuf) lds_barrier();           // single buffer: overwrite after every reader
             if (regx)
-                xr.store(Xn, s.x_bf16, L);
+                xr.store(Xn, L);
             else if (!g.dbuf)
                 dma_tile((const float*)s.X, s.ldx, L, nt, Xs);
         }
@@ -928,8 +849,8 @@ __device__ __forceinline__ void bpass_body(const Geom& g, const State& s, int bi
     __syncthreads();
     if (pg < g.ntiles) {
         if (regx) {
-            xr.issue(s.X, s.x_bf16, s.ldx, L, pg);
-            xr.store(smem + xo[0], s.x_bf16, L);
+            xr.issue(s.X, s.ldx, L, pg);
+            xr.store(smem + xo[0], L);
         } else if (dma) {
             dma_tile((const float*)s.X, s.ldx, L, pg, smem + xo[0]);
         }
@@ -952,7 +873,7 @@ __device__ __forceinline__ void bpass_body(const Geom& g, const State& s, int bi
         const int nt = tile + g.npg;
         if (nt < g.ntiles) {
             load_b(nt);
-            if (regx) xr.issue(s.X, s.x_bf16, s.ldx, L, nt);
+            if (regx) xr.issue(s.X, s.ldx, L, nt);
             if (dma && g.dbuf) dma_tile((const float*)s.X, s.ldx, L, nt, Xn);
         }
 
@@ -1024,7 +945,7 @@ __device__ __forceinline__ void bpass_body(const Geom& g, const State& s, int bi
         if (nt < g.ntiles && (regx || dma)) {
             if (!g.dbuf) lds_barrier();           // single buffer: overwrite after every reader
             if (regx)
-                xr.store(Xn, s.x_bf16, L);
+                xr.store(Xn, L);
             else if (!g.dbuf)
                 dma_tile((const float*)s.X, s.ldx, L, nt, Xs);
         }
