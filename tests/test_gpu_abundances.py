@@ -44,3 +44,24 @@ def test_abundances_vs_oracle(api, L, N, p, gamma):
     assert rel <= 1e-5 and A_err <= 1e-4
     A = r["A"].cpu().numpy().astype(np.float64)
     assert np.all(A >= 0) and np.max(np.abs(A.sum(axis=0) - 1)) < 1e-5
+
+
+@gpu
+def test_abundances_bf16_X_and_resume(api):
+    """bf16 X (the oracle runs on the same bf16 values), and resuming from
+    the A and eta1 of a first call equals one longer call."""
+    s = synth.small_case(seed=77, L=60, N=450, p=4)
+    Xn, _ = O.normalize_pixels(s.X)
+    X16 = torch.from_numpy(Xn.astype(np.float32)).to(torch.bfloat16)
+    X64 = X16.to(torch.float64).numpy()
+    E = (s.M / np.linalg.norm(s.M, axis=0)).astype(np.float32)
+    Eg = torch.from_numpy(E).cuda()
+    r = api.abundances(X16.cuda(), Eg, T=12, K1=5, gamma=1.0)
+    ref = O.abundances(X64, E.astype(np.float64), T=12, K1=5, gamma=1.0)
+    rel = np.max(np.abs(r["loss"] - ref["loss"]) / ref["loss"])
+    _say(f"bf16 abundances: loss rel {rel:.2e}")
+    assert rel <= 1e-5 and np.max(np.abs(r["A"].cpu().numpy() - ref["A"])) <= 1e-4
+    r1 = api.abundances(X16.cuda(), Eg, T=6, K1=5, gamma=1.0)
+    r2 = api.abundances(X16.cuda(), Eg, T=6, K1=5, A0=r1["A"], eta1=r1["eta1"])
+    assert np.max(np.abs(r2["loss"] - r["loss"][6:]) / r["loss"][6:]) <= 1e-6
+    assert np.max(np.abs(r2["A"].cpu().numpy() - r["A"].cpu().numpy())) <= 1e-6

@@ -26,8 +26,9 @@ def api():
     return A
 
 
-# (L, N, p): two groups share p = 4, tails of 1..63 pixels, p from 1 to 16
-SHAPES = [(40, 333, 4), (57, 1000, 3), (31, 64, 1), (64, 777, 4), (20, 130, 16), (156, 2500, 6)]
+# (L, N, p): three images share p = 4, tails of 1..63 pixels, p from 1 to
+# 16, fewer pixels than one tile, and L > 256 (more row blocks per wave)
+SHAPES = [(40, 333, 4), (57, 1000, 3), (31, 64, 1), (64, 777, 4), (20, 130, 16), (156, 2500, 6), (300, 50, 4)]
 
 
 def _images(dtype=torch.float32):
@@ -45,7 +46,7 @@ def test_ragged_equals_single_image_fits(api):
     _say("ragged vs single fits:", SHAPES)
     imgs = _images()
     seeds = [11 * k + 1 for k in range(len(imgs))]
-    gammas = [0.5, 1.0, 2.0, 1.0, 0.25, 1.0]
+    gammas = [0.5, 1.0, 2.0, 1.0, 0.25, 1.0, 4.0]
     rr = api.fit_ragged([x for x, _, _ in imgs], [p for _, _, p in imgs], seeds, gammas, T=12)
     for k, ((Xg, _, p), r) in enumerate(zip(imgs, rr)):
         single = api.fit(Xg, p, T=12, gamma=gammas[k], seed=seeds[k])
