@@ -31,6 +31,13 @@
 namespace edaa {
 namespace {
 
+// Waves per workgroup of the B-step pass (the A-pass and the closing pass
+// use kThreads / 64 = 4).  With 8, each SIMD runs two waves of the
+// workgroup, so one wave's LDS waits overlap the other's matrix
+// instructions, and each wave issues half as many direct-to-LDS loads
+// (their issue, about 55 clocks each, stalls the issuing wave); both waves
+// share the one LDS allocation.
+constexpr int kBpassWaves = 8;
 constexpr int kXS = 68;   // LDS pitch (floats) of an X tile row of 64 pixels
 
 typedef float f4 __attribute__((ext_vector_type(4)));
@@ -143,17 +150,18 @@ __device__ __forceinline__ void wg_coords(const Geom& g, int b, int& pg, int& c)
 constexpr int kRegXGroups = 16;     // row groups per wave: L <= 4 * 4 * 16 = 256
 
 // ON = false compiles to nothing (kernels without room for the registers).
-template <bool ON>
+template <bool ON, int NW = 4>
 struct XRegs {
-    uint2 v[kRegXGroups];                        // 4 bf16 per lane and row group
+    static constexpr int NG = kRegXGroups * 4 / NW;   // row groups per wave
+    uint2 v[NG];                                 // 4 bf16 per lane and row group
 
     __device__ __forceinline__ void issue(const void* X, size_t ldx, int L, int tile) {
         const int lane = threadIdx.x & 63, w = uniform_int(threadIdx.x >> 6);
         const int rsub = lane >> 4, col = 4 * (lane & 15);
 #pragma unroll
-        for (int i = 0; i < kRegXGroups; ++i) {
-            const int row = 16 * i + 4 * w + rsub;
-            if (16 * i + 4 * w < L) {                      // uniform per wave
+        for (int i = 0; i < NG; ++i) {
+            const int row = 4 * NW * i + 4 * w + rsub;
+            if (4 * NW * i + 4 * w < L) {                  // uniform per wave
                 const size_t off = (size_t)min(row, L - 1) * ldx + (size_t)tile * kTile + col;
                 v[i] = *(const uint2*)((const uint16_t*)X + off);
             }
@@ -163,41 +171,43 @@ struct XRegs {
         const int lane = threadIdx.x & 63, w = uniform_int(threadIdx.x >> 6);
         const int rsub = lane >> 4, col = 4 * (lane & 15);
 #pragma unroll
-        for (int i = 0; i < kRegXGroups; ++i) {
-            const int row = 16 * i + 4 * w + rsub;
-            if (16 * i + 4 * w < L && row < L)
+        for (int i = 0; i < NG; ++i) {
+            const int row = 4 * NW * i + 4 * w + rsub;
+            if (4 * NW * i + 4 * w < L && row < L)
                 *(f4*)(Xs + row * kXS + col) =
                     f4{__uint_as_float(v[i].x << 16), __uint_as_float(v[i].x & 0xffff0000u),
                        __uint_as_float(v[i].y << 16), __uint_as_float(v[i].y & 0xffff0000u)};
         }
     }
 };
-template <>
-struct XRegs<false> {
+template <int NW>
+struct XRegs<false, NW> {
     __device__ __forceinline__ void issue(const void*, size_t, int, int) {}
     __device__ __forceinline__ void store(float*, int) const {}
 };
 
-__device__ __forceinline__ void dma_tile(const float* X, size_t ldx, int L, int tile, float* Xs) {
-    const int lane = threadIdx.x & 63, w = uniform_int(threadIdx.x >> 6);
+// Rows l = wd, wd + NWD, ... are loaded by wave wd of a group of NWD waves.
+template <int NWD = 4>
+__device__ __forceinline__ void dma_tile(const float* X, size_t ldx, int L, int tile, float* Xs, int wd) {
+    const int lane = threadIdx.x & 63;
     const float* src = X + (size_t)tile * kTile + lane;
-    for (int l = w; l < L; l += 4) __builtin_amdgcn_global_load_lds(src + (size_t)l * ldx, Xs + l * kXS, 4, 0, 0);
+    for (int l = wd; l < L; l += NWD) __builtin_amdgcn_global_load_lds(src + (size_t)l * ldx, Xs + l * kXS, 4, 0, 0);
 }
 
 __device__ __forceinline__ void load_tile_sync(const void* X, int x_bf16, int L, size_t ldx, int tile, float* Xs) {
-    const int i = threadIdx.x & 63, r0 = threadIdx.x >> 6;
+    const int i = threadIdx.x & 63, r0 = threadIdx.x >> 6, nw = blockDim.x >> 6;
     const size_t pc = (size_t)tile * kTile + i;
     constexpr int B = 16;
-    for (int l0 = r0; l0 < L; l0 += 4 * B) {
+    for (int l0 = r0; l0 < L; l0 += nw * B) {
         float v[B];
 #pragma unroll
         for (int b = 0; b < B; ++b) {
-            const size_t off = (size_t)min(l0 + 4 * b, L - 1) * ldx + pc;
+            const size_t off = (size_t)min(l0 + nw * b, L - 1) * ldx + pc;
             v[b] = x_bf16 ? bf16_to_f32(((const uint16_t*)X)[off]) : ((const float*)X)[off];
         }
 #pragma unroll
         for (int b = 0; b < B; ++b)
-            if (l0 + 4 * b < L) Xs[(l0 + 4 * b) * kXS + i] = v[b];
+            if (l0 + nw * b < L) Xs[(l0 + nw * b) * kXS + i] = v[b];
     }
 }
 
@@ -300,14 +310,14 @@ __device__ __forceinline__ void interleave_loads() {
 // in float32 by the MFMAs and folded into float64 running sums, so that the
 // partial of a workgroup carries no error that grows with its tile count
 // (W = E A A^T - X A^T cancels and would amplify it).  Wave w owns the row blocks
-// rb = w + 4 j (16 bands each) and every column block; with SCALE the
+// rb = w + NW j (16 bands each) and every column block; with SCALE the
 // running accumulation of column q is first multiplied by F[q].  The B
 // operands (Wt, 64 x QCP) are loaded once per tile and reused for every row
 // block; the optional Gram accumulation Wt^T Wt reuses them as well.
 // QMAJOR: the weights are stored column-major, Wt[q * kXS + pixel].
 // With SCALE the running sums of column q are first multiplied by F[q] and
 // the tile's sums by G[q].
-template <int NCB, int NRBW, int WTS, bool SCALE, int NGBW, bool QMAJOR = false>
+template <int NCB, int NRBW, int WTS, bool SCALE, int NGBW, bool QMAJOR = false, int NW = 4>
 __device__ __forceinline__ void mfma_accumulate(d4 (&acc)[NRBW][NCB], d4 (&gram)[NGBW], bool do_gram,
                                                 const float* Xs, const float* Wt, const float* F, const float* G,
                                                 int nrb, int w, int lane) {
@@ -336,7 +346,7 @@ __device__ __forceinline__ void mfma_accumulate(d4 (&acc)[NRBW][NCB], d4 (&gram)
     }
 #pragma unroll
     for (int j = 0; j < NRBW; ++j) {
-        const int rb = w + 4 * j;
+        const int rb = w + NW * j;
         if (rb < nrb) {
             f4 t[NCB];
 #pragma unroll
@@ -348,7 +358,7 @@ __device__ __forceinline__ void mfma_accumulate(d4 (&acc)[NRBW][NCB], d4 (&gram)
             }
             float xn[16];
             if (j + 1 < NRBW) {
-                const float* xr = Xs + (16 * min(rb + 4, nrb - 1) + m) * kXS + kk;
+                const float* xr = Xs + (16 * min(rb + NW, nrb - 1) + m) * kXS + kk;
 #pragma unroll
                 for (int k = 0; k < 16; ++k) xn[k] = xr[4 * k];
                 interleave_loads<16 * NCB>();
@@ -370,7 +380,7 @@ __device__ __forceinline__ void mfma_accumulate(d4 (&acc)[NRBW][NCB], d4 (&gram)
     if (do_gram) {
 #pragma unroll
         for (int gi = 0; gi < NGBW; ++gi) {
-            const int gb = w + 4 * gi;                 // (qb, qb) for even gb, (qb, qb+1) for odd
+            const int gb = w + NW * gi;                // (qb, qb) for even gb, (qb, qb+1) for odd
             if (gb < 2 * NCB - 1) {
                 const int q1 = gb >> 1, q2 = q1 + (gb & 1);
                 f4 tg = f4{0.f, 0.f, 0.f, 0.f};
@@ -392,12 +402,12 @@ __device__ __forceinline__ void mfma_accumulate(d4 (&acc)[NRBW][NCB], d4 (&gram)
 }
 
 // Write the accumulated V (rows < L, columns < QC) of this workgroup.
-template <int NCB, int NRBW, int QC>
+template <int NCB, int NRBW, int QC, int NW = 4>
 __device__ __forceinline__ void store_acc(const d4 (&acc)[NRBW][NCB], float* Vp, int L, int nrb, int w, int lane) {
     const int m = lane & 15, kk = lane >> 4;
 #pragma unroll
     for (int j = 0; j < NRBW; ++j) {
-        const int rb = w + 4 * j;
+        const int rb = w + NW * j;
         if (rb < nrb)
 #pragma unroll
             for (int cb = 0; cb < NCB; ++cb) {
@@ -412,7 +422,8 @@ __device__ __forceinline__ void store_acc(const d4 (&acc)[NRBW][NCB], float* Vp,
 }
 
 // Projection of the tile by a chunk operand staged in LDS (R > 1): wave w
-// computes the 16 pixels 16w..16w+15 for all QCP columns, S[q][i] =
+// computes the 16 pixels 16w..16w+15 for the NCB column blocks from CB0
+// (16 columns each), S[q][i] =
 // sum_l Ec[l][q] Xs[l][i]; results go to Sc[i][q] (or Sc[q][i] with QMAJOR).  Also returns, for the
 // same pixels, the partial sums of x^2 over the bands this lane touched.
 // LP (a multiple of 16) rows of both operands are read; rows L..LP-1 of
@@ -420,7 +431,7 @@ __device__ __forceinline__ void store_acc(const d4 (&acc)[NRBW][NCB], float* Vp,
 // u, u + 4, u + 8, u + 12 (lane group kk gets u + 4 kk): the four rows a
 // wave reads are then 4 rows apart, which with the pitches kXS = 68 and
 // ECS = QCP + 4 puts the 64 lanes on 64 distinct LDS banks.
-template <int NCB, int WTS, bool QMAJOR = false>
+template <int NCB, int WTS, bool QMAJOR = false, int CB0 = 0>
 __device__ __forceinline__ float mfma_project(const float* Ec, int ECS, const float* Xs, float* Sc, int LP, int w,
                                               int lane) {
     const int m = lane & 15, kk = lane >> 4;
@@ -429,7 +440,7 @@ __device__ __forceinline__ float mfma_project(const float* Ec, int ECS, const fl
     for (int cb = 0; cb < NCB; ++cb) s[cb] = f4{0.f, 0.f, 0.f, 0.f};
     float xx = 0.f;
     const float* xb = Xs + 4 * kk * kXS + 16 * w + m;
-    const float* eb = Ec + 4 * kk * ECS + m;
+    const float* eb = Ec + 4 * kk * ECS + 16 * CB0 + m;
     // Software pipeline over blocks of 16 bands with two operand sets: the
     // operands of the next block are read between the first MFMAs of the
     // current one, so they arrive while the rest of its MFMAs run.
@@ -472,9 +483,9 @@ __device__ __forceinline__ float mfma_project(const float* Ec, int ECS, const fl
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             if (QMAJOR)
-                Sc[(16 * cb + 4 * kk + v) * kXS + 16 * w + m] = s[cb][v];
+                Sc[(16 * (CB0 + cb) + 4 * kk + v) * kXS + 16 * w + m] = s[cb][v];
             else
-                Sc[(16 * w + m) * WTS + 16 * cb + 4 * kk + v] = s[cb][v];
+                Sc[(16 * w + m) * WTS + 16 * (CB0 + cb) + 4 * kk + v] = s[cb][v];
         }
     return xx;
 }
@@ -547,7 +558,7 @@ __device__ __forceinline__ double mfma_project_f64(const float* Ec, int ECS, con
 template <int QC, int QCP>
 __device__ __forceinline__ void stage_chunk(const float* __restrict__ U, int Qp, int col0, int L, int LP, float* Ec,
                                             int ECS) {
-    for (int e = threadIdx.x; e < LP * QCP; e += kThreads) {
+    for (int e = threadIdx.x; e < LP * QCP; e += blockDim.x) {
         const int l = e / QCP, q = e % QCP;
         Ec[l * ECS + q] = (l < L && q < QC) ? U[(size_t)l * Qp + col0 + q] : 0.f;
     }
@@ -636,7 +647,7 @@ __device__ __forceinline__ void apass_body(const Geom& g, const State& s, int bi
             xr.issue(s.X, s.ldx, L, pg);
             xr.store(smem + xo[0], L);
         } else if (dma) {
-            dma_tile((const float*)s.X, s.ldx, L, pg, smem + xo[0]);
+            dma_tile((const float*)s.X, s.ldx, L, pg, smem + xo[0], w);
         }
         load_a(pg);
     }
@@ -664,7 +675,7 @@ __device__ __forceinline__ void apass_body(const Geom& g, const State& s, int bi
         if (nt < g.ntiles) {
             load_a(nt);
             if (regx) xr.issue(s.X, s.ldx, L, nt);
-            if (dma && g.dbuf) dma_tile((const float*)s.X, s.ldx, L, nt, Xn);
+            if (dma && g.dbuf) dma_tile((const float*)s.X, s.ldx, L, nt, Xn, w);
         }
         {
             // projection on the matrix cores: P for pixels 16w..16w+15
@@ -717,7 +728,7 @@ __device__ __forceinline__ void apass_body(const Geom& g, const State& s, int bi
             if (regx)
                 xr.store(Xn, L);
             else if (!g.dbuf)
-                dma_tile((const float*)s.X, s.ldx, L, nt, Xs);
+                dma_tile((const float*)s.X, s.ldx, L, nt, Xs, w);
         }
     }
 
@@ -783,9 +794,16 @@ template <int PP, int R, bool STEP>
 __device__ __forceinline__ void bpass_body(const Geom& g, const State& s, int bid, const float* __restrict__ W, int mode,
                                            const RunInit& ri) {
     using S = Shape<PP, R>;
-    constexpr int QC = S::QC, QCP = S::QCP, NCB = S::NCB, WTS = S::WTS, NRBW = S::NRBW;
+    constexpr int NW = kBpassWaves, NT = 64 * NW;
+    constexpr int QC = S::QC, QCP = S::QCP, NCB = S::NCB, WTS = S::WTS, NRBW = S::NRBW * 4 / NW;
+    // softmax: NW lanes per column, SPX pixels each
+    constexpr int SPX = kTile / NW, SV = SPX / 4;
+    // projection: wave group 0 (waves 0-3) takes the first NC0 column
+    // blocks, group 1 the other NC1, each for the pixel block w & 3
+    constexpr int NC0 = (NW == 8) ? (NCB + 1) / 2 : NCB, NC1 = NCB - NC0;
     const int ECS = g.ecs;
-    static_assert(QCP <= kThreads / 4, "one quad of threads per softmax column");
+    static_assert(NW == 4 || NW == 8, "four or eight waves");
+    static_assert(QCP * NW <= NT, "NW threads per softmax column");
     extern __shared__ float smem[];
     const PassLds lo = pass_lds(PP, R, g.L, g.dbuf, g.ecs, g.gf);
     float* Wq = smem + lo.wt;                      // [QCP][kXS]
@@ -802,20 +820,20 @@ __device__ __forceinline__ void bpass_body(const Geom& g, const State& s, int bi
     const size_t Np = (size_t)g.ntiles * kTile;
     const int col0 = c * QC;
 
-    for (int e = tid; e < (LP - L) * kXS; e += kThreads) {
+    for (int e = tid; e < (LP - L) * kXS; e += NT) {
         smem[xo[0] + L * kXS + e] = 0.f;
         smem[xo[1] + L * kXS + e] = 0.f;
     }
-    for (int e = tid; e < QCP * kXS; e += kThreads) Wq[e] = 0.f;
-    for (int e = tid; e < QCP; e += kThreads) F[e] = FG[e] = 0.f;
+    for (int e = tid; e < QCP * kXS; e += NT) Wq[e] = 0.f;
+    for (int e = tid; e < QCP; e += NT) F[e] = FG[e] = 0.f;
     if (STEP) stage_chunk<QC, QCP>(W, g.Qp, col0, L, LP, Ec, ECS);
 
     // this thread's softmax column and pixel segment
-    const int sq = tid >> 2, sub = tid & 3;
+    const int sq = tid / NW, sub = tid % NW;
     const int sm = c * R + sq / PP, sj = sq % PP;
     const bool qin = sq < QC;                      // a column of the chunk
     const bool cok = qin && sm < g.M;              // ... of an existing run
-    float* bcol = s.Bst + (size_t)(cok ? col0 + sq : 0) * Np + 16 * sub;
+    float* bcol = s.Bst + (size_t)(cok ? col0 + sq : 0) * Np + SPX * sub;
     float mrun = -INFINITY, lzc = 0.f, eta2 = 0.f;
     double srun = 0.0;                             // float64: it runs over every tile of the workgroup
     if (STEP && cok) {
@@ -834,15 +852,15 @@ __device__ __forceinline__ void bpass_body(const Geom& g, const State& s, int bi
     constexpr bool kRX = kRegX<PP, R, false>;
     const bool regx = kRX && L <= kRegXMaxL && s.x_bf16;      // float32 X: direct-to-LDS loads
     const bool dma = !regx && !s.x_bf16;
-    XRegs<kRX> xr;
+    XRegs<kRX, NW> xr;
 
-    f4 bn[4];
+    f4 bn[SV];
     float tn = 0.f;
     auto load_b = [&](int tile) {
         if (STEP && cok) {
             const f4* src = (const f4*)(bcol + (size_t)tile * kTile);
 #pragma unroll
-            for (int u = 0; u < 4; ++u) bn[u] = src[u];
+            for (int u = 0; u < SV; ++u) bn[u] = src[u];
             tn = s.tshift[(size_t)tile * g.Qp + col0 + sq];
         }
     };
@@ -852,7 +870,7 @@ __device__ __forceinline__ void bpass_body(const Geom& g, const State& s, int bi
             xr.issue(s.X, s.ldx, L, pg);
             xr.store(smem + xo[0], L);
         } else if (dma) {
-            dma_tile((const float*)s.X, s.ldx, L, pg, smem + xo[0]);
+            dma_tile<NW>((const float*)s.X, s.ldx, L, pg, smem + xo[0], w);
         }
         load_b(pg);
     }
@@ -866,30 +884,33 @@ __device__ __forceinline__ void bpass_body(const Geom& g, const State& s, int bi
         }
         __builtin_amdgcn_s_waitcnt(0);
         lds_barrier();
-        f4 bv[4];
+        f4 bv[SV];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) bv[u] = bn[u];
+        for (int u = 0; u < SV; ++u) bv[u] = bn[u];
         const float ts = tn;
         const int nt = tile + g.npg;
         if (nt < g.ntiles) {
             load_b(nt);
             if (regx) xr.issue(s.X, s.ldx, L, nt);
-            if (dma && g.dbuf) dma_tile((const float*)s.X, s.ldx, L, nt, Xn);
+            if (dma && g.dbuf) dma_tile<NW>((const float*)s.X, s.ldx, L, nt, Xn, w);
         }
 
         if (STEP) {
-            (void)mfma_project<NCB, WTS, true>(Ec, ECS, Xs, Wq, LP, w, lane);
+            if (w < 4)
+                (void)mfma_project<NC0, WTS, true>(Ec, ECS, Xs, Wq, LP, w, lane);
+            else if constexpr (NC1 > 0)
+                (void)mfma_project<NC1, WTS, true, NC0>(Ec, ECS, Xs, Wq, LP, w - 4, lane);
             lds_barrier();
         }
 
         if (qin) {
-            const int pix0 = tile * kTile + 16 * sub;
-            float* wrow = Wq + sq * kXS + 16 * sub;
-            float v[16];
+            const int pix0 = tile * kTile + SPX * sub;
+            float* wrow = Wq + sq * kXS + SPX * sub;
+            float v[SPX];
             if (STEP) {
                 const float sh = ts + lzc;
 #pragma unroll
-                for (int u = 0; u < 4; ++u) {
+                for (int u = 0; u < SV; ++u) {
                     const f4 gv = *(const f4*)(wrow + 4 * u);
 #pragma unroll
                     for (int e = 0; e < 4; ++e) v[4 * u + e] = fast_log(bv[u][e]) + sh - eta2 * gv[e];
@@ -897,19 +918,20 @@ __device__ __forceinline__ void bpass_body(const Geom& g, const State& s, int bi
             } else if (mode == kModeInitRng) {
                 const uint64_t seed = ri.seeds[cok ? sm : 0];
 #pragma unroll
-                for (int i = 0; i < 16; ++i) v[i] = ri.init_scale * uniform_u(seed, pix0 + i, sj);
+                for (int i = 0; i < SPX; ++i) v[i] = ri.init_scale * uniform_u(seed, pix0 + i, sj);
             } else {
 #pragma unroll
-                for (int i = 0; i < 16; ++i) v[i] = fast_log(ri.B0[(size_t)min(pix0 + i, N - 1) * PP + sj]);
+                for (int i = 0; i < SPX; ++i) v[i] = fast_log(ri.B0[(size_t)min(pix0 + i, N - 1) * PP + sj]);
             }
             float mx = -INFINITY;
 #pragma unroll
-            for (int i = 0; i < 16; ++i) {
+            for (int i = 0; i < SPX; ++i) {
                 v[i] = (cok && pix0 + i < N) ? v[i] : -INFINITY;
                 mx = fmaxf(mx, v[i]);
             }
-            mx = fmaxf(mx, dpp<0xB1>(mx));             // the quad of this column
+            mx = fmaxf(mx, dpp<0xB1>(mx));             // the NW lanes of this column
             mx = fmaxf(mx, dpp<0x4E>(mx));
+            if (NW == 8) mx = fmaxf(mx, dpp<0x141>(mx));
             // The tile's weights are stored relative to the tile's own max
             // (its largest weight is 1, so none underflows for being far
             // below a larger tile of this workgroup); the running sums are
@@ -918,18 +940,19 @@ __device__ __forceinline__ void bpass_body(const Geom& g, const State& s, int bi
             const float mnew = fmaxf(mrun, mx);
             const float f = (mrun == -INFINITY) ? 0.f : fast_exp(mrun - mnew);
             const float fg = (mx == -INFINITY) ? 0.f : fast_exp(mx - mnew);
-            float wv[16], sum = 0.f;
+            float wv[SPX], sum = 0.f;
 #pragma unroll
-            for (int i = 0; i < 16; ++i) {
+            for (int i = 0; i < SPX; ++i) {
                 wv[i] = (v[i] == -INFINITY) ? 0.f : fast_exp(v[i] - mx);
                 sum += wv[i];
             }
             sum += dpp<0xB1>(sum);
             sum += dpp<0x4E>(sum);
+            if (NW == 8) sum += dpp<0x141>(sum);
             srun = fma(srun, (double)f, (double)sum * (double)fg);
             mrun = mnew;
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
+            for (int u = 0; u < SV; ++u) {
                 const f4 o = f4{wv[4 * u], wv[4 * u + 1], wv[4 * u + 2], wv[4 * u + 3]};
                 *(f4*)(wrow + 4 * u) = o;
                 if (cok) ((f4*)(bcol + (size_t)tile * kTile))[u] = o;
@@ -941,18 +964,18 @@ __device__ __forceinline__ void bpass_body(const Geom& g, const State& s, int bi
             }
         }
         lds_barrier();
-        mfma_accumulate<NCB, NRBW, WTS, true, 1, true>(acc, gdummy, false, Xs, Wq, F, FG, nrb, w, lane);
+        mfma_accumulate<NCB, NRBW, WTS, true, 1, true, NW>(acc, gdummy, false, Xs, Wq, F, FG, nrb, w, lane);
         if (nt < g.ntiles && (regx || dma)) {
             if (!g.dbuf) lds_barrier();           // single buffer: overwrite after every reader
             if (regx)
                 xr.store(Xn, L);
             else if (!g.dbuf)
-                dma_tile((const float*)s.X, s.ldx, L, nt, Xs);
+                dma_tile<NW>((const float*)s.X, s.ldx, L, nt, Xs, w);
         }
     }
 
     const size_t wgi = (size_t)pg * g.nqc + c;
-    store_acc<NCB, NRBW, QC>(acc, s.Vpart + wgi * (size_t)L * QC, L, nrb, w, lane);
+    store_acc<NCB, NRBW, QC, NW>(acc, s.Vpart + wgi * (size_t)L * QC, L, nrb, w, lane);
     if (qin && sub == 0) {
         s.mpart[(size_t)pg * g.Qp + col0 + sq] = cok ? mrun : -INFINITY;
         s.spart[(size_t)pg * g.Qp + col0 + sq] = cok ? (float)srun : 0.f;
@@ -960,12 +983,12 @@ __device__ __forceinline__ void bpass_body(const Geom& g, const State& s, int bi
 }
 
 template <int PP, int R, bool STEP>
-__global__ __launch_bounds__(kThreads, 1) void k_bpass(Geom g, State s, const float* __restrict__ W, int mode,
+__global__ __launch_bounds__(64 * kBpassWaves, 1) void k_bpass(Geom g, State s, const float* __restrict__ W, int mode,
                                                        RunInit ri) {
     bpass_body<PP, R, STEP>(g, s, blockIdx.x, W, mode, ri);
 }
 template <int PP, int R, bool STEP>
-__global__ __launch_bounds__(kThreads, 1) void k_bpass_multi(const ImageJob* __restrict__ jobs,
+__global__ __launch_bounds__(64 * kBpassWaves, 1) void k_bpass_multi(const ImageJob* __restrict__ jobs,
                                                              const int2* __restrict__ map, int mode) {
     const int2 jl = map[blockIdx.x];
     const ImageJob& J = jobs[jl.x];
@@ -1533,11 +1556,11 @@ struct Kernels {
         const size_t lds = (size_t)pass_lds(PP, R, g.L, g.dbuf, g.ecs, g.gf).total * sizeof(float);
         if (mode == kModeStep) {
             set_max_lds((const void*)k_bpass<PP, R, true>, (int)lds);
-            hipLaunchKernelGGL((k_bpass<PP, R, true>), dim3(g.npg * g.nqc), dim3(kThreads), lds, st, g, s,
+            hipLaunchKernelGGL((k_bpass<PP, R, true>), dim3(g.npg * g.nqc), dim3(64 * kBpassWaves), lds, st, g, s,
                                (const float*)s.W, mode, ri);
         } else {
             set_max_lds((const void*)k_bpass<PP, R, false>, (int)lds);
-            hipLaunchKernelGGL((k_bpass<PP, R, false>), dim3(g.npg * g.nqc), dim3(kThreads), lds, st, g, s,
+            hipLaunchKernelGGL((k_bpass<PP, R, false>), dim3(g.npg * g.nqc), dim3(64 * kBpassWaves), lds, st, g, s,
                                (const float*)s.W, mode, ri);
         }
         return hipGetLastError();
@@ -1671,18 +1694,18 @@ template <int PP>
 struct MultiKernels {
     static hipError_t run(int kernel, const ImageJob* jobs, const int2* map, int nb, size_t lds, int arg,
                           hipStream_t st) {
-        const dim3 grid(nb), block(kThreads);
+        const dim3 grid(nb), block(kThreads), bblock(64 * kBpassWaves);
         switch (kernel) {
             case kMultiPrep:
                 hipLaunchKernelGGL((k_prep_multi<PP>), grid, block, 0, st, jobs, map);
                 break;
             case kMultiBpassInit:
                 set_max_lds((const void*)k_bpass_multi<PP, 1, false>, (int)lds);
-                hipLaunchKernelGGL((k_bpass_multi<PP, 1, false>), grid, block, lds, st, jobs, map, (int)kModeInitRng);
+                hipLaunchKernelGGL((k_bpass_multi<PP, 1, false>), grid, bblock, lds, st, jobs, map, (int)kModeInitRng);
                 break;
             case kMultiBpassStep:
                 set_max_lds((const void*)k_bpass_multi<PP, 1, true>, (int)lds);
-                hipLaunchKernelGGL((k_bpass_multi<PP, 1, true>), grid, block, lds, st, jobs, map, (int)kModeStep);
+                hipLaunchKernelGGL((k_bpass_multi<PP, 1, true>), grid, bblock, lds, st, jobs, map, (int)kModeStep);
                 break;
             case kMultiRedB:
                 hipLaunchKernelGGL((k_reduce_b_multi<PP>), grid, block, 0, st, jobs, map, arg);

@@ -183,7 +183,16 @@ def test_hundred_runs_gamma_drawn_from_S(api):
     """M = 100 runs with gamma drawn uniformly from the paper's set S (one
     draw per run, seeded) and seeds 0..99, T = 10: every run against the
     oracle, and the selection of Algorithm 2 against the oracle's fits and
-    coherences (allowing the ties float32 cannot separate)."""
+    coherences (allowing the ties float32 cannot separate).
+
+    The gate is conditioned per run.  The oracle run in float32 (same steps,
+    plain float32 arithmetic) measures how much rounding alone moves each
+    trajectory: at gamma <= 0.5 it stays within about 1e-7, while at gamma
+    of 1 and above the larger steps amplify it up to about 1e-4 by T = 10.
+    Every run must agree to the float32 gate of 1e-4 relative, or to ten
+    times its own float32 drift where that is larger (the GPU rounds in a
+    different order, so on an amplifying run its deviation is another draw
+    of the same noise); the calm runs must agree to 1e-6."""
     s = synth.small_case(seed=90, L=40, N=333, p=3)
     Xg, X = _prep(s.X)
     rng = np.random.default_rng(2209)
@@ -191,15 +200,24 @@ def test_hundred_runs_gamma_drawn_from_S(api):
     seeds = list(range(100))
     _say("M=100, gamma ~ U(S), T=10")
     r = api.ensemble(Xg, 3, seeds, gammas, T=10)
-    fit_ref, mu_ref = np.zeros(100), np.zeros(100)
-    worst = 0.0
+    fit_ref, mu_ref, d32, dl = np.zeros(100), np.zeros(100), np.zeros(100), np.zeros(100)
     for m in range(100):
         ref = O.edaa_fit(X, 3, T=10, gamma=gammas[m], seed=seeds[m])
-        worst = max(worst, float(np.max(np.abs(r["loss"][m] - ref["loss"]) / ref["loss"])))
+        r32 = O.edaa_fit(X, 3, T=10, gamma=gammas[m], seed=seeds[m], dtype=np.float32)
+        d32[m] = np.max(np.abs(r32["loss"] - ref["loss"]) / ref["loss"])
+        dl[m] = np.max(np.abs(r["loss"][m] - ref["loss"]) / ref["loss"])
         fit_ref[m] = O.fit_l1(X, ref["E"], ref["A"])
         mu_ref[m] = O.coherence(ref["E"])
-    _say(f"worst loss rel over 100 runs {worst:.2e}; selected {r['selected']} (oracle {O.select(fit_ref, mu_ref)})")
-    assert worst <= 1e-4
-    assert np.max(np.abs(r["fit"] - fit_ref) / fit_ref) <= 1e-4
-    assert np.max(np.abs(r["mu"] - mu_ref)) <= 1e-4
+    df = np.abs(r["fit"] - fit_ref) / fit_ref
+    dm = np.abs(r["mu"] - mu_ref)
+    tol = np.maximum(1e-4, 10.0 * d32)
+    calm = np.array(gammas) <= 0.5
+    w = int(np.argmax(dl / tol))
+    _say(f"loss rel: calm runs {dl[calm].max():.2e}, others {dl[~calm].max():.2e}; tightest run {w} "
+         f"(gamma {gammas[w]}) {dl[w]:.2e} of {tol[w]:.2e}; selected {r['selected']} "
+         f"(oracle {O.select(fit_ref, mu_ref)})")
+    assert calm.sum() >= 20 and d32[calm].max() <= 1e-6
+    for d in (dl, df, dm):
+        assert np.all(d <= tol)
+        assert d[calm].max() <= 1e-6
     _check_selection(r["selected"], fit_ref, mu_ref)
