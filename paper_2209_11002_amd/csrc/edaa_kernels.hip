@@ -38,6 +38,10 @@ namespace {
 // (their issue, about 55 clocks each, stalls the issuing wave); both waves
 // share the one LDS allocation.
 constexpr int kBpassWaves = 8;
+// Waves per workgroup of the A-step pass: eight up to p = 9; above, the
+// per-pixel A-steps (p x p products on p-vectors in registers) need more
+// than the 256 registers a wave has at two waves per SIMD.
+constexpr int apass_waves(int p) { return p <= 9 ? 8 : 4; }
 constexpr int kXS = 68;   // LDS pitch (floats) of an X tile row of 64 pixels
 
 typedef float f4 __attribute__((ext_vector_type(4)));
@@ -497,7 +501,7 @@ __device__ __forceinline__ float mfma_project(const float* Ec, int ECS, const fl
 // P is kept as a float pair, hi = fl(P) (used by the A-steps) and
 // lo = fl(P - hi), which carries it to about 48 bits; returns the partial
 // ||x||^2 of this lane's bands.
-template <int NCB, int WTS>
+template <int NCB, int WTS, int CB0 = 0>
 __device__ __forceinline__ double mfma_project_f64(const float* Ec, int ECS, const float* Xs, float* Sc, float* Plo,
                                                    int LP, int w, int lane) {
     const int m = lane & 15, kk = lane >> 4;
@@ -506,7 +510,7 @@ __device__ __forceinline__ double mfma_project_f64(const float* Ec, int ECS, con
     for (int cb = 0; cb < NCB; ++cb) s[cb] = d4{0.0, 0.0, 0.0, 0.0};
     double xx = 0.0;
     const float* xb = Xs + 4 * kk * kXS + 16 * w + m;
-    const float* eb = Ec + 4 * kk * ECS + m;
+    const float* eb = Ec + 4 * kk * ECS + 16 * CB0 + m;
     // same software pipeline as mfma_project
     float b0[4], e0[4][NCB], b1[4], e1[4][NCB];
     auto load = [&](float (&b)[4], float (&e)[4][NCB], int k0) {
@@ -548,8 +552,8 @@ __device__ __forceinline__ double mfma_project_f64(const float* Ec, int ECS, con
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             const float hi = (float)s[cb][v];
-            Sc[(16 * w + m) * WTS + 16 * cb + 4 * v + kk] = hi;
-            Plo[(16 * w + m) * WTS + 16 * cb + 4 * v + kk] = (float)(s[cb][v] - (double)hi);
+            Sc[(16 * w + m) * WTS + 16 * (CB0 + cb) + 4 * v + kk] = hi;
+            Plo[(16 * w + m) * WTS + 16 * (CB0 + cb) + 4 * v + kk] = (float)(s[cb][v] - (double)hi);
         }
     return xx;
 }
@@ -571,9 +575,16 @@ __device__ __forceinline__ void stage_chunk(const float* __restrict__ U, int Qp,
 template <int PP, int R>
 __device__ __forceinline__ void apass_body(const Geom& g, const State& s, int bid, const float* __restrict__ E, int K1) {
     using S = Shape<PP, R>;
-    constexpr int QC = S::QC, QCP = S::QCP, NCB = S::NCB, WTS = S::WTS, RW = S::RW, NRBW = S::NRBW;
+    constexpr int NW = apass_waves(PP), NT = 64 * NW;
+    constexpr int QC = S::QC, QCP = S::QCP, NCB = S::NCB, WTS = S::WTS;
+    constexpr int RW = (R + NW - 1) / NW;          // runs per wave in the A-step phase (r = w + NW k < R)
+    constexpr int NRBW = S::NRBW * 4 / NW;          // accumulation row blocks per wave
+    constexpr int NGBW = (S::NGB + NW - 1) / NW;    // Gram blocks per wave
+    // projection: waves w and w + 4 share the pixel block w & 3 (eight
+    // waves), waves 0-3 taking the first NC0 column blocks
+    constexpr int NC0 = (NW == 8) ? (NCB + 1) / 2 : NCB, NC1 = NCB - NC0;
+    static_assert(NW == 4 || NW == 8, "four or eight waves");
     const int ECS = g.ecs;
-    constexpr int NGBW = S::NGBW;
     extern __shared__ float smem[];
     const PassLds lo = pass_lds(PP, R, g.L, g.dbuf, g.ecs, g.gf);
     float* Wt = smem + lo.wt;
@@ -597,7 +608,7 @@ __device__ __forceinline__ void apass_body(const Geom& g, const State& s, int bi
     // consistent with that E).
     stage_chunk<QC, QCP>(E, g.Qp, col0, L, LP, Ec, ECS);
     __syncthreads();
-    for (int e = tid; e < R * PP * PP; e += kThreads) {
+    for (int e = tid; e < R * PP * PP; e += NT) {
         const int r = e / (PP * PP), jk = e % (PP * PP), j = jk / PP, k = jk % PP;
         const float* Ek = Ec + r * PP;
         double acc = 0.0;
@@ -607,11 +618,11 @@ __device__ __forceinline__ void apass_body(const Geom& g, const State& s, int bi
     }
     __syncthreads();
     // zero the X rows beyond L and the weight padding (never written later)
-    for (int e = tid; e < (LP - L) * kXS; e += kThreads) {
+    for (int e = tid; e < (LP - L) * kXS; e += NT) {
         smem[xo[0] + L * kXS + e] = 0.f;
         smem[xo[1] + L * kXS + e] = 0.f;
     }
-    for (int e = tid; e < kTile * WTS; e += kThreads) Wt[e] = 0.f;
+    for (int e = tid; e < kTile * WTS; e += NT) Wt[e] = 0.f;
 
     d4 acc[NRBW][NCB], gram[NGBW];
 #pragma unroll
@@ -629,14 +640,14 @@ __device__ __forceinline__ void apass_body(const Geom& g, const State& s, int bi
     constexpr bool kRX = kRegX<PP, R, true>;
     const bool regx = kRX && L <= kRegXMaxL && s.x_bf16;      // float32 X: direct-to-LDS loads
     const bool dma = !regx && !s.x_bf16;
-    XRegs<kRX> xr;
+    XRegs<kRX, NW> xr;
 
     float an[RW][PP];
     auto load_a = [&](int tile) {
         const size_t pixc = (size_t)min(tile * kTile + lane, N - 1);
 #pragma unroll
         for (int k = 0; k < RW; ++k) {
-            const int m = c * R + min(w + 4 * k, R - 1);
+            const int m = c * R + min(w + NW * k, R - 1);
 #pragma unroll
             for (int j = 0; j < PP; ++j) an[k][j] = A[(size_t)(min(m, g.M - 1) * PP + j) * N + pixc];
         }
@@ -647,7 +658,7 @@ __device__ __forceinline__ void apass_body(const Geom& g, const State& s, int bi
             xr.issue(s.X, s.ldx, L, pg);
             xr.store(smem + xo[0], L);
         } else if (dma) {
-            dma_tile((const float*)s.X, s.ldx, L, pg, smem + xo[0], w);
+            dma_tile<NW>((const float*)s.X, s.ldx, L, pg, smem + xo[0], w);
         }
         load_a(pg);
     }
@@ -666,8 +677,8 @@ __device__ __forceinline__ void apass_body(const Geom& g, const State& s, int bi
         float a[RW][PP];
 #pragma unroll
         for (int k = 0; k < RW; ++k) {
-            const int m = c * R + w + 4 * k;
-            const bool mok = m < g.M && w + 4 * k < R;
+            const int m = c * R + w + NW * k;
+            const bool mok = m < g.M && w + NW * k < R;
 #pragma unroll
             for (int j = 0; j < PP; ++j) a[k][j] = (mok && pok) ? an[k][j] : 0.f;
         }
@@ -675,20 +686,25 @@ __device__ __forceinline__ void apass_body(const Geom& g, const State& s, int bi
         if (nt < g.ntiles) {
             load_a(nt);
             if (regx) xr.issue(s.X, s.ldx, L, nt);
-            if (dma && g.dbuf) dma_tile((const float*)s.X, s.ldx, L, nt, Xn, w);
+            if (dma && g.dbuf) dma_tile<NW>((const float*)s.X, s.ldx, L, nt, Xn, w);
         }
         {
             // projection on the matrix cores: P for pixels 16w..16w+15
-            double xx = mfma_project_f64<NCB, WTS>(Ec, ECS, Xs, Wt, Plo, LP, w, lane);
-            xx += __shfl_xor(xx, 16);       // the 4 band classes of the pixel
-            xx += __shfl_xor(xx, 32);
-            if (lane < 16) XX[16 * w + lane] = xx;
+            // (16 (w - 4).. with eight waves, w >= 4)
+            if (w < 4) {
+                double xx = mfma_project_f64<NC0, WTS>(Ec, ECS, Xs, Wt, Plo, LP, w, lane);
+                xx += __shfl_xor(xx, 16);       // the 4 band classes of the pixel
+                xx += __shfl_xor(xx, 32);
+                if (lane < 16) XX[16 * w + lane] = xx;
+            } else if constexpr (NC1 > 0) {
+                (void)mfma_project_f64<NC1, WTS, NC0>(Ec, ECS, Xs, Wt, Plo, LP, w - 4, lane);
+            }
             lds_barrier();
-            // A-steps: lane = pixel, runs r = w + 4k of the chunk
+            // A-steps: lane = pixel, runs r = w + NW k of the chunk
             const double xnorm = XX[lane];
 #pragma unroll
             for (int k = 0; k < RW; ++k) {
-                const int r = w + 4 * k, m = c * R + r;
+                const int r = w + NW * k, m = c * R + r;
                 if (r >= R) continue;                 // uniform per wave
                 const bool mok = m < g.M;
                 float P[PP];
@@ -722,18 +738,19 @@ __device__ __forceinline__ void apass_body(const Geom& g, const State& s, int bi
             }
         }
         lds_barrier();
-        mfma_accumulate<NCB, NRBW, WTS, false, NGBW>(acc, gram, true, Xs, Wt, nullptr, nullptr, nrb, w, lane);
+        mfma_accumulate<NCB, NRBW, WTS, false, NGBW, false, NW>(acc, gram, true, Xs, Wt, nullptr, nullptr, nrb, w,
+                                                                lane);
         if (nt < g.ntiles && (regx || dma)) {
             if (!g.dbuf) lds_barrier();           // single buffer: overwrite after every reader
             if (regx)
                 xr.store(Xn, L);
             else if (!g.dbuf)
-                dma_tile((const float*)s.X, s.ldx, L, nt, Xs, w);
+                dma_tile<NW>((const float*)s.X, s.ldx, L, nt, Xs, w);
         }
     }
 
     const size_t wgi = (size_t)pg * g.nqc + c;
-    store_acc<NCB, NRBW, QC>(acc, s.Vpart + wgi * (size_t)L * QC, L, nrb, w, lane);
+    store_acc<NCB, NRBW, QC, NW>(acc, s.Vpart + wgi * (size_t)L * QC, L, nrb, w, lane);
     // A A^T of every run from the Gram blocks: entry (q1, q2) of block
     // (qb1, qb2) with q1 = 16 qb1 + 4 (lane/16) + v, q2 = 16 qb2 + lane%16.
     {
@@ -741,7 +758,7 @@ __device__ __forceinline__ void apass_body(const Geom& g, const State& s, int bi
         float* AAp = s.AApart + wgi * (size_t)(R * PP * PP);
 #pragma unroll
         for (int gi = 0; gi < NGBW; ++gi) {
-            const int gb = w + 4 * gi;
+            const int gb = w + NW * gi;
             if (gb < 2 * NCB - 1) {
                 const int qb1 = gb >> 1, qb2 = qb1 + (gb & 1);
 #pragma unroll
@@ -758,7 +775,7 @@ __device__ __forceinline__ void apass_body(const Geom& g, const State& s, int bi
     }
 #pragma unroll
     for (int k = 0; k < RW; ++k) {
-        const int r = w + 4 * k, m = c * R + r;
+        const int r = w + NW * k, m = c * R + r;
         if (r >= R) continue;
         const double tot = wave_sum(lacc[k]);
         if (lane == 0 && m < g.M) s.lpart[(size_t)pg * g.M + m] = tot;
@@ -766,11 +783,11 @@ __device__ __forceinline__ void apass_body(const Geom& g, const State& s, int bi
 }
 
 template <int PP, int R>
-__global__ __launch_bounds__(kThreads, 1) void k_apass(Geom g, State s, const float* __restrict__ E, int K1) {
+__global__ __launch_bounds__(64 * apass_waves(PP), 1) void k_apass(Geom g, State s, const float* __restrict__ E, int K1) {
     apass_body<PP, R>(g, s, blockIdx.x, E, K1);
 }
 template <int PP, int R>
-__global__ __launch_bounds__(kThreads, 1) void k_apass_multi(const ImageJob* __restrict__ jobs, const int2* __restrict__ map,
+__global__ __launch_bounds__(64 * apass_waves(PP), 1) void k_apass_multi(const ImageJob* __restrict__ jobs, const int2* __restrict__ map,
                                                              int K1) {
     const int2 jl = map[blockIdx.x];
     const ImageJob& J = jobs[jl.x];
@@ -1549,7 +1566,7 @@ struct Kernels {
     static hipError_t apass(const Geom& g, const State& s, int K1, hipStream_t st) {
         const size_t lds = (size_t)pass_lds(PP, R, g.L, g.dbuf, g.ecs, g.gf).total * sizeof(float);
         set_max_lds((const void*)k_apass<PP, R>, (int)lds);
-        hipLaunchKernelGGL((k_apass<PP, R>), dim3(g.npg * g.nqc), dim3(kThreads), lds, st, g, s, (const float*)s.E, K1);
+        hipLaunchKernelGGL((k_apass<PP, R>), dim3(g.npg * g.nqc), dim3(64 * apass_waves(PP)), lds, st, g, s, (const float*)s.E, K1);
         return hipGetLastError();
     }
     static hipError_t bpass(const Geom& g, const State& s, int mode, const RunInit& ri, hipStream_t st) {
@@ -1694,7 +1711,7 @@ template <int PP>
 struct MultiKernels {
     static hipError_t run(int kernel, const ImageJob* jobs, const int2* map, int nb, size_t lds, int arg,
                           hipStream_t st) {
-        const dim3 grid(nb), block(kThreads), bblock(64 * kBpassWaves);
+        const dim3 grid(nb), block(kThreads), bblock(64 * kBpassWaves), ablock(64 * apass_waves(PP));
         switch (kernel) {
             case kMultiPrep:
                 hipLaunchKernelGGL((k_prep_multi<PP>), grid, block, 0, st, jobs, map);
@@ -1715,7 +1732,7 @@ struct MultiKernels {
                 break;
             case kMultiApass:
                 set_max_lds((const void*)k_apass_multi<PP, 1>, (int)lds);
-                hipLaunchKernelGGL((k_apass_multi<PP, 1>), grid, block, lds, st, jobs, map, arg);
+                hipLaunchKernelGGL((k_apass_multi<PP, 1>), grid, ablock, lds, st, jobs, map, arg);
                 break;
             case kMultiRedAA:
                 hipLaunchKernelGGL((k_reduce_aa_multi<PP>), grid, block, 0, st, jobs, map, arg);
