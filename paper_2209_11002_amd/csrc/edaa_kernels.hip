@@ -1146,7 +1146,14 @@ __device__ __forceinline__ void sliced_sum(const float* __restrict__ src, size_t
     const int o = tid % no, sl = tid / no;
     double acc = 0.0;
     if (sl < S)
-        for (int pg = sl; pg < npg; pg += S) acc += (double)src[(size_t)pg * stride + o];
+        for (int pg0 = sl; pg0 < npg; pg0 += 4 * S) {     // loads first, sums in the plain order
+            float v[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) v[u] = pg0 + u * S < npg ? src[(size_t)(pg0 + u * S) * stride + o] : 0.f;
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                if (pg0 + u * S < npg) acc += (double)v[u];
+        }
     red[tid] = acc;
     __syncthreads();
     if (tid < no) {
@@ -1244,10 +1251,22 @@ __device__ __forceinline__ void reduce_b_body(const Geom& g, const State& s, int
     const int col0 = c * QC, L = g.L;
     const int S = kThreads / QC, o = tid % QC, sl = tid / QC;
     const bool act = sl < S;
-    // column maxima over the workgroup partials
+    // column maxima over the workgroup partials; the partials of a slice are
+    // walked four at a time, loads first, the arithmetic in the same order
+    // as a plain walk
+    constexpr int U = 4;
     float mx = -INFINITY;
     if (act)
-        for (int pg = sl; pg < g.npg; pg += S) mx = fmaxf(mx, s.mpart[(size_t)pg * g.Qp + col0 + o]);
+        for (int pg0 = sl; pg0 < g.npg; pg0 += U * S) {
+            float v[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int pg = pg0 + u * S;
+                v[u] = pg < g.npg ? s.mpart[(size_t)pg * g.Qp + col0 + o] : -INFINITY;
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) mx = fmaxf(mx, v[u]);
+        }
     red[tid] = (double)mx;
     __syncthreads();
     if (tid < QC) {
@@ -1260,12 +1279,23 @@ __device__ __forceinline__ void reduce_b_body(const Geom& g, const State& s, int
     const float mq = Ms[o];
     double sa = 0.0, ea = 0.0;
     if (act && mq != -INFINITY)
-        for (int pg = sl; pg < g.npg; pg += S) {
-            const float mp = s.mpart[(size_t)pg * g.Qp + col0 + o];
-            if (mp == -INFINITY) continue;
-            const double f = (double)expf(mp - mq);
-            sa += (double)s.spart[(size_t)pg * g.Qp + col0 + o] * f;
-            ea += (double)s.Vpart[(((size_t)pg * g.nqc + c) * L + l) * QC + o] * f;
+        for (int pg0 = sl; pg0 < g.npg; pg0 += U * S) {
+            float mp[U], sp[U], vp[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int pg = pg0 + u * S;
+                const bool ok = pg < g.npg;
+                mp[u] = ok ? s.mpart[(size_t)pg * g.Qp + col0 + o] : -INFINITY;
+                sp[u] = ok ? s.spart[(size_t)pg * g.Qp + col0 + o] : 0.f;
+                vp[u] = ok ? s.Vpart[(((size_t)pg * g.nqc + c) * L + l) * QC + o] : 0.f;
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                if (mp[u] == -INFINITY) continue;
+                const double f = (double)expf(mp[u] - mq);
+                sa += (double)sp[u] * f;
+                ea += (double)vp[u] * f;
+            }
         }
     red[tid] = sa;
     __syncthreads();
