@@ -22,6 +22,8 @@ Paper passages followed:
     (eq. eta0A, eq. eta0B) and the defaults T = 100, K1 = K2 = 5.
   * Section "Model selection procedure": l1 fit, coherence (eq. coherence)
     and Algorithm 2 (model selection).
+  * Section "Experimental setup": abundance RMSE (eq. RMSE) and
+    spectral angle distance (eq. SAD).
 """
 import numpy as np
 
@@ -287,7 +289,7 @@ def ensemble(X, p, seeds, gammas, T=DEFAULT_T, K1=DEFAULT_K1, K2=DEFAULT_K2,
 
 
 def rmse_abundance(A_true, A_hat):
-    """eq. RMSE (Section "Metrics"): 100 sqrt(sum (A - A_hat)^2 / (p N))."""
+    """eq. RMSE (Section "Experimental setup"): 100 sqrt(sum (A - A_hat)^2 / (p N))."""
     A_true = np.asarray(A_true)
     return 100.0 * float(np.sqrt(np.mean((A_true - np.asarray(A_hat)) ** 2)))
 
@@ -299,3 +301,34 @@ def sad_degrees(M, E_hat):
     E_hat = np.asarray(E_hat, dtype=np.float64)
     c = np.sum(M * E_hat, axis=0) / (np.linalg.norm(M, axis=0) * np.linalg.norm(E_hat, axis=0))
     return float(np.mean(np.degrees(np.arccos(np.clip(c, -1.0, 1.0)))))
+
+
+def match_endmembers(M, E_hat):
+    """Pairing of estimated with reference endmembers before scoring.  The
+    paper does not say how the columns are paired (Section "Experimental
+    setup", eq. SAD); the reading taken is the pairing of least total
+    spectral angle, found here by trying every one of the p! pairings
+    (p <= 9).  Returns perm with E_hat[:, perm[i]] paired to M[:, i]."""
+    M = np.asarray(M, dtype=np.float64)
+    E_hat = np.asarray(E_hat, dtype=np.float64)
+    p = M.shape[1]
+    if p > 9:
+        raise ValueError("exhaustive pairing is limited to p <= 9")
+    import itertools
+    ang = np.zeros((p, p))                   # angle between M[:, i] and E_hat[:, j]
+    for i in range(p):
+        for j in range(p):
+            c = np.dot(M[:, i], E_hat[:, j]) / (np.linalg.norm(M[:, i]) * np.linalg.norm(E_hat[:, j]))
+            ang[i, j] = np.degrees(np.arccos(np.clip(c, -1.0, 1.0)))
+    perms = np.array(list(itertools.permutations(range(p))))
+    cost = ang[np.arange(p)[None, :], perms].sum(axis=1)
+    return [int(v) for v in perms[int(np.argmin(cost))]]
+
+
+def score(M, A, E_hat, A_hat):
+    """Global abundance RMSE (eq. RMSE) and SAD (eq. SAD) of an estimate
+    after pairing its endmembers with the reference ones."""
+    perm = match_endmembers(M, E_hat)
+    E_hat = np.asarray(E_hat, dtype=np.float64)[:, perm]
+    A_hat = np.asarray(A_hat, dtype=np.float64)[perm, :]
+    return dict(rmse=rmse_abundance(A, A_hat), sad=sad_degrees(M, E_hat), perm=perm)
