@@ -8,7 +8,10 @@
 
 namespace edaa {
 
-// A workgroup is 4 wave64s and works on tiles of 64 consecutive pixels.
+// The pass kernels work on tiles of 64 consecutive pixels.  kThreads is the
+// workgroup size of the kernels with 4 wave64s (reductions, the closing
+// pass, the A-pass above p = 9); the B-pass and the A-pass up to p = 9 use
+// 8 wave64s.
 constexpr int kTile = 64;
 constexpr int kThreads = 256;
 constexpr int kMaxL = 448;

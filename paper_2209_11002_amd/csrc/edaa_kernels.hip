@@ -261,11 +261,10 @@ struct Shape {
     static constexpr int QCP = (QC + 15) & ~15;         // padded to MFMA blocks of 16
     static constexpr int NCB = QCP / 16;                // column blocks
     static constexpr int WTS = QCP + 1;                 // LDS pitch of the per-pixel weight rows
-    static constexpr int RW = (R + 3) / 4;              // runs per wave in the A-step phase (r = w + 4k < R)
-    static constexpr int CPW = (QC + 3) / 4;            // softmax columns per wave (q = w + 4k)
-    static constexpr int NRBW = (R == 1) ? 8 : 4;       // accumulation row blocks per wave (L <= 512 / 256)
+    // accumulation row blocks of 16 bands per wave at four waves (L <= 512
+    // with R = 1, L <= 256 otherwise); a kernel with NW waves takes 4/NW of it
+    static constexpr int NRBW = (R == 1) ? 8 : 4;
     static constexpr int NGB = 2 * NCB - 1;             // Gram blocks (qb, qb) and (qb, qb+1)
-    static constexpr int NGBW = (NGB + 3) / 4;          // Gram blocks per wave
 };
 
 // LDS layout of a pass kernel, in floats.  LP = L rounded up to 16.
