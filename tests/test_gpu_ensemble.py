@@ -54,6 +54,8 @@ def _check_selection(sel, fit_ref, mu_ref, fit_tol=1e-4, mu_tol=1e-4):
     (6, 3, 40, 333, 10),      # 20 runs per chunk, 14 unused slots
     (10, 6, 37, 500, 8),      # 8 runs per chunk: two chunks, 6 unused slots
     (20, 12, 60, 257, 6),     # 4 runs per chunk: five full chunks
+    (8, 9, 45, 300, 6),       # p = 9: eight-wave A-pass, 4 runs per chunk (waves 4-7 hold no run)
+    (5, 10, 50, 300, 6),      # p = 10: four-wave A-pass
 ])
 def test_ensemble_matches_oracle_runs(api, M, p, L, N, T):
     _say(f"ensemble M={M} p={p} L={L} N={N} T={T}")
