@@ -74,7 +74,8 @@ __device__ __forceinline__ double wave_sum(double v) {
 
 // A DPP lane permutation within rows of 16 lanes (all rows and banks
 // enabled); the B-step softmax uses the quad permutes 0xB1 (lane ^ 1) and
-// 0x4E (lane ^ 2).
+// 0x4E (lane ^ 2), and the half-row mirror 0x141 (lane i <-> 7 - i within
+// 8 lanes).
 template <int CTRL>
 __device__ __forceinline__ float dpp(float v) {
     return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
@@ -151,7 +152,7 @@ __device__ __forceinline__ void wg_coords(const Geom& g, int b, int& pg, int& c)
 //    writes 16 B per lane to LDS once the loads have landed;
 //  - load_tile_sync: synchronous loads through registers (bf16 kernels
 //    without room for the staging registers, and the closing pass).
-constexpr int kRegXGroups = 16;     // row groups per wave: L <= 4 * 4 * 16 = 256
+constexpr int kRegXGroups = 16;     // row groups of 4 rows per wave at 4 waves: L <= 4 * 4 * 16 = 256
 
 // ON = false compiles to nothing (kernels without room for the registers).
 template <bool ON, int NW = 4>
@@ -799,12 +800,13 @@ __global__ __launch_bounds__(64 * apass_waves(PP), 1) void k_apass_multi(const I
 // the workgroup's running (max, sum); write the shifted weights and the
 // tile's shift; accumulate X * weights^T.
 //
-// Softmax layout: thread t owns column q = t / 4 of the chunk and the 16
-// pixels 16 (t % 4) .. +15 of the tile, so a column's tile max and sum take
-// two quad permutes and the running (max, sum) stays in the four lanes.  The
-// projection results and the weights live column-major in LDS ([QCP][kXS]).
-// Bst rows are padded to whole tiles (pixels >= N hold zero weights), so the
-// 16-pixel segments are read and written as float4 without bounds checks.
+// Softmax layout (NW waves): thread t owns column q = t / NW of the chunk
+// and the 64 / NW pixels (t % NW) * 64 / NW .. of the tile, so a column's
+// tile max and sum take two quad permutes (and a half-row mirror with eight
+// waves), and the running (max, sum) stays in those lanes.  The projection
+// results and the weights live column-major in LDS ([QCP][kXS]).  Bst rows
+// are padded to whole tiles (pixels >= N hold zero weights), so the pixel
+// segments are read and written as float4 without bounds checks.
 // --------------------------------------------------------------------------
 template <int PP, int R, bool STEP>
 __device__ __forceinline__ void bpass_body(const Geom& g, const State& s, int bid, const float* __restrict__ W, int mode,
