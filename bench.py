@@ -197,7 +197,7 @@ def main():
         summarize(args.summarize)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(run it with --gpus 1)", file=sys.stderr)
         sys.exit(2)
     if args.profile_run > 0:
