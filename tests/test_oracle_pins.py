@@ -485,3 +485,91 @@ def test_abundances_given_E_p2_closed_form():
     a1 = np.clip(((X - E[:, [1]]).T @ d) / (d @ d), 0.0, 1.0)
     r = O.abundances(X, E, T=4000, K1=5, gamma=1.0)
     assert np.max(np.abs(r["A"][0] - a1)) < 2e-3
+
+
+# --------------------------------------------------------------------------
+# Algorithm 1's order and the trace timing, pinned through the functions
+# already fixed above (the A-subproblem by brute force, the single updates
+# by their KKT conditions), so that a loop in the wrong order, a step that
+# reuses a stale residual or a trace taken at another point fails here.
+# --------------------------------------------------------------------------
+def _order_case():
+    s = synth.small_case(seed=81, L=18, N=120, p=3)
+    X, _ = O.normalize_pixels(s.X)
+    rng = np.random.default_rng(81)
+    # contrasted pixel weights (sparse Dirichlet columns), so that the
+    # endmembers X B0 differ and every step moves the iterate visibly
+    B0 = rng.dirichlet(np.full(120, 0.05), size=3).T
+    A0 = _rand_simplex_cols(rng, 3, 120)
+    e1, e2 = O.step_sizes(X, B0, 2.0)
+    return X, A0, B0, e1, e2
+
+
+def test_fit_with_B_frozen_equals_abundances_for_E_given():
+    """K2 = 0: B stays at B0, so Algorithm 1 reduces to the A-steps of
+    eq. update_A with E = X B0 fixed, which oracle.abundances runs and the
+    brute-force simplex least squares pins (test_abundances_given_E_*)."""
+    X, A0, B0, e1, e2 = _order_case()
+    r = O.edaa_fit(X, 3, T=7, K1=3, K2=0, B0=B0, A0=A0, eta=(e1, e2))
+    ref = O.abundances(X, X @ B0, T=7, K1=3, A0=A0, eta1=e1)
+    assert np.max(np.abs(r["A"] - ref["A"])) < 1e-12
+    assert np.max(np.abs(r["loss"] - ref["loss"]) / ref["loss"]) < 1e-12
+    assert np.array_equal(r["B"], B0)
+
+
+def test_fit_step_order_and_trace_points():
+    """Outer iterations built from the KKT-pinned single updates: K1 A-steps
+    on the current B, then K2 B-steps on the new A, each with a fresh
+    residual; trace[0] at (A0, B0) and trace[t] after outer iteration t."""
+    X, A0, B0, e1, e2 = _order_case()
+    K1, K2, T = 2, 3, 2
+    A, B = A0, B0
+    trace = [O.loss(X, A, B)]
+    for _ in range(T):
+        for _ in range(K1):
+            A = O.update_A(X, A, B, e1)
+        for _ in range(K2):
+            B = O.update_B(X, A, B, e2)
+        trace.append(O.loss(X, A, B))
+    r = O.edaa_fit(X, 3, T=T, K1=K1, K2=K2, B0=B0, A0=A0, eta=(e1, e2))
+    assert np.max(np.abs(r["A"] - A)) < 1e-13
+    assert np.max(np.abs(r["B"] - B)) < 1e-15
+    assert np.max(np.abs(r["loss"] - np.array(trace)) / np.array(trace)) < 1e-13
+    assert np.max(np.abs(r["E"] - X @ B)) < 1e-13
+
+    # the data separate the orders: B-steps first (or one residual for all
+    # the steps of a phase) would move the result by far more than rounding
+    Ab, Bb = A0, B0
+    for _ in range(T):
+        for _ in range(K2):
+            Bb = O.update_B(X, Ab, Bb, e2)
+        for _ in range(K1):
+            Ab = O.update_A(X, Ab, Bb, e1)
+    assert np.max(np.abs(Ab - A)) > 1e-6 and np.max(np.abs(Bb - B)) * 120 > 1e-6
+    R0 = X - (X @ B0) @ A0
+    with np.errstate(divide="ignore"):
+        As = O.softmax_cols(np.log(A0) + K1 * e1 * ((X @ B0).T @ R0))    # stale residual
+    assert np.max(np.abs(As - O.update_A(X, O.update_A(X, A0, B0, e1), B0, e1))) > 1e-6
+    # the trace is taken after the B-steps, not between the phases
+    A1 = O.update_A(X, O.update_A(X, A0, B0, e1), B0, e1)
+    assert abs(O.loss(X, A1, B0) - r["loss"][1]) > 1e-6 * r["loss"][1]
+
+
+def test_ensemble_non_finite_run_gets_infinite_fit():
+    """A run whose objective is not finite (here eta1 = inf from gamma = inf)
+    gets fit = +inf, so Algorithm 2 never selects it; the other runs are the
+    plain single runs."""
+    s = synth.small_case(seed=82, L=16, N=90, p=3)
+    X, _ = O.normalize_pixels(s.X)
+    with np.errstate(invalid="ignore", over="ignore"):
+        e = O.ensemble(X, 3, [0, 1, 2], [1.0, np.inf, 0.5], T=3)
+    assert not np.isfinite(e["runs"][1]["loss"][-1])
+    assert e["fit"][1] == np.inf
+    assert e["selected"] in (0, 2)
+    for m, g in ((0, 1.0), (2, 0.5)):
+        one = O.edaa_fit(X, 3, T=3, gamma=g, seed=m)
+        assert np.isfinite(e["fit"][m])
+        assert e["fit"][m] == O.fit_l1(X, one["E"], one["A"])
+    with np.errstate(invalid="ignore", over="ignore"):
+        e_all = O.ensemble(X, 3, [0, 1], [np.inf, np.inf], T=2)
+    assert np.all(e_all["fit"] == np.inf) and e_all["selected"] == -1
