@@ -46,9 +46,46 @@ def _x_dtype(X):
 
 
 def _check_x(X):
-    if not (X.is_cuda and X.dim() == 2 and X.is_contiguous()):
-        raise ValueError("X must be a contiguous 2-D [L, N] GPU tensor")
+    if not (isinstance(X, torch.Tensor) and X.dim() == 2 and X.is_contiguous()):
+        raise ValueError("X must be a contiguous 2-D [L, N] tensor")
+    _x_dtype(X)
+    if not X.is_cuda:
+        raise ValueError("X must be a GPU tensor")
     return X.shape[0], X.shape[1]
+
+
+def _check_f32(name, t, shape, device):
+    """t must be a contiguous float32 tensor of exactly `shape` on `device`
+    (the kernels read and write it through a raw pointer with that layout)."""
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a tensor")
+    if t.dtype != torch.float32:
+        raise TypeError(f"{name} must be float32, got {t.dtype}")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if t.device != device:
+        raise ValueError(f"{name} must be on {device}, got {t.device}")
+
+
+def _check_dense_operands(X, A, B):
+    """Operands of the objective and its gradients: X [L, N] float32 (these
+    kernels read float32 X only), A [p, N] and B [N, p] float32, all
+    contiguous and on X's device."""
+    if not (isinstance(X, torch.Tensor) and X.dim() == 2 and X.is_contiguous()):
+        raise ValueError("X must be a contiguous 2-D [L, N] tensor")
+    if X.dtype != torch.float32:
+        raise TypeError(f"X must be float32 for the objective and its gradients, got {X.dtype}")
+    Lb, N = X.shape
+    if not (isinstance(A, torch.Tensor) and A.dim() == 2):
+        raise ValueError("A must be a 2-D [p, N] tensor")
+    p = A.shape[0]
+    _check_f32("A", A, (p, N), X.device)
+    _check_f32("B", B, (N, p), X.device)
+    if not X.is_cuda:
+        raise ValueError("X must be a GPU tensor")
+    return Lb, N, p
 
 
 def _params(T, K1, K2, gamma, eta, init_scale, threshold, x_dtype, coherence, graph, time_passes=False):
@@ -91,8 +128,8 @@ def fit(X, p, T=100, K1=5, K2=5, gamma=1.0, seed=0, A0=None, B0=None, eta=None,
     B = torch.empty((N, p), dtype=torch.float32, device=dev)
     E = torch.empty((Lb, p), dtype=torch.float32, device=dev)
     for name, t, shp in (("A0", A0, (p, N)), ("B0", B0, (N, p))):
-        if t is not None and (t.dtype != torch.float32 or tuple(t.shape) != shp or not t.is_contiguous()):
-            raise ValueError(f"{name} must be a contiguous float32 tensor of shape {shp}")
+        if t is not None:
+            _check_f32(name, t, shp, dev)
     trace = (c_double * (T + 1))()
     eta_out = (c_double * 2)()
     P = _params(T, K1, K2, gamma, eta, init_scale, 1.05, _x_dtype(X), "cosine", graph, time_passes)
@@ -111,11 +148,12 @@ def abundances(X, E, T=100, K1=5, gamma=1.0, A0=None, eta1=None, graph=False):
     l2-normalised X [L, N].  Returns a dict: A [p, N] (tensor), loss (numpy,
     T+1), eta1."""
     Lb, N = _check_x(X)
-    if not (E.is_cuda and E.dtype == torch.float32 and E.dim() == 2 and E.shape[0] == Lb and E.is_contiguous()):
-        raise ValueError("E must be a contiguous float32 [L, p] GPU tensor")
+    if not (isinstance(E, torch.Tensor) and E.dim() == 2):
+        raise ValueError("E must be a 2-D [L, p] tensor")
     p = E.shape[1]
-    if A0 is not None and (A0.dtype != torch.float32 or tuple(A0.shape) != (p, N) or not A0.is_contiguous()):
-        raise ValueError(f"A0 must be a contiguous float32 tensor of shape {(p, N)}")
+    _check_f32("E", E, (Lb, p), X.device)
+    if A0 is not None:
+        _check_f32("A0", A0, (p, N), X.device)
     A = torch.empty((p, N), dtype=torch.float32, device=X.device)
     trace = (c_double * (T + 1))()
     eta_out = (c_double * 2)()
@@ -141,6 +179,11 @@ def ensemble(X, p, seeds, gammas, T=100, K1=5, K2=5, coherence="cosine", thresho
         out = dict(A=torch.empty((M, p, N), dtype=torch.float32, device=dev),
                    B=torch.empty((M, N, p), dtype=torch.float32, device=dev),
                    E=torch.empty((M, Lb, p), dtype=torch.float32, device=dev))
+    else:
+        for k, shp in (("A", (M, p, N)), ("B", (M, N, p)), ("E", (M, Lb, p))):
+            if k not in out:
+                raise ValueError(f"out must hold '{k}'")
+            _check_f32(f"out['{k}']", out[k], shp, dev)
     sd = (c_uint64 * M)(*[int(s) for s in seeds])
     gm = (c_double * M)(*[float(g) for g in gammas])
     loss = np.zeros((M, T + 1))
@@ -166,6 +209,15 @@ def fit_ragged(images, ps, seeds, gammas, T=100, K1=5, K2=5, init_scale=0.1, gra
     images: list of l2-normalised [L_k, N_k] GPU tensors (one dtype).
     Returns a list of dicts with A, B, E (tensors) and loss (numpy)."""
     n = len(images)
+    if n < 1 or len(ps) != n or len(seeds) != n or len(gammas) != n:
+        raise ValueError("images, ps, seeds and gammas must be non-empty and of equal length")
+    dt, dev0 = images[0].dtype, images[0].device
+    for k, X in enumerate(images):
+        if not isinstance(X, torch.Tensor):
+            raise TypeError(f"image {k} must be a tensor")
+        if X.dtype != dt or X.device != dev0:
+            raise ValueError(f"image {k}: every image must share the dtype and device of image 0 "
+                             f"({dt}, {dev0}), got ({X.dtype}, {X.device})")
     descs = (L_.EdaaImageDesc * n)()
     outs, traces = [], []
     for k, X in enumerate(images):
@@ -201,8 +253,7 @@ def pass_times(device, kind):
 
 def loss_fwd(X, A, B):
     """1/2 ||X - X B A||_F^2 as a 0-d float32 GPU tensor."""
-    Lb, N = _check_x(X)
-    p = A.shape[0]
+    Lb, N, p = _check_dense_operands(X, A, B)
     out = torch.empty((), dtype=torch.float32, device=X.device)
     check(L_.load().edaa_loss_fwd(_ctx(X.device), _ptr(X), _ptr(A), _ptr(B), Lb, N, p, _ptr(out)))
     return out
@@ -210,11 +261,10 @@ def loss_fwd(X, A, B):
 
 def loss_bwd(X, A, B, grad_out):
     """(dA, dB) of grad_out * 1/2 ||X - X B A||^2; grad_out is a 0-d GPU tensor."""
-    Lb, N = _check_x(X)
-    p = A.shape[0]
+    Lb, N, p = _check_dense_operands(X, A, B)
     gA = torch.empty_like(A)
     gB = torch.empty_like(B)
-    go = grad_out.detach().to(dtype=torch.float32).reshape(()).contiguous()
+    go = grad_out.detach().to(device=X.device, dtype=torch.float32).reshape(()).contiguous()
     check(L_.load().edaa_loss_bwd(_ctx(X.device), _ptr(X), _ptr(A), _ptr(B), Lb, N, p, _ptr(go),
                                   _ptr(gA), _ptr(gB)))
     return gA, gB
@@ -222,14 +272,26 @@ def loss_bwd(X, A, B, grad_out):
 
 def mirror_step_A(A, gA, eta):
     """In place: every column of A [p, N] <- softmax(log a - eta gA)."""
+    if not (isinstance(A, torch.Tensor) and A.dim() == 2):
+        raise ValueError("A must be a 2-D [p, N] tensor")
     p, N = A.shape
+    _check_f32("A", A, (p, N), A.device)
+    _check_f32("gA", gA, (p, N), A.device)
+    if not A.is_cuda:
+        raise ValueError("A must be a GPU tensor")
     check(L_.load().edaa_mirror_step_A(_ctx(A.device), _ptr(A), _ptr(gA), p, N, float(eta)))
     return A
 
 
 def mirror_step_B(B, gB, eta):
     """In place: every column of B [N, p] <- softmax over N of (log b - eta gB)."""
+    if not (isinstance(B, torch.Tensor) and B.dim() == 2):
+        raise ValueError("B must be a 2-D [N, p] tensor")
     N, p = B.shape
+    _check_f32("B", B, (N, p), B.device)
+    _check_f32("gB", gB, (N, p), B.device)
+    if not B.is_cuda:
+        raise ValueError("B must be a GPU tensor")
     check(L_.load().edaa_mirror_step_B(_ctx(B.device), _ptr(B), _ptr(gB), N, p, float(eta)))
     return B
 
