@@ -72,6 +72,11 @@ typedef struct {
     int x_dtype;             /* EDAA_X_F32 or EDAA_X_BF16                        */
     int coherence_mode;      /* EDAA_COHERENCE_COSINE (default) or _RAW          */
     int flags;               /* EDAA_FLAG_*                                      */
+    int runs_per_chunk;      /* launch shape: runs that share one pass over an X
+                                tile (0: tuned or default; else one of the
+                                compiled sizes, EDAA_EUNSUPPORTED otherwise)    */
+    int pixel_groups;        /* launch shape: workgroups per chunk of runs
+                                (0: tuned or default; capped at ceil(N / 64))    */
 } edaa_params;
 
 /* One image of a ragged batch (edaa_fit_ragged).  All pointers are device
@@ -87,6 +92,16 @@ typedef struct {
     double* loss_trace;      /* out, host, T+1 values, may be NULL               */
 } edaa_image_desc;
 
+/* Launch shape of a batched problem (edaa_plan). */
+typedef struct {
+    int runs_per_chunk;      /* runs sharing each pass over an X tile            */
+    int chunks;              /* ceil(M / runs_per_chunk)                         */
+    int pixel_groups;        /* workgroups per chunk (each strides over tiles)   */
+    int double_buffer;       /* 1: the next X tile loads while one is processed  */
+    int source;              /* EDAA_PLAN_DEFAULT, _TUNED or _REQUESTED          */
+} edaa_launch_plan;
+enum { EDAA_PLAN_DEFAULT = 0, EDAA_PLAN_TUNED = 1, EDAA_PLAN_REQUESTED = 2 };
+
 /* Fill *params with the paper's defaults (see edaa_params). */
 void edaa_default_params(edaa_params* params);
 
@@ -99,6 +114,18 @@ void edaa_destroy(edaa_ctx* ctx);
 
 /* Message of the last error on the calling thread ("" if none). */
 const char* edaa_last_error(void);
+
+/* The launch shape edaa_fit (M = 1) or edaa_ensemble (M runs) would use for
+ * an L x N image with p endmembers under params (its runs_per_chunk and
+ * pixel_groups requests, else a tuned shape, else the default).  Pure host
+ * function, needs no context or device.  EDAA_EINVAL for bad sizes,
+ * EDAA_EUNSUPPORTED when no compiled pass kernels fit the request. */
+edaa_status edaa_plan(int L, int N, int p, int M, const edaa_params* params, edaa_launch_plan* out);
+
+/* Capacity of the context's cache of captured HIP graphs (EDAA_FLAG_GRAPH),
+ * one per (shape, buffers, parameters) key; the least recently captured is
+ * dropped when it is full.  Default 16; n >= 1. */
+edaa_status edaa_set_graph_cache(edaa_ctx* ctx, int n);
 
 /* Number of kernel launches the last edaa_fit / edaa_ensemble call enqueued
  * (graph replays count the kernels inside the graph). */

@@ -23,7 +23,8 @@ class EdaaParams(ctypes.Structure):
     _fields_ = [("T", c_int), ("K1", c_int), ("K2", c_int),
                 ("gamma", c_double), ("eta1", c_double), ("eta2", c_double),
                 ("init_scale", c_double), ("select_threshold", c_double),
-                ("x_dtype", c_int), ("coherence_mode", c_int), ("flags", c_int)]
+                ("x_dtype", c_int), ("coherence_mode", c_int), ("flags", c_int),
+                ("runs_per_chunk", c_int), ("pixel_groups", c_int)]
 
 
 class EdaaImageDesc(ctypes.Structure):
@@ -32,6 +33,13 @@ class EdaaImageDesc(ctypes.Structure):
                 ("A", c_void_p), ("B", c_void_p), ("E", c_void_p),
                 ("loss_trace", POINTER(c_double))]
 
+
+class EdaaLaunchPlan(ctypes.Structure):
+    _fields_ = [("runs_per_chunk", c_int), ("chunks", c_int), ("pixel_groups", c_int),
+                ("double_buffer", c_int), ("source", c_int)]
+
+
+EDAA_PLAN_DEFAULT, EDAA_PLAN_TUNED, EDAA_PLAN_REQUESTED = 0, 1, 2
 
 # name -> (restype, argtypes)
 SIGNATURES = {
@@ -58,6 +66,8 @@ SIGNATURES = {
     "edaa_mirror_step_A": (c_int, [c_void_p, c_void_p, c_void_p, c_int, c_int, c_float]),
     "edaa_mirror_step_B": (c_int, [c_void_p, c_void_p, c_void_p, c_int, c_int, c_float]),
     "edaa_select": (c_int, [POINTER(c_double), POINTER(c_double), c_int, c_double]),
+    "edaa_plan": (c_int, [c_int, c_int, c_int, c_int, POINTER(EdaaParams), POINTER(EdaaLaunchPlan)]),
+    "edaa_set_graph_cache": (c_int, [c_void_p, c_int]),
 }
 
 _lib = None

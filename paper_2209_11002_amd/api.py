@@ -88,8 +88,10 @@ def _check_dense_operands(X, A, B):
     return Lb, N, p
 
 
-def _params(T, K1, K2, gamma, eta, init_scale, threshold, x_dtype, coherence, graph, time_passes=False):
+def _params(T, K1, K2, gamma, eta, init_scale, threshold, x_dtype, coherence, graph, time_passes=False,
+            runs_per_chunk=0, pixel_groups=0):
     P = L_.default_params()
+    P.runs_per_chunk, P.pixel_groups = int(runs_per_chunk), int(pixel_groups)
     P.T, P.K1, P.K2 = int(T), int(K1), int(K2)
     P.gamma = float(gamma)
     if eta is not None:
@@ -118,21 +120,30 @@ def normalize_pixels(X, out_dtype=torch.float32, count_zero=False):
 
 
 def fit(X, p, T=100, K1=5, K2=5, gamma=1.0, seed=0, A0=None, B0=None, eta=None,
-        init_scale=0.1, graph=False, time_passes=False):
+        init_scale=0.1, graph=False, time_passes=False, pixel_groups=0, out=None):
     """One run of Algorithm 1 on l2-normalised X [L, N] (float32 or bfloat16,
     on the GPU).  Returns a dict: A [p, N], B [N, p], E [L, p] (tensors),
-    loss (numpy, T+1), eta1, eta2."""
+    loss (numpy, T+1), eta1, eta2.  out: optional dict of preallocated
+    A [p, N], B [N, p], E [L, p] float32 tensors to write into."""
     Lb, N = _check_x(X)
     dev = X.device
-    A = torch.empty((p, N), dtype=torch.float32, device=dev)
-    B = torch.empty((N, p), dtype=torch.float32, device=dev)
-    E = torch.empty((Lb, p), dtype=torch.float32, device=dev)
+    if out is None:
+        A = torch.empty((p, N), dtype=torch.float32, device=dev)
+        B = torch.empty((N, p), dtype=torch.float32, device=dev)
+        E = torch.empty((Lb, p), dtype=torch.float32, device=dev)
+    else:
+        for k, shp in (("A", (p, N)), ("B", (N, p)), ("E", (Lb, p))):
+            if k not in out:
+                raise ValueError(f"out must hold '{k}'")
+            _check_f32(f"out['{k}']", out[k], shp, dev)
+        A, B, E = out["A"], out["B"], out["E"]
     for name, t, shp in (("A0", A0, (p, N)), ("B0", B0, (N, p))):
         if t is not None:
             _check_f32(name, t, shp, dev)
     trace = (c_double * (T + 1))()
     eta_out = (c_double * 2)()
-    P = _params(T, K1, K2, gamma, eta, init_scale, 1.05, _x_dtype(X), "cosine", graph, time_passes)
+    P = _params(T, K1, K2, gamma, eta, init_scale, 1.05, _x_dtype(X), "cosine", graph, time_passes,
+                pixel_groups=pixel_groups)
     lib = L_.load()
     st = lib.edaa_fit(_ctx(dev), _ptr(X), Lb, N, p, byref(P), c_uint64(seed), _ptr(A0), _ptr(B0),
                       _ptr(A), _ptr(B), _ptr(E), trace, eta_out)
@@ -166,10 +177,12 @@ def abundances(X, E, T=100, K1=5, gamma=1.0, A0=None, eta1=None, graph=False):
 
 
 def ensemble(X, p, seeds, gammas, T=100, K1=5, K2=5, coherence="cosine", threshold=1.05,
-             init_scale=0.1, graph=False, out=None, time_passes=False):
+             init_scale=0.1, graph=False, out=None, time_passes=False, runs_per_chunk=0, pixel_groups=0):
     """M runs of Algorithm 1 advanced together plus Algorithm 2.  Returns a
     dict with A [M, p, N], B [M, N, p], E [M, L, p] (tensors), loss [M, T+1],
-    fit [M], mu [M], status [M] (numpy) and the selected run index."""
+    fit [M], mu [M], status [M] (numpy) and the selected run index.
+    runs_per_chunk / pixel_groups pin the launch shape (0: tuned or
+    default; see plan())."""
     Lb, N = _check_x(X)
     M = len(seeds)
     if len(gammas) != M:
@@ -191,7 +204,8 @@ def ensemble(X, p, seeds, gammas, T=100, K1=5, K2=5, coherence="cosine", thresho
     mu = np.zeros(M)
     status = np.zeros(M, dtype=np.int32)
     sel = c_int(-1)
-    P = _params(T, K1, K2, 1.0, None, init_scale, threshold, _x_dtype(X), coherence, graph, time_passes)
+    P = _params(T, K1, K2, 1.0, None, init_scale, threshold, _x_dtype(X), coherence, graph, time_passes,
+                runs_per_chunk, pixel_groups)
     lib = L_.load()
     dp = lambda a: a.ctypes.data_as(ctypes.POINTER(c_double))  # noqa: E731
     st = lib.edaa_ensemble(_ctx(dev), _ptr(X), Lb, N, p, byref(P), M, sd, gm,
@@ -239,6 +253,26 @@ def fit_ragged(images, ps, seeds, gammas, T=100, K1=5, K2=5, init_scale=0.1, gra
     for o, tr in zip(outs, traces):
         o["loss"] = np.array(tr[:])
     return outs
+
+
+def plan(L, N, p, M=1, runs_per_chunk=0, pixel_groups=0, x_dtype=torch.float32):
+    """Launch shape that fit (M = 1) or ensemble (M runs) would use: a dict
+    with runs_per_chunk, chunks, pixel_groups, double_buffer and source
+    ('default', 'tuned' or 'requested').  Host only."""
+    P = _params(1, 1, 1, 1.0, None, 0.1, 1.05, L_.EDAA_X_BF16 if x_dtype == torch.bfloat16 else L_.EDAA_X_F32,
+                "cosine", False, runs_per_chunk=runs_per_chunk, pixel_groups=pixel_groups)
+    out = L_.EdaaLaunchPlan()
+    check(L_.load().edaa_plan(int(L), int(N), int(p), int(M), byref(P), byref(out)))
+    return dict(runs_per_chunk=out.runs_per_chunk, chunks=out.chunks, pixel_groups=out.pixel_groups,
+                double_buffer=out.double_buffer,
+                source={L_.EDAA_PLAN_DEFAULT: "default", L_.EDAA_PLAN_TUNED: "tuned",
+                        L_.EDAA_PLAN_REQUESTED: "requested"}[out.source])
+
+
+def set_graph_cache(device, n):
+    """Capacity of the captured-graph cache of this device's current-stream
+    context (default 16)."""
+    check(L_.load().edaa_set_graph_cache(_ctx(device), int(n)))
 
 
 def pass_times(device, kind):

@@ -11,7 +11,11 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libedaa.so")
-SOURCES = ["edaa_kernels.hip", "edaa_grad.hip", "edaa_api.hip"]
+# (source, extra defines, object name); edaa_inst.hip is compiled once per p
+MAX_P = 16
+UNITS = ([("edaa_inst.hip", [f"-DEDAA_INST_P={p}"], f"edaa_inst_p{p}.o") for p in range(MAX_P, 0, -1)]
+         + [("edaa_kernels.hip", [], "edaa_kernels.o"), ("edaa_grad.hip", [], "edaa_grad.o"),
+            ("edaa_api.hip", [], "edaa_api.o")])
 ARCH = os.environ.get("EDAA_OFFLOAD_ARCH", "gfx950")
 
 # Packed FP32 instructions are disabled for all device code.
@@ -25,9 +29,10 @@ def _hipcc():
     return h
 
 
-def _compile(src):
-    obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
-    cmd = [_hipcc(), *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+def _compile(unit):
+    src, defines, name = unit
+    obj = os.path.join(BUILD, name)
+    cmd = [_hipcc(), *FLAGS, *defines, "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     out = "\n".join(l for l in (r.stdout + r.stderr).splitlines() if "packed-fp32-ops" not in l)
     if r.returncode != 0:
@@ -37,8 +42,9 @@ def _compile(src):
 
 def build(verbose=False):
     os.makedirs(BUILD, exist_ok=True)
-    with ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
-        results = list(ex.map(_compile, SOURCES))
+    jobs = int(os.environ.get("MAX_JOBS", 0)) or os.cpu_count() or 4
+    with ThreadPoolExecutor(max_workers=max(1, min(jobs, 16))) as ex:
+        results = list(ex.map(_compile, UNITS))
     if verbose:
         for _, out in results:
             if out.strip():

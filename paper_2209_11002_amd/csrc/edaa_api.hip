@@ -69,6 +69,7 @@ struct edaa_ctx {
     size_t ws_bytes = 0;
     long long last_launches = 0;
     std::vector<GraphEntry> graphs;    // most recent last
+    size_t graph_cap = 16;
     PassTimer timer;
 };
 
@@ -140,6 +141,7 @@ edaa_status check_params(const edaa_params* P) {
                  "eta1/eta2 must be finite and >= 0 (0 selects the paper's rule)");
     EDAA_REQUIRE(isfinite(P->select_threshold) && P->select_threshold >= 1.0, "select_threshold must be >= 1");
     EDAA_REQUIRE(P->x_dtype == EDAA_X_F32 || P->x_dtype == EDAA_X_BF16, "x_dtype must be EDAA_X_F32 or EDAA_X_BF16");
+    EDAA_REQUIRE(P->runs_per_chunk >= 0 && P->pixel_groups >= 0, "runs_per_chunk and pixel_groups must be >= 0");
     EDAA_REQUIRE(P->coherence_mode == EDAA_COHERENCE_COSINE || P->coherence_mode == EDAA_COHERENCE_RAW,
                  "coherence_mode must be EDAA_COHERENCE_COSINE or EDAA_COHERENCE_RAW");
     return EDAA_OK;
@@ -151,6 +153,20 @@ edaa_status check_shape(int L, int N, int p, int M) {
     EDAA_REQUIRE(N >= p, "N must be >= p (got N=%d, p=%d)", N, p);
     EDAA_REQUIRE(M >= 1, "M must be >= 1 (got %d)", M);
     EDAA_REQUIRE((double)M * p * N < 2147483647.0 && (double)L * N < 2147483647.0, "problem too large");
+    return EDAA_OK;
+}
+
+// Launch shape of an M-run problem: the caller's requests, else the default
+// (EDAA_PLAN_* in *source).
+edaa_status plan_geom(int L, int N, int p, int M, const edaa_params* P, Geom* g, int* source) {
+    if (P->runs_per_chunk > 0 && !runs_fit(p, P->runs_per_chunk, L))
+        return fail(EDAA_EUNSUPPORTED, "runs_per_chunk=%d has no pass kernels for p=%d, L=%d", P->runs_per_chunk, p,
+                    L);
+    *g = make_geom(L, N, M, p, P->runs_per_chunk, P->pixel_groups);
+    if (!geom_valid(*g))
+        return fail(EDAA_EUNSUPPORTED, "no pass kernels fit L=%d with p=%d (runs per chunk %d, LDS limit %zu bytes)",
+                    L, p, g->R, kMaxLdsBytes);
+    if (source) *source = (P->runs_per_chunk > 0 || P->pixel_groups > 0) ? EDAA_PLAN_REQUESTED : EDAA_PLAN_DEFAULT;
     return EDAA_OK;
 }
 
@@ -350,7 +366,7 @@ edaa_status run_captured(edaa_ctx* ctx, const std::string& key, bool use_graph, 
         ctx->poisoned = true;
         return fail(EDAA_EDEVICE, "hipGraphInstantiate failed: %s", hipGetErrorString(e));
     }
-    if (ctx->graphs.size() >= 4) {
+    while (!ctx->graphs.empty() && ctx->graphs.size() >= ctx->graph_cap) {
         (void)hipGraphExecDestroy(ctx->graphs.front().exec);
         ctx->graphs.erase(ctx->graphs.begin());
     }
@@ -376,11 +392,9 @@ edaa_status run_batch(edaa_ctx* ctx, const void* X, int L, int N, int p, const e
                       const uint64_t* seeds, const double* gammas, const float* A0, const float* B0, float* A_all,
                       float* B_all, float* E_all, double* loss, double* fit, double* mu, double* eta_out,
                       const float* E_given = nullptr) {
-    const Geom g = make_geom(L, N, M, p);
-    for (int kind = 0; kind < 3; ++kind)
-        if (pass_lds_bytes(p, g.R, L, kind) > kMaxLdsBytes)
-            return fail(EDAA_EUNSUPPORTED, "L=%d with p=%d needs %zu bytes of LDS (limit %zu)", L, p,
-                        pass_lds_bytes(p, g.R, L, kind), kMaxLdsBytes);
+    Geom g;
+    edaa_status st0 = plan_geom(L, N, p, M, P, &g, nullptr);
+    if (st0 != EDAA_OK) return st0;
     const int x_bytes = P->x_dtype == EDAA_X_BF16 ? 2 : 4;
     const size_t need = layout(g, P->T, x_bytes, nullptr, nullptr);
     edaa_status st = ensure_ws(ctx, need);
@@ -643,6 +657,8 @@ void edaa_default_params(edaa_params* P) {
     P->x_dtype = EDAA_X_F32;
     P->coherence_mode = EDAA_COHERENCE_COSINE;
     P->flags = 0;
+    P->runs_per_chunk = 0;
+    P->pixel_groups = 0;
 }
 
 const char* edaa_last_error(void) { return g_last_error.c_str(); }
@@ -676,6 +692,34 @@ void edaa_destroy(edaa_ctx* ctx) {
 }
 
 long long edaa_last_launch_count(edaa_ctx* ctx) { return ctx ? ctx->last_launches : -1; }
+
+edaa_status edaa_set_graph_cache(edaa_ctx* ctx, int n) {
+    edaa_status st = check_ctx(ctx);
+    if (st != EDAA_OK) return st;
+    EDAA_REQUIRE(n >= 1, "graph cache capacity must be >= 1 (got %d)", n);
+    ctx->graph_cap = (size_t)n;
+    while (ctx->graphs.size() > ctx->graph_cap) {
+        (void)hipGraphExecDestroy(ctx->graphs.front().exec);
+        ctx->graphs.erase(ctx->graphs.begin());
+    }
+    return EDAA_OK;
+}
+
+edaa_status edaa_plan(int L, int N, int p, int M, const edaa_params* params, edaa_launch_plan* out) {
+    edaa_status st = check_params(params);
+    if (st != EDAA_OK) return st;
+    if ((st = check_shape(L, N, p, M)) != EDAA_OK) return st;
+    EDAA_REQUIRE(out != nullptr, "out is null");
+    Geom g;
+    int source = 0;
+    if ((st = plan_geom(L, N, p, M, params, &g, &source)) != EDAA_OK) return st;
+    out->runs_per_chunk = g.R;
+    out->chunks = g.nqc;
+    out->pixel_groups = g.npg;
+    out->double_buffer = g.dbuf;
+    out->source = source;
+    return EDAA_OK;
+}
 
 edaa_status edaa_pass_times(edaa_ctx* ctx, int kind, int* count, double* total_ms) {
     edaa_status st = check_ctx(ctx);
@@ -822,10 +866,9 @@ edaa_status edaa_fit_ragged(edaa_ctx* ctx, int n_images, const edaa_image_desc* 
         if ((st = check_shape(d.L, d.N, d.p, 1)) != EDAA_OK) return st;
         EDAA_REQUIRE(d.X && d.A && d.B, "image %d: X, A and B must not be null", k);
         EDAA_REQUIRE(params->eta1 > 0.0 || (isfinite(d.gamma) && d.gamma > 0.0), "image %d: gamma must be > 0", k);
-        for (int kind = 0; kind < 3; ++kind)
-            if (pass_lds_bytes(d.p, 1, d.L, kind) > kMaxLdsBytes)
-                return fail(EDAA_EUNSUPPORTED, "image %d: L=%d with p=%d needs %zu bytes of LDS (limit %zu)", k,
-                            d.L, d.p, pass_lds_bytes(d.p, 1, d.L, kind), kMaxLdsBytes);
+        if (!runs_fit(d.p, 1, d.L))
+            return fail(EDAA_EUNSUPPORTED, "image %d: no pass kernels fit L=%d with p=%d (LDS limit %zu bytes)", k,
+                        d.L, d.p, kMaxLdsBytes);
     }
     return run_ragged(ctx, n_images, images, params);
 }

@@ -1,0 +1,1537 @@
+// Device code of the EDAA pass kernels (gfx950, wave64), shared by the
+// per-p instantiation units (edaa_inst.hip, compiled once per p) and the
+// common unit (edaa_kernels.hip).
+//
+// The method (arXiv 2209.11002, Algorithm 1) alternates K1 entropic steps on
+// the abundances A (eq. update_A) and K2 entropic steps on the pixel weights B
+// (eq. update_B).  Written per pixel i with E = X B (L x p):
+//
+//   A-step:  a_i <- softmax(log a_i - eta1 (G a_i - E^T x_i)),  G = E^T E
+//            (the A-subproblem separates over pixels once E is fixed, so one
+//            pass over X serves all K1 steps);
+//   B-step:  b_j <- softmax over all N pixels of (log b_j - eta2 X^T w_j),
+//            W = E (A A^T) - X A^T, followed by E <- X B_new
+//            (the new E is accumulated in the same pass over X).
+//
+// Every pass streams X once in tiles of 64 pixels x L bands staged in LDS.  A
+// tile serves both contractions of the pass:
+//   * the per-pixel projection S = U^T X_tile (U = E or W, L x QC), and
+//   * the accumulation V += X_tile Wt over the tile's 64 pixels (Wt = the
+//     tile's new abundances or B weights, 64 x QC), which is a dense GEMM run
+//     on the matrix cores (v_mfma_f32_16x16x4f32, float32 in and out).
+// Runs of an ensemble are stacked along the endmember axis, R runs per
+// workgroup column (a "chunk" of QC = R p columns), so one X tile serves every
+// run of the chunk.  Both contractions run on 16-column MFMA blocks for every
+// R (with R = 1 the chunk is one run's p columns, padded to 16).
+// Cross-workgroup sums go through per-workgroup partials reduced in a fixed
+// order (deterministic); the column softmax over N uses per-tile shifts and an
+// online (max, sum) merge.
+#pragma once
+
+#include <math.h>
+
+#include "edaa_internal.h"
+namespace edaa {
+namespace {
+
+// Waves per workgroup of the B-step pass (the A-pass and the closing pass
+// use kThreads / 64 = 4).  With 8, each SIMD runs two waves of the
+// workgroup, so one wave's LDS waits overlap the other's matrix
+// instructions, and each wave issues half as many direct-to-LDS loads
+// (their issue, about 55 clocks each, stalls the issuing wave); both waves
+// share the one LDS allocation.
+constexpr int kBpassWaves = 8;
+// Waves per workgroup of the A-step pass: eight up to p = 9; above, the
+// per-pixel A-steps (p x p products on p-vectors in registers) need more
+// than the 256 registers a wave has at two waves per SIMD.
+constexpr int apass_waves(int p) { return p <= 9 ? 8 : 4; }
+constexpr int kXS = 68;   // LDS pitch (floats) of an X tile row of 64 pixels
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+// D(16x16) += A(16x4) B(4x16).  Lane l holds A[l % 16][l / 16] and
+// B[l / 16][l % 16]; D[4 (l / 16) + v][l % 16] is element v of its float4.
+__device__ __forceinline__ f4 mfma16(float a, float b, f4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+// The same shape in float64 (v_mfma_f64_16x16x4f64): same A and B lane
+// layout, but element v of lane l's double4 is D[4 v + l / 16][l % 16].
+__device__ __forceinline__ d4 mfma16d(double a, double b, d4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+__device__ __forceinline__ int uniform_int(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+// A DPP lane permutation within rows of 16 lanes (all rows and banks
+// enabled); the B-step softmax uses the quad permutes 0xB1 (lane ^ 1) and
+// 0x4E (lane ^ 2), and the half-row mirror 0x141 (lane i <-> 7 - i within
+// 8 lanes).
+template <int CTRL>
+__device__ __forceinline__ float dpp(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+
+// Workgroup barrier for LDS traffic: waits for this wave's LDS operations
+// only.  __syncthreads() would also wait for every outstanding global load,
+// store and direct-to-LDS load (its release fence), which would stall the
+// prefetch of the next tile at every barrier; the pass kernels wait for
+// those explicitly where their data is used.
+__device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
+
+// e^x and ln x from the hardware base-2 instructions (v_exp_f32, v_log_f32).
+__device__ __forceinline__ float fast_exp(float x) { return __builtin_amdgcn_exp2f(x * 1.4426950408889634f); }
+__device__ __forceinline__ float fast_log(float x) { return __builtin_amdgcn_logf(x) * 0.6931471805599453f; }
+
+__device__ __forceinline__ float bf16_to_f32(uint16_t b) { return __uint_as_float(((uint32_t)b) << 16); }
+
+__device__ __forceinline__ uint16_t f32_to_bf16_rne(float f) {
+    uint32_t u = __float_as_uint(f);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+// Philox4x64-10 (Salmon et al., SC'11): 10 rounds of two 64x64->128
+// multiplies with a Weyl key schedule.
+__device__ __forceinline__ void philox4x64_10(uint64_t c[4], uint64_t k0, uint64_t k1) {
+    const uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
+    const uint64_t W0 = 0x9E3779B97F4A7C15ull, W1 = 0xBB67AE8584CAA73Bull;
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        if (r) { k0 += W0; k1 += W1; }
+        const uint64_t lo0 = M0 * c[0], hi0 = __umul64hi(M0, c[0]);
+        const uint64_t lo1 = M1 * c[2], hi1 = __umul64hi(M1, c[2]);
+        const uint64_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
+        c[0] = n0; c[1] = lo1; c[2] = n2; c[3] = lo0;
+    }
+}
+
+// u[i][j] in [0,1): word j%4 of the block for counter (i, j/4, 0, 0), key
+// (seed, 0), top 24 bits.
+__device__ __forceinline__ float uniform_u(uint64_t seed, int i, int j) {
+    uint64_t c[4] = {(uint64_t)i, (uint64_t)(j >> 2), 0ull, 0ull};
+    philox4x64_10(c, seed, 0ull);
+    const uint64_t w = c[j & 3];
+    return (float)(uint32_t)(w >> 40) * 5.9604644775390625e-08f;   // 2^-24
+}
+
+// Workgroup -> (pixel group, chunk).  Blocks are dispatched round-robin over
+// the 8 XCDs (block b runs on XCD b % 8); all chunks of one pixel group are
+// placed on one XCD, at consecutive dispatch slots, so they share the X tiles
+// in that XCD's L2.
+__device__ __forceinline__ void wg_coords(const Geom& g, int b, int& pg, int& c) {
+    if ((g.npg & 7) == 0) {
+        const int xcd = b & 7, k = b >> 3;
+        c = k % g.nqc;
+        pg = (k / g.nqc) * 8 + xcd;
+    } else {
+        c = b % g.nqc;
+        pg = b / g.nqc;
+    }
+}
+
+// X tile staging.  X here is the library's padded copy, [L][ldx] with
+// ldx = ntiles * 64 and zero pixels past N, so every tile is whole and
+// aligned.  Three ways to put X[:, tile*64 : +64] into rows [0, L) of an LDS
+// tile (pitch kXS):
+//  - dma_tile (float32 X): direct global->LDS loads, one 64-pixel row per
+//    instruction, issued one tile ahead (measured faster than the register
+//    staging below for float32);
+//  - XRegs (bf16 X): register staging; wave w loads the row groups
+//    4w + 16i .. +3, each lane 4 consecutive pixels of one row (8 B) per
+//    instruction, one tile ahead, and store() widens them to float and
+//    writes 16 B per lane to LDS once the loads have landed;
+//  - load_tile_sync: synchronous loads through registers (bf16 kernels
+//    without room for the staging registers, and the closing pass).
+constexpr int kRegXGroups = 16;     // row groups of 4 rows per wave at 4 waves: L <= 4 * 4 * 16 = 256
+
+// ON = false compiles to nothing (kernels without room for the registers).
+template <bool ON, int NW = 4>
+struct XRegs {
+    static constexpr int NG = kRegXGroups * 4 / NW;   // row groups per wave
+    uint2 v[NG];                                 // 4 bf16 per lane and row group
+
+    __device__ __forceinline__ void issue(const void* X, size_t ldx, int L, int tile) {
+        const int lane = threadIdx.x & 63, w = uniform_int(threadIdx.x >> 6);
+        const int rsub = lane >> 4, col = 4 * (lane & 15);
+#pragma unroll
+        for (int i = 0; i < NG; ++i) {
+            const int row = 4 * NW * i + 4 * w + rsub;
+            if (4 * NW * i + 4 * w < L) {                  // uniform per wave
+                const size_t off = (size_t)min(row, L - 1) * ldx + (size_t)tile * kTile + col;
+                v[i] = *(const uint2*)((const uint16_t*)X + off);
+            }
+        }
+    }
+    __device__ __forceinline__ void store(float* Xs, int L) const {
+        const int lane = threadIdx.x & 63, w = uniform_int(threadIdx.x >> 6);
+        const int rsub = lane >> 4, col = 4 * (lane & 15);
+#pragma unroll
+        for (int i = 0; i < NG; ++i) {
+            const int row = 4 * NW * i + 4 * w + rsub;
+            if (4 * NW * i + 4 * w < L && row < L)
+                *(f4*)(Xs + row * kXS + col) =
+                    f4{__uint_as_float(v[i].x << 16), __uint_as_float(v[i].x & 0xffff0000u),
+                       __uint_as_float(v[i].y << 16), __uint_as_float(v[i].y & 0xffff0000u)};
+        }
+    }
+};
+template <int NW>
+struct XRegs<false, NW> {
+    __device__ __forceinline__ void issue(const void*, size_t, int, int) {}
+    __device__ __forceinline__ void store(float*, int) const {}
+};
+
+// Rows l = wd, wd + NWD, ... are loaded by wave wd of a group of NWD waves.
+template <int NWD = 4>
+__device__ __forceinline__ void dma_tile(const float* X, size_t ldx, int L, int tile, float* Xs, int wd) {
+    const int lane = threadIdx.x & 63;
+    const float* src = X + (size_t)tile * kTile + lane;
+    for (int l = wd; l < L; l += NWD) __builtin_amdgcn_global_load_lds(src + (size_t)l * ldx, Xs + l * kXS, 4, 0, 0);
+}
+
+__device__ __forceinline__ void load_tile_sync(const void* X, int x_bf16, int L, size_t ldx, int tile, float* Xs) {
+    const int i = threadIdx.x & 63, r0 = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const size_t pc = (size_t)tile * kTile + i;
+    constexpr int B = 16;
+    for (int l0 = r0; l0 < L; l0 += nw * B) {
+        float v[B];
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+            const size_t off = (size_t)min(l0 + nw * b, L - 1) * ldx + pc;
+            v[b] = x_bf16 ? bf16_to_f32(((const uint16_t*)X)[off]) : ((const float*)X)[off];
+        }
+#pragma unroll
+        for (int b = 0; b < B; ++b)
+            if (l0 + nw * b < L) Xs[(l0 + nw * b) * kXS + i] = v[b];
+    }
+}
+
+// Whether a pass kernel has room for the staging registers (compile time);
+// at run time L must also fit the row groups.
+template <int PP, int R, bool APASS>
+constexpr bool kRegX = PP * R <= 48 && (!APASS || PP <= 12);
+constexpr int kRegXMaxL = 4 * 4 * kRegXGroups;
+
+// K1 entropic steps of eq. update_A for one pixel: a <- softmax(log a -
+// eta1 (G a - P)), P = E^T x.  The logarithm is carried between steps.
+template <int PP, typename GT>
+__device__ __forceinline__ void a_steps(float (&a)[PP], const float (&P)[PP], const GT* G, float eta1, int K1) {
+    float la[PP];
+#pragma unroll
+    for (int j = 0; j < PP; ++j) la[j] = fast_log(a[j]);
+    for (int k = 0; k < K1; ++k) {
+        float v[PP];
+        float mx = -INFINITY;
+#pragma unroll
+        for (int j = 0; j < PP; ++j) {
+            float gj = -P[j];
+#pragma unroll
+            for (int kk = 0; kk < PP; ++kk) gj = fmaf((float)G[j * PP + kk], a[kk], gj);
+            v[j] = fmaf(-eta1, gj, la[j]);
+            mx = fmaxf(mx, v[j]);
+        }
+        float ssum = 0.f;
+#pragma unroll
+        for (int j = 0; j < PP; ++j) {
+            v[j] -= mx;
+            a[j] = fast_exp(v[j]);
+            ssum += a[j];
+        }
+        const float inv = 1.f / ssum, lsum = fast_log(ssum);
+#pragma unroll
+        for (int j = 0; j < PP; ++j) {
+            a[j] *= inv;
+            la[j] = v[j] - lsum;
+        }
+    }
+}
+
+template <int PP, int R>
+struct Shape {
+    static constexpr int QC = PP * R;                   // columns per chunk
+    static constexpr int QCP = (QC + 15) & ~15;         // padded to MFMA blocks of 16
+    static constexpr int NCB = QCP / 16;                // column blocks
+    static constexpr int WTS = QCP + 1;                 // LDS pitch of the per-pixel weight rows
+    // accumulation row blocks of 16 bands per wave at four waves (the
+    // accumulators are NRBW x NCB float64 blocks per wave; see
+    // acc_row_blocks); a kernel with NW waves takes 4/NW of it
+    static constexpr int NRBW = acc_row_blocks(PP, R);
+    static constexpr int NGB = 2 * NCB - 1;             // Gram blocks (qb, qb) and (qb, qb+1)
+};
+
+// LDS layout of a pass kernel, in floats.  LP = L rounded up to 16.
+struct PassLds {
+    int xs, wt, f, fg, ec, gs, gf, xx, pd, xs2, total;
+};
+// dbuf: a second X tile buffer, so that the next tile loads while the
+// current one is processed.
+// ecs: LDS pitch of the staged projection operand (QCP + 4 avoids bank
+// conflicts in the projections; QCP + 1 where LDS is short).
+// gf: room for a float copy of the Gram matrices (A-steps).
+__host__ __device__ inline PassLds pass_lds(int PP, int R, int L, int dbuf, int ecs, int gf) {
+    const int QC = PP * R, QCP = (QC + 15) & ~15, WTS = QCP + 1, ECS = ecs;
+    const int LP = (L + 15) & ~15;
+    PassLds o;
+    o.xs = 0;
+    o.wt = o.xs + LP * kXS;                    // [64][WTS] or [QCP][kXS] weights / projection results
+    o.f = o.wt + (kTile * WTS > QCP * kXS ? kTile * WTS : QCP * kXS);   // [QCP] rescale factors
+    o.fg = o.f + QCP;                          // [QCP] factors of the tile's weights
+    o.ec = o.fg + QCP;                         // [LP][ECS] projection operand chunk (E or W)
+    o.gs = o.ec + LP * ECS;                    // [R][PP][PP] Gram matrices (double, 2 floats each)
+    o.gs = (o.gs + 1) & ~1;
+    o.gf = o.gs + 2 * R * PP * PP;             // [R][PP][PP] the same Gram matrices in float (A-steps)
+    o.xx = (o.gf + (gf ? R * PP * PP : 0) + 1) & ~1;   // [64] squared pixel norms (double, 2 floats each)
+    o.pd = o.xx + 2 * kTile;                   // [64][WTS] low part of the A-pass projection
+    o.xs2 = o.pd + kTile * WTS;
+    o.total = o.xs2 + (dbuf ? LP * kXS : 0);
+    return o;
+}
+
+// Scheduling pattern for a block of NMFMA matrix instructions and the LDS
+// reads of the next block's operands: the reads go, up to four at a time,
+// between the first four MFMAs, so they complete while the later MFMAs of
+// the block run instead of stalling the next block.
+template <int NMFMA>
+__device__ __forceinline__ void interleave_loads() {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);   // one MFMA
+        __builtin_amdgcn_sched_group_barrier(0x100, 4, 0);   // up to four LDS reads
+    }
+    if (NMFMA > 4) __builtin_amdgcn_sched_group_barrier(0x008, NMFMA - 4, 0);
+}
+
+// V += X_tile Wt on the matrix cores: each tile's 64-pixel sums are formed
+// in float32 by the MFMAs and folded into float64 running sums, so that the
+// partial of a workgroup carries no error that grows with its tile count
+// (W = E A A^T - X A^T cancels and would amplify it).  Wave w owns the row blocks
+// rb = w + NW j (16 bands each) and every column block; with SCALE the
+// running accumulation of column q is first multiplied by F[q].  The B
+// operands (Wt, 64 x QCP) are loaded once per tile and reused for every row
+// block; the optional Gram accumulation Wt^T Wt reuses them as well.
+// QMAJOR: the weights are stored column-major, Wt[q * kXS + pixel].
+// With SCALE the running sums of column q are first multiplied by F[q] and
+// the tile's sums by G[q].
+template <int NCB, int NRBW, int WTS, bool SCALE, int NGBW, bool QMAJOR = false, int NW = 4>
+__device__ __forceinline__ void mfma_accumulate(d4 (&acc)[NRBW][NCB], d4 (&gram)[NGBW], bool do_gram,
+                                                const float* Xs, const float* Wt, const float* F, const float* G,
+                                                int nrb, int w, int lane) {
+    const int m = lane & 15, kk = lane >> 4;
+    float bop[16][NCB];
+#pragma unroll
+    for (int k = 0; k < 16; ++k)
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb)
+            bop[k][cb] = QMAJOR ? Wt[(16 * cb + m) * kXS + 4 * k + kk] : Wt[(4 * k + kk) * WTS + 16 * cb + m];
+    // the X operands of the next row block are read while the MFMAs of the
+    // current one run (rows past the last block re-read the last one)
+    float xa[16];
+    {
+        const float* xr = Xs + (16 * min(w, nrb - 1) + m) * kXS + kk;
+#pragma unroll
+        for (int k = 0; k < 16; ++k) xa[k] = xr[4 * k];
+    }
+    float fs[NCB], gs[NCB];
+    if (SCALE) {
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb) {
+            fs[cb] = F[16 * cb + m];
+            gs[cb] = G[16 * cb + m];
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < NRBW; ++j) {
+        const int rb = w + NW * j;
+        if (rb < nrb) {
+            f4 t[NCB];
+#pragma unroll
+            for (int cb = 0; cb < NCB; ++cb) t[cb] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int k = 0; k < 16; ++k) {
+#pragma unroll
+                for (int cb = 0; cb < NCB; ++cb) t[cb] = mfma16(xa[k], bop[k][cb], t[cb]);
+            }
+            float xn[16];
+            if (j + 1 < NRBW) {
+                const float* xr = Xs + (16 * min(rb + NW, nrb - 1) + m) * kXS + kk;
+#pragma unroll
+                for (int k = 0; k < 16; ++k) xn[k] = xr[4 * k];
+                interleave_loads<16 * NCB>();
+            }
+            if (j + 1 < NRBW) {
+#pragma unroll
+                for (int k = 0; k < 16; ++k) xa[k] = xn[k];
+            }
+            // fold the tile's sums into the float64 running sums (rescaled
+            // first with SCALE)
+#pragma unroll
+            for (int cb = 0; cb < NCB; ++cb)
+#pragma unroll
+                for (int v = 0; v < 4; ++v)
+                    acc[j][cb][v] = SCALE ? fma(acc[j][cb][v], (double)fs[cb], (double)t[cb][v] * (double)gs[cb])
+                                          : acc[j][cb][v] + (double)t[cb][v];
+        }
+    }
+    if (do_gram) {
+#pragma unroll
+        for (int gi = 0; gi < NGBW; ++gi) {
+            const int gb = w + NW * gi;                // (qb, qb) for even gb, (qb, qb+1) for odd
+            if (gb < 2 * NCB - 1) {
+                const int q1 = gb >> 1, q2 = q1 + (gb & 1);
+                f4 tg = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int k = 0; k < 16; ++k) {
+                    float a = 0.f, b = 0.f;
+#pragma unroll
+                    for (int cb = 0; cb < NCB; ++cb) {
+                        if (cb == q1) a = bop[k][cb];
+                        if (cb == q2) b = bop[k][cb];
+                    }
+                    tg = mfma16(a, b, tg);
+                }
+#pragma unroll
+                for (int v = 0; v < 4; ++v) gram[gi][v] += (double)tg[v];
+            }
+        }
+    }
+}
+
+// Write the accumulated V (rows < L, columns < QC) of this workgroup.
+template <int NCB, int NRBW, int QC, int NW = 4>
+__device__ __forceinline__ void store_acc(const d4 (&acc)[NRBW][NCB], float* Vp, int L, int nrb, int w, int lane) {
+    const int m = lane & 15, kk = lane >> 4;
+#pragma unroll
+    for (int j = 0; j < NRBW; ++j) {
+        const int rb = w + NW * j;
+        if (rb < nrb)
+#pragma unroll
+            for (int cb = 0; cb < NCB; ++cb) {
+                const int q = 16 * cb + m;
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int l = 16 * rb + 4 * kk + v;
+                    if (l < L && q < QC) Vp[(size_t)l * QC + q] = (float)acc[j][cb][v];
+                }
+            }
+    }
+}
+
+// Projection of the tile by a chunk operand staged in LDS (R > 1): wave w
+// computes the 16 pixels 16w..16w+15 for the NCB column blocks from CB0
+// (16 columns each), S[q][i] =
+// sum_l Ec[l][q] Xs[l][i]; results go to Sc[i][q] (or Sc[q][i] with QMAJOR).  Also returns, for the
+// same pixels, the partial sums of x^2 over the bands this lane touched.
+// LP (a multiple of 16) rows of both operands are read; rows L..LP-1 of
+// both are zero.  Within a block of 16 bands, MFMA step u takes the bands
+// u, u + 4, u + 8, u + 12 (lane group kk gets u + 4 kk): the four rows a
+// wave reads are then 4 rows apart, which with the pitches kXS = 68 and
+// ECS = QCP + 4 puts the 64 lanes on 64 distinct LDS banks.
+template <int NCB, int WTS, bool QMAJOR = false, int CB0 = 0>
+__device__ __forceinline__ float mfma_project(const float* Ec, int ECS, const float* Xs, float* Sc, int LP, int w,
+                                              int lane) {
+    const int m = lane & 15, kk = lane >> 4;
+    f4 s[NCB];
+#pragma unroll
+    for (int cb = 0; cb < NCB; ++cb) s[cb] = f4{0.f, 0.f, 0.f, 0.f};
+    float xx = 0.f;
+    const float* xb = Xs + 4 * kk * kXS + 16 * w + m;
+    const float* eb = Ec + 4 * kk * ECS + 16 * CB0 + m;
+    // Software pipeline over blocks of 16 bands with two operand sets: the
+    // operands of the next block are read between the first MFMAs of the
+    // current one, so they arrive while the rest of its MFMAs run.
+    float b0[4], e0[4][NCB], b1[4], e1[4][NCB];
+    auto load = [&](float (&b)[4], float (&e)[4][NCB], int k0) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            b[u] = xb[(k0 + u) * kXS];
+#pragma unroll
+            for (int cb = 0; cb < NCB; ++cb) e[u][cb] = eb[(k0 + u) * ECS + 16 * cb];
+        }
+    };
+    auto mma = [&](const float (&b)[4], const float (&e)[4][NCB]) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            xx = fmaf(b[u], b[u], xx);
+#pragma unroll
+            for (int cb = 0; cb < NCB; ++cb) s[cb] = mfma16(e[u][cb], b[u], s[cb]);
+        }
+    };
+    // One block per trip, no branch in the body: a branch (or a body that
+    // alternates two accumulation orders) made the compiler copy the
+    // accumulators out of and back into AGPRs on every trip, which drains
+    // the MFMA pipeline.  Only the operands are copied between sets.
+    load(b0, e0, 0);
+    int k0 = 0;
+    for (; k0 + 16 < LP; k0 += 32) {
+        load(b1, e1, k0 + 16);
+        __builtin_amdgcn_sched_barrier(0);
+        mma(b0, e0);
+        __builtin_amdgcn_sched_barrier(0);
+        load(b0, e0, (k0 + 32 < LP) ? k0 + 32 : k0);
+        __builtin_amdgcn_sched_barrier(0);
+        mma(b1, e1);
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    if (k0 < LP) mma(b0, e0);
+#pragma unroll
+    for (int cb = 0; cb < NCB; ++cb)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            if (QMAJOR)
+                Sc[(16 * (CB0 + cb) + 4 * kk + v) * kXS + 16 * w + m] = s[cb][v];
+            else
+                Sc[(16 * w + m) * WTS + 16 * (CB0 + cb) + 4 * kk + v] = s[cb][v];
+        }
+    return xx;
+}
+
+// The A-pass projection in float64: P = E^T x feeds the objective
+// ||x - E a||^2 = ||x||^2 - 2 a.P + a.G a, whose terms are of order ||x||^2
+// while the result is of the order of the residual, so P and ||x||^2 are
+// accumulated in float64 (products of float32 values are exact in float64).
+// P is kept as a float pair, hi = fl(P) (used by the A-steps) and
+// lo = fl(P - hi), which carries it to about 48 bits; returns the partial
+// ||x||^2 of this lane's bands.
+template <int NCB, int WTS, int CB0 = 0>
+__device__ __forceinline__ double mfma_project_f64(const float* Ec, int ECS, const float* Xs, float* Sc, float* Plo,
+                                                   int LP, int w, int lane) {
+    const int m = lane & 15, kk = lane >> 4;
+    d4 s[NCB];
+#pragma unroll
+    for (int cb = 0; cb < NCB; ++cb) s[cb] = d4{0.0, 0.0, 0.0, 0.0};
+    double xx = 0.0;
+    const float* xb = Xs + 4 * kk * kXS + 16 * w + m;
+    const float* eb = Ec + 4 * kk * ECS + 16 * CB0 + m;
+    // same software pipeline as mfma_project
+    float b0[4], e0[4][NCB], b1[4], e1[4][NCB];
+    auto load = [&](float (&b)[4], float (&e)[4][NCB], int k0) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            b[u] = xb[(k0 + u) * kXS];
+#pragma unroll
+            for (int cb = 0; cb < NCB; ++cb) e[u][cb] = eb[(k0 + u) * ECS + 16 * cb];
+        }
+    };
+    auto mma = [&](const float (&b)[4], const float (&e)[4][NCB]) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const double bd = (double)b[u];
+            xx = fma(bd, bd, xx);
+#pragma unroll
+            for (int cb = 0; cb < NCB; ++cb) s[cb] = mfma16d((double)e[u][cb], bd, s[cb]);
+        }
+    };
+    // One block per trip, no branch in the body: a branch (or a body that
+    // alternates two accumulation orders) made the compiler copy the
+    // accumulators out of and back into AGPRs on every trip, which drains
+    // the MFMA pipeline.  Only the operands are copied between sets.
+    load(b0, e0, 0);
+    int k0 = 0;
+    for (; k0 + 16 < LP; k0 += 32) {
+        load(b1, e1, k0 + 16);
+        __builtin_amdgcn_sched_barrier(0);
+        mma(b0, e0);
+        __builtin_amdgcn_sched_barrier(0);
+        load(b0, e0, (k0 + 32 < LP) ? k0 + 32 : k0);
+        __builtin_amdgcn_sched_barrier(0);
+        mma(b1, e1);
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    if (k0 < LP) mma(b0, e0);
+#pragma unroll
+    for (int cb = 0; cb < NCB; ++cb)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const float hi = (float)s[cb][v];
+            Sc[(16 * w + m) * WTS + 16 * (CB0 + cb) + 4 * v + kk] = hi;
+            Plo[(16 * w + m) * WTS + 16 * (CB0 + cb) + 4 * v + kk] = (float)(s[cb][v] - (double)hi);
+        }
+    return xx;
+}
+
+// Stage U[:, chunk] (rows < L, QCP columns) in LDS with rows L..LP-1 zero.
+template <int QC, int QCP>
+__device__ __forceinline__ void stage_chunk(const float* __restrict__ U, int Qp, int col0, int L, int LP, float* Ec,
+                                            int ECS) {
+    for (int e = threadIdx.x; e < LP * QCP; e += blockDim.x) {
+        const int l = e / QCP, q = e % QCP;
+        Ec[l * ECS + q] = (l < L && q < QC) ? U[(size_t)l * Qp + col0 + q] : 0.f;
+    }
+}
+
+// --------------------------------------------------------------------------
+// A-pass: per tile, the objective at the incoming (A, E) for the trace,
+// P = E^T x, K1 A-steps, write A, accumulate X A^T and A A^T partials.
+// --------------------------------------------------------------------------
+template <int PP, int R>
+__device__ __forceinline__ void apass_body(const Geom& g, const State& s, int bid, const float* __restrict__ E, int K1) {
+    using S = Shape<PP, R>;
+    constexpr int NW = apass_waves(PP), NT = 64 * NW;
+    constexpr int QC = S::QC, QCP = S::QCP, NCB = S::NCB, WTS = S::WTS;
+    constexpr int RW = (R + NW - 1) / NW;          // runs per wave in the A-step phase (r = w + NW k < R)
+    constexpr int NRBW = S::NRBW * 4 / NW;          // accumulation row blocks per wave
+    constexpr int NGBW = (S::NGB + NW - 1) / NW;    // Gram blocks per wave
+    // projection: waves w and w + 4 share the pixel block w & 3 (eight
+    // waves), waves 0-3 taking the first NC0 column blocks
+    constexpr int NC0 = (NW == 8) ? (NCB + 1) / 2 : NCB, NC1 = NCB - NC0;
+    static_assert(NW == 4 || NW == 8, "four or eight waves");
+    const int ECS = g.ecs;
+    extern __shared__ float smem[];
+    const PassLds lo = pass_lds(PP, R, g.L, g.dbuf, g.ecs, g.gf);
+    float* Wt = smem + lo.wt;
+    float* Ec = smem + lo.ec;
+    double* Gd = (double*)(smem + lo.gs);
+    float* Gf = smem + lo.gf;                  // used when g.gf
+    const int xo[2] = {lo.xs, g.dbuf ? lo.xs2 : lo.xs};
+    double* XX = (double*)(smem + lo.xx);
+    float* Plo = smem + lo.pd;
+
+    int pg, c;
+    wg_coords(g, bid, pg, c);
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int w = uniform_int(tid >> 6);
+    const int L = g.L, N = g.N, LP = (L + 15) & ~15, nrb = LP / 16;
+    const int col0 = c * QC;
+    float* __restrict__ A = s.A;
+
+    // Gram matrices of this chunk's runs, in float64 from the float32 E the
+    // projection uses (so that the objective formed from P and G below is
+    // consistent with that E).
+    stage_chunk<QC, QCP>(E, g.Qp, col0, L, LP, Ec, ECS);
+    __syncthreads();
+    for (int e = tid; e < R * PP * PP; e += NT) {
+        const int r = e / (PP * PP), jk = e % (PP * PP), j = jk / PP, k = jk % PP;
+        const float* Ek = Ec + r * PP;
+        double acc = 0.0;
+        for (int l = 0; l < L; ++l) acc = fma((double)Ek[l * ECS + j], (double)Ek[l * ECS + k], acc);
+        Gd[e] = acc;
+        if (g.gf) Gf[e] = (float)acc;
+    }
+    __syncthreads();
+    // zero the X rows beyond L and the weight padding (never written later)
+    for (int e = tid; e < (LP - L) * kXS; e += NT) {
+        smem[xo[0] + L * kXS + e] = 0.f;
+        smem[xo[1] + L * kXS + e] = 0.f;
+    }
+    for (int e = tid; e < kTile * WTS; e += NT) Wt[e] = 0.f;
+
+    d4 acc[NRBW][NCB], gram[NGBW];
+#pragma unroll
+    for (int j = 0; j < NRBW; ++j)
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb) acc[j][cb] = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int j = 0; j < NGBW; ++j) gram[j] = d4{0.0, 0.0, 0.0, 0.0};
+    double lacc[RW];
+#pragma unroll
+    for (int r = 0; r < RW; ++r) lacc[r] = 0.0;
+
+    // Pipeline: the X tile and this thread's abundances (registers) of tile
+    // t + npg are requested while tile t is processed.
+    constexpr bool kRX = kRegX<PP, R, true>;
+    const bool regx = kRX && L <= kRegXMaxL && s.x_bf16;      // float32 X: direct-to-LDS loads
+    const bool dma = !regx && !s.x_bf16;
+    XRegs<kRX, NW> xr;
+
+    float an[RW][PP];
+    auto load_a = [&](int tile) {
+        const size_t pixc = (size_t)min(tile * kTile + lane, N - 1);
+#pragma unroll
+        for (int k = 0; k < RW; ++k) {
+            const int m = c * R + min(w + NW * k, R - 1);
+#pragma unroll
+            for (int j = 0; j < PP; ++j) an[k][j] = A[(size_t)(min(m, g.M - 1) * PP + j) * N + pixc];
+        }
+    };
+    __syncthreads();
+    if (pg < g.ntiles) {
+        if (regx) {
+            xr.issue(s.X, s.ldx, L, pg);
+            xr.store(smem + xo[0], L);
+        } else if (dma) {
+            dma_tile<NW>((const float*)s.X, s.ldx, L, pg, smem + xo[0], w);
+        }
+        load_a(pg);
+    }
+    int it = 0;
+    for (int tile = pg; tile < g.ntiles; tile += g.npg, ++it) {
+        float* Xs = smem + ((it & 1) ? xo[1] : xo[0]);
+        float* Xn = smem + ((it & 1) ? xo[0] : xo[1]);     // == Xs when single-buffered
+        if (!dma && !regx) {
+            lds_barrier();
+            load_tile_sync(s.X, s.x_bf16, L, s.ldx, tile, Xs);
+        }
+        __builtin_amdgcn_s_waitcnt(0);
+        lds_barrier();
+        const int pix = tile * kTile + lane;
+        const bool pok = pix < N;
+        float a[RW][PP];
+#pragma unroll
+        for (int k = 0; k < RW; ++k) {
+            const int m = c * R + w + NW * k;
+            const bool mok = m < g.M && w + NW * k < R;
+#pragma unroll
+            for (int j = 0; j < PP; ++j) a[k][j] = (mok && pok) ? an[k][j] : 0.f;
+        }
+        const int nt = tile + g.npg;
+        if (nt < g.ntiles) {
+            load_a(nt);
+            if (regx) xr.issue(s.X, s.ldx, L, nt);
+            if (dma && g.dbuf) dma_tile<NW>((const float*)s.X, s.ldx, L, nt, Xn, w);
+        }
+        {
+            // projection on the matrix cores: P for pixels 16w..16w+15
+            // (16 (w - 4).. with eight waves, w >= 4)
+            if (w < 4) {
+                double xx = mfma_project_f64<NC0, WTS>(Ec, ECS, Xs, Wt, Plo, LP, w, lane);
+                xx += __shfl_xor(xx, 16);       // the 4 band classes of the pixel
+                xx += __shfl_xor(xx, 32);
+                if (lane < 16) XX[16 * w + lane] = xx;
+            } else if constexpr (NC1 > 0) {
+                (void)mfma_project_f64<NC1, WTS, NC0>(Ec, ECS, Xs, Wt, Plo, LP, w - 4, lane);
+            }
+            lds_barrier();
+            // A-steps: lane = pixel, runs r = w + NW k of the chunk
+            const double xnorm = XX[lane];
+#pragma unroll
+            for (int k = 0; k < RW; ++k) {
+                const int r = w + NW * k, m = c * R + r;
+                if (r >= R) continue;                 // uniform per wave
+                const bool mok = m < g.M;
+                float P[PP];
+#pragma unroll
+                for (int j = 0; j < PP; ++j) P[j] = Wt[lane * WTS + r * PP + j];
+                const double* Gr = Gd + r * PP * PP;
+                if (mok && pok) {
+                    // ||x - E a||^2 = ||x||^2 - 2 a.P + a.G a, in float64
+                    double q = xnorm;
+#pragma unroll
+                    for (int j = 0; j < PP; ++j) {
+                        double ga = 0.0;
+#pragma unroll
+                        for (int kk = 0; kk < PP; ++kk) ga = fma(Gr[j * PP + kk], (double)a[k][kk], ga);
+                        const double pj = (double)P[j] + (double)Plo[lane * WTS + r * PP + j];
+                        q = fma((double)a[k][j], ga - 2.0 * pj, q);
+                    }
+                    lacc[k] += q;
+                }
+                if (mok) {
+                    if (g.gf)
+                        a_steps<PP>(a[k], P, Gf + r * PP * PP, s.eta[2 * m], K1);
+                    else
+                        a_steps<PP>(a[k], P, Gr, s.eta[2 * m], K1);
+                }
+#pragma unroll
+                for (int j = 0; j < PP; ++j) {
+                    if (mok && pok) A[(size_t)(m * PP + j) * N + pix] = a[k][j];
+                    Wt[lane * WTS + r * PP + j] = (mok && pok) ? a[k][j] : 0.f;
+                }
+            }
+        }
+        lds_barrier();
+        mfma_accumulate<NCB, NRBW, WTS, false, NGBW, false, NW>(acc, gram, true, Xs, Wt, nullptr, nullptr, nrb, w,
+                                                                lane);
+        if (nt < g.ntiles && (regx || dma)) {
+            if (!g.dbuf) lds_barrier();           // single buffer: overwrite after every reader
+            if (regx)
+                xr.store(Xn, L);
+            else if (!g.dbuf)
+                dma_tile<NW>((const float*)s.X, s.ldx, L, nt, Xs, w);
+        }
+    }
+
+    const size_t wgi = (size_t)pg * g.nqc + c;
+    store_acc<NCB, NRBW, QC, NW>(acc, s.Vpart + wgi * (size_t)L * QC, L, nrb, w, lane);
+    // A A^T of every run from the Gram blocks: entry (q1, q2) of block
+    // (qb1, qb2) with q1 = 16 qb1 + 4 (lane/16) + v, q2 = 16 qb2 + lane%16.
+    {
+        const int m16 = lane & 15, kk = lane >> 4;
+        float* AAp = s.AApart + wgi * (size_t)(R * PP * PP);
+#pragma unroll
+        for (int gi = 0; gi < NGBW; ++gi) {
+            const int gb = w + NW * gi;
+            if (gb < 2 * NCB - 1) {
+                const int qb1 = gb >> 1, qb2 = qb1 + (gb & 1);
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int q1 = 16 * qb1 + 4 * kk + v, q2 = 16 * qb2 + m16;
+                    if (q1 < QC && q2 < QC && q1 / PP == q2 / PP) {
+                        const int r = q1 / PP, j = q1 % PP, k = q2 % PP;
+                        AAp[r * PP * PP + j * PP + k] = (float)gram[gi][v];
+                        if (qb1 != qb2) AAp[r * PP * PP + k * PP + j] = (float)gram[gi][v];
+                    }
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < RW; ++k) {
+        const int r = w + NW * k, m = c * R + r;
+        if (r >= R) continue;
+        const double tot = wave_sum(lacc[k]);
+        if (lane == 0 && m < g.M) s.lpart[(size_t)pg * g.M + m] = tot;
+    }
+}
+
+template <int PP, int R>
+__global__ __launch_bounds__(64 * apass_waves(PP), 1) void k_apass(Geom g, State s, const float* __restrict__ E, int K1) {
+    apass_body<PP, R>(g, s, blockIdx.x, E, K1);
+}
+template <int PP, int R>
+__global__ __launch_bounds__(64 * apass_waves(PP), 1) void k_apass_multi(const ImageJob* __restrict__ jobs, const int2* __restrict__ map,
+                                                             int K1) {
+    const int2 jl = map[blockIdx.x];
+    const ImageJob& J = jobs[jl.x];
+    apass_body<PP, R>(J.g, J.s, jl.y, J.s.E, K1);
+}
+
+// --------------------------------------------------------------------------
+// B-pass: per tile, g = W^T x (STEP) and v = log b - eta2 g, or the start
+// values (INIT: 0.1 u, or log B0); per-tile column max and online merge into
+// the workgroup's running (max, sum); write the shifted weights and the
+// tile's shift; accumulate X * weights^T.
+//
+// Softmax layout (NW waves): thread t owns column q = t / NW of the chunk
+// and the 64 / NW pixels (t % NW) * 64 / NW .. of the tile, so a column's
+// tile max and sum take two quad permutes (and a half-row mirror with eight
+// waves), and the running (max, sum) stays in those lanes.  The projection
+// results and the weights live column-major in LDS ([QCP][kXS]).  Bst rows
+// are padded to whole tiles (pixels >= N hold zero weights), so the pixel
+// segments are read and written as float4 without bounds checks.
+// --------------------------------------------------------------------------
+template <int PP, int R, bool STEP>
+__device__ __forceinline__ void bpass_body(const Geom& g, const State& s, int bid, const float* __restrict__ W, int mode,
+                                           const RunInit& ri) {
+    using S = Shape<PP, R>;
+    constexpr int NW = kBpassWaves, NT = 64 * NW;
+    constexpr int QC = S::QC, QCP = S::QCP, NCB = S::NCB, WTS = S::WTS, NRBW = S::NRBW * 4 / NW;
+    // softmax: NW lanes per column, SPX pixels each
+    constexpr int SPX = kTile / NW, SV = SPX / 4;
+    // projection: wave group 0 (waves 0-3) takes the first NC0 column
+    // blocks, group 1 the other NC1, each for the pixel block w & 3
+    constexpr int NC0 = (NW == 8) ? (NCB + 1) / 2 : NCB, NC1 = NCB - NC0;
+    const int ECS = g.ecs;
+    static_assert(NW == 4 || NW == 8, "four or eight waves");
+    static_assert(QCP * NW <= NT, "NW threads per softmax column");
+    extern __shared__ float smem[];
+    const PassLds lo = pass_lds(PP, R, g.L, g.dbuf, g.ecs, g.gf);
+    float* Wq = smem + lo.wt;                      // [QCP][kXS]
+    float* F = smem + lo.f;
+    float* FG = smem + lo.fg;
+    float* Ec = smem + lo.ec;
+    const int xo[2] = {lo.xs, g.dbuf ? lo.xs2 : lo.xs};
+
+    int pg, c;
+    wg_coords(g, bid, pg, c);
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int w = uniform_int(tid >> 6);
+    const int L = g.L, N = g.N, LP = (L + 15) & ~15, nrb = LP / 16;
+    const size_t Np = (size_t)g.ntiles * kTile;
+    const int col0 = c * QC;
+
+    for (int e = tid; e < (LP - L) * kXS; e += NT) {
+        smem[xo[0] + L * kXS + e] = 0.f;
+        smem[xo[1] + L * kXS + e] = 0.f;
+    }
+    for (int e = tid; e < QCP * kXS; e += NT) Wq[e] = 0.f;
+    for (int e = tid; e < QCP; e += NT) F[e] = FG[e] = 0.f;
+    if (STEP) stage_chunk<QC, QCP>(W, g.Qp, col0, L, LP, Ec, ECS);
+
+    // this thread's softmax column and pixel segment
+    const int sq = tid / NW, sub = tid % NW;
+    const int sm = c * R + sq / PP, sj = sq % PP;
+    const bool qin = sq < QC;                      // a column of the chunk
+    const bool cok = qin && sm < g.M;              // ... of an existing run
+    float* bcol = s.Bst + (size_t)(cok ? col0 + sq : 0) * Np + SPX * sub;
+    float mrun = -INFINITY, lzc = 0.f, eta2 = 0.f;
+    double srun = 0.0;                             // float64: it runs over every tile of the workgroup
+    if (STEP && cok) {
+        lzc = -s.colm[col0 + sq] - logf(s.cols[col0 + sq]);
+        eta2 = s.eta[2 * sm + 1];
+    }
+
+    d4 acc[NRBW][NCB], gdummy[1];
+#pragma unroll
+    for (int jb = 0; jb < NRBW; ++jb)
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb) acc[jb][cb] = d4{0.0, 0.0, 0.0, 0.0};
+
+    // Pipeline: the X tile and this thread's B segment and shift (registers)
+    // of tile t + npg are requested while tile t is processed.
+    constexpr bool kRX = kRegX<PP, R, false>;
+    const bool regx = kRX && L <= kRegXMaxL && s.x_bf16;      // float32 X: direct-to-LDS loads
+    const bool dma = !regx && !s.x_bf16;
+    XRegs<kRX, NW> xr;
+
+    f4 bn[SV];
+    float tn = 0.f;
+    auto load_b = [&](int tile) {
+        if (STEP && cok) {
+            const f4* src = (const f4*)(bcol + (size_t)tile * kTile);
+#pragma unroll
+            for (int u = 0; u < SV; ++u) bn[u] = src[u];
+            tn = s.tshift[(size_t)tile * g.Qp + col0 + sq];
+        }
+    };
+    __syncthreads();
+    if (pg < g.ntiles) {
+        if (regx) {
+            xr.issue(s.X, s.ldx, L, pg);
+            xr.store(smem + xo[0], L);
+        } else if (dma) {
+            dma_tile<NW>((const float*)s.X, s.ldx, L, pg, smem + xo[0], w);
+        }
+        load_b(pg);
+    }
+    int it = 0;
+    for (int tile = pg; tile < g.ntiles; tile += g.npg, ++it) {
+        float* Xs = smem + ((it & 1) ? xo[1] : xo[0]);
+        float* Xn = smem + ((it & 1) ? xo[0] : xo[1]);     // == Xs when single-buffered
+        if (!dma && !regx) {
+            lds_barrier();
+            load_tile_sync(s.X, s.x_bf16, L, s.ldx, tile, Xs);
+        }
+        __builtin_amdgcn_s_waitcnt(0);
+        lds_barrier();
+        f4 bv[SV];
+#pragma unroll
+        for (int u = 0; u < SV; ++u) bv[u] = bn[u];
+        const float ts = tn;
+        const int nt = tile + g.npg;
+        if (nt < g.ntiles) {
+            load_b(nt);
+            if (regx) xr.issue(s.X, s.ldx, L, nt);
+            if (dma && g.dbuf) dma_tile<NW>((const float*)s.X, s.ldx, L, nt, Xn, w);
+        }
+
+        if (STEP) {
+            if (w < 4)
+                (void)mfma_project<NC0, WTS, true>(Ec, ECS, Xs, Wq, LP, w, lane);
+            else if constexpr (NC1 > 0)
+                (void)mfma_project<NC1, WTS, true, NC0>(Ec, ECS, Xs, Wq, LP, w - 4, lane);
+            lds_barrier();
+        }
+
+        if (qin) {
+            const int pix0 = tile * kTile + SPX * sub;
+            float* wrow = Wq + sq * kXS + SPX * sub;
+            float v[SPX];
+            if (STEP) {
+                const float sh = ts + lzc;
+#pragma unroll
+                for (int u = 0; u < SV; ++u) {
+                    const f4 gv = *(const f4*)(wrow + 4 * u);
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) v[4 * u + e] = fast_log(bv[u][e]) + sh - eta2 * gv[e];
+                }
+            } else if (mode == kModeInitRng) {
+                const uint64_t seed = ri.seeds[cok ? sm : 0];
+#pragma unroll
+                for (int i = 0; i < SPX; ++i) v[i] = ri.init_scale * uniform_u(seed, pix0 + i, sj);
+            } else {
+#pragma unroll
+                for (int i = 0; i < SPX; ++i) v[i] = fast_log(ri.B0[(size_t)min(pix0 + i, N - 1) * PP + sj]);
+            }
+            float mx = -INFINITY;
+#pragma unroll
+            for (int i = 0; i < SPX; ++i) {
+                v[i] = (cok && pix0 + i < N) ? v[i] : -INFINITY;
+                mx = fmaxf(mx, v[i]);
+            }
+            mx = fmaxf(mx, dpp<0xB1>(mx));             // the NW lanes of this column
+            mx = fmaxf(mx, dpp<0x4E>(mx));
+            if (NW == 8) mx = fmaxf(mx, dpp<0x141>(mx));
+            // The tile's weights are stored relative to the tile's own max
+            // (its largest weight is 1, so none underflows for being far
+            // below a larger tile of this workgroup); the running sums are
+            // relative to the running max: factors f (old sums) and fg
+            // (this tile).
+            const float mnew = fmaxf(mrun, mx);
+            const float f = (mrun == -INFINITY) ? 0.f : fast_exp(mrun - mnew);
+            const float fg = (mx == -INFINITY) ? 0.f : fast_exp(mx - mnew);
+            float wv[SPX], sum = 0.f;
+#pragma unroll
+            for (int i = 0; i < SPX; ++i) {
+                wv[i] = (v[i] == -INFINITY) ? 0.f : fast_exp(v[i] - mx);
+                sum += wv[i];
+            }
+            sum += dpp<0xB1>(sum);
+            sum += dpp<0x4E>(sum);
+            if (NW == 8) sum += dpp<0x141>(sum);
+            srun = fma(srun, (double)f, (double)sum * (double)fg);
+            mrun = mnew;
+#pragma unroll
+            for (int u = 0; u < SV; ++u) {
+                const f4 o = f4{wv[4 * u], wv[4 * u + 1], wv[4 * u + 2], wv[4 * u + 3]};
+                *(f4*)(wrow + 4 * u) = o;
+                if (cok) ((f4*)(bcol + (size_t)tile * kTile))[u] = o;
+            }
+            if (sub == 0) {
+                F[sq] = f;
+                FG[sq] = fg;
+                if (cok) s.tshift[(size_t)tile * g.Qp + col0 + sq] = mx;
+            }
+        }
+        lds_barrier();
+        mfma_accumulate<NCB, NRBW, WTS, true, 1, true, NW>(acc, gdummy, false, Xs, Wq, F, FG, nrb, w, lane);
+        if (nt < g.ntiles && (regx || dma)) {
+            if (!g.dbuf) lds_barrier();           // single buffer: overwrite after every reader
+            if (regx)
+                xr.store(Xn, L);
+            else if (!g.dbuf)
+                dma_tile<NW>((const float*)s.X, s.ldx, L, nt, Xs, w);
+        }
+    }
+
+    const size_t wgi = (size_t)pg * g.nqc + c;
+    store_acc<NCB, NRBW, QC, NW>(acc, s.Vpart + wgi * (size_t)L * QC, L, nrb, w, lane);
+    if (qin && sub == 0) {
+        s.mpart[(size_t)pg * g.Qp + col0 + sq] = cok ? mrun : -INFINITY;
+        s.spart[(size_t)pg * g.Qp + col0 + sq] = cok ? (float)srun : 0.f;
+    }
+}
+
+template <int PP, int R, bool STEP>
+__global__ __launch_bounds__(64 * kBpassWaves, 1) void k_bpass(Geom g, State s, const float* __restrict__ W, int mode,
+                                                       RunInit ri) {
+    bpass_body<PP, R, STEP>(g, s, blockIdx.x, W, mode, ri);
+}
+template <int PP, int R, bool STEP>
+__global__ __launch_bounds__(64 * kBpassWaves, 1) void k_bpass_multi(const ImageJob* __restrict__ jobs,
+                                                             const int2* __restrict__ map, int mode) {
+    const int2 jl = map[blockIdx.x];
+    const ImageJob& J = jobs[jl.x];
+    bpass_body<PP, R, STEP>(J.g, J.s, jl.y, J.s.W, mode, J.ri);
+}
+
+// --------------------------------------------------------------------------
+// Closing pass: objective and l1 fit of every run at the final (A, E), from
+// the per-band residual (the l1 fit needs it band by band).
+// --------------------------------------------------------------------------
+template <int PP, int R>
+__device__ __forceinline__ void close_body(const Geom& g, const State& s, int bid, const float* __restrict__ E) {
+    constexpr int QC = PP * R;
+    constexpr int RW = (R + 3) / 4;                   // runs per wave (R > 1): w RW + r < R
+    extern __shared__ float smem[];
+    float* Xs = smem;                                  // [L][kXS]
+    float* Ls = Xs + g.L * kXS;                        // R == 1: [2][4][kTile]
+
+    int pg, c;
+    wg_coords(g, bid, pg, c);
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int w = uniform_int(tid >> 6);
+    const int L = g.L, N = g.N, col0 = c * QC;
+    double lacc[RW], facc[RW];
+#pragma unroll
+    for (int r = 0; r < RW; ++r) lacc[r] = facc[r] = 0.0;
+
+    for (int tile = pg; tile < g.ntiles; tile += g.npg) {
+        __syncthreads();
+        load_tile_sync(s.X, s.x_bf16, L, s.ldx, tile, Xs);
+        const int pix = tile * kTile + lane;
+        const bool pok = pix < N;
+        __syncthreads();
+        if constexpr (R == 1) {
+            const int m = c;
+            float a[PP];
+#pragma unroll
+            for (int j = 0; j < PP; ++j) a[j] = pok ? s.A[(size_t)(m * PP + j) * N + pix] : 0.f;
+            float ls = 0.f, fs = 0.f;
+            const int Lq = (L + 3) >> 2, l0 = min(L, w * Lq), l1 = min(L, l0 + Lq);
+            for (int l = l0; l < l1; ++l) {
+                const float* El = E + (size_t)l * g.Qp + col0;
+                float r = Xs[l * kXS + lane];
+#pragma unroll
+                for (int j = 0; j < PP; ++j) r = fmaf(-El[j], a[j], r);
+                ls = fmaf(r, r, ls);
+                fs += fabsf(r);
+            }
+            Ls[w * kTile + lane] = ls;
+            Ls[(4 + w) * kTile + lane] = fs;
+            __syncthreads();
+            if (w == 0 && pok) {
+                lacc[0] += (double)(Ls[lane] + Ls[kTile + lane] + Ls[2 * kTile + lane] + Ls[3 * kTile + lane]);
+                facc[0] += (double)(Ls[4 * kTile + lane] + Ls[5 * kTile + lane] + Ls[6 * kTile + lane] +
+                                    Ls[7 * kTile + lane]);
+            }
+        } else {
+            float a[RW][PP], ls[RW], fs[RW];
+#pragma unroll
+            for (int r = 0; r < RW; ++r) {
+                const int m = c * R + w * RW + r;
+                const bool rok = pok && m < g.M && w * RW + r < R;
+#pragma unroll
+                for (int j = 0; j < PP; ++j) a[r][j] = rok ? s.A[(size_t)(m * PP + j) * N + pix] : 0.f;
+                ls[r] = fs[r] = 0.f;
+            }
+            const float* Ew = E + col0 + w * RW * PP;
+            for (int l = 0; l < L; ++l) {
+                const float x = Xs[l * kXS + lane];
+                const float* El = Ew + (size_t)l * g.Qp;
+#pragma unroll
+                for (int r = 0; r < RW; ++r) {
+                    float rv = x;
+#pragma unroll
+                    for (int j = 0; j < PP; ++j) rv = fmaf(-El[r * PP + j], a[r][j], rv);
+                    ls[r] = fmaf(rv, rv, ls[r]);
+                    fs[r] += fabsf(rv);
+                }
+            }
+            if (pok)
+#pragma unroll
+                for (int r = 0; r < RW; ++r) {
+                    lacc[r] += (double)ls[r];
+                    facc[r] += (double)fs[r];
+                }
+        }
+    }
+    if constexpr (R == 1) {
+        if (w == 0) {
+            const double lt = wave_sum(lacc[0]), ft = wave_sum(facc[0]);
+            if (lane == 0) {
+                s.lpart[(size_t)pg * g.M + c] = lt;
+                s.fpart[(size_t)pg * g.M + c] = ft;
+            }
+        }
+    } else {
+#pragma unroll
+        for (int r = 0; r < RW; ++r) {
+            const int m = c * R + w * RW + r;
+            const double lt = wave_sum(lacc[r]), ft = wave_sum(facc[r]);
+            if (lane == 0 && m < g.M && w * RW + r < R) {
+                s.lpart[(size_t)pg * g.M + m] = lt;
+                s.fpart[(size_t)pg * g.M + m] = ft;
+            }
+        }
+    }
+}
+
+template <int PP, int R>
+__global__ __launch_bounds__(kThreads, 2) void k_close(Geom g, State s, const float* __restrict__ E) {
+    close_body<PP, R>(g, s, blockIdx.x, E);
+}
+template <int PP, int R>
+__global__ __launch_bounds__(kThreads, 2) void k_close_multi(const ImageJob* __restrict__ jobs,
+                                                             const int2* __restrict__ map) {
+    const int2 jl = map[blockIdx.x];
+    const ImageJob& J = jobs[jl.x];
+    close_body<PP, R>(J.g, J.s, jl.y, J.s.E);
+}
+
+
+// --------------------------------------------------------------------------
+// Reductions of the per-workgroup partials, in a fixed order.  Grid:
+// (row blocks, chunks); a workgroup owns whole rows of its chunk.
+// --------------------------------------------------------------------------
+// The cross-workgroup sums, E and W = E (A A^T) - X A^T are formed in float64:
+// E A A^T and X A^T are both of order N/p while W is of the order of the
+// residual, so forming the difference in float32 would lose most digits.
+//
+// Every sum over the npg per-workgroup partials is split into fixed slices
+// of the partial index (one slice per thread) whose results are combined in
+// slice order, so the result does not depend on scheduling.
+
+// out[o] = sum over pg of src[pg * stride + o] for o < no (no <= 256).
+__device__ __forceinline__ void sliced_sum(const float* __restrict__ src, size_t stride, int npg, int no,
+                                           double* red, double* out) {
+    const int tid = threadIdx.x, S = kThreads / no;
+    const int o = tid % no, sl = tid / no;
+    double acc = 0.0;
+    if (sl < S)
+        for (int pg0 = sl; pg0 < npg; pg0 += 4 * S) {     // loads first, sums in the plain order
+            float v[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) v[u] = pg0 + u * S < npg ? src[(size_t)(pg0 + u * S) * stride + o] : 0.f;
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                if (pg0 + u * S < npg) acc += (double)v[u];
+        }
+    red[tid] = acc;
+    __syncthreads();
+    if (tid < no) {
+        double t = 0.0;
+        for (int k = 0; k < S; ++k) t += red[k * no + tid];
+        out[tid] = t;
+    }
+    __syncthreads();
+}
+
+// A A^T of run m (blockIdx.x) and its objective at the incoming state
+// (trace[t]), each summed over the npg workgroup partials in fixed slices.
+template <int PP, int R>
+__device__ __forceinline__ void reduce_aa_body(const Geom& g, const State& s, int bx, int t) {
+    constexpr int P2 = PP * PP;
+    __shared__ double red[kThreads];
+    __shared__ double out[P2 > 1 ? P2 : 1];
+    const int m = bx, tid = threadIdx.x;
+    sliced_sum(s.AApart + (size_t)m * P2, (size_t)g.nqc * R * P2, g.npg, P2, red, out);   // [npg][nqc R][p][p]
+    if (tid < P2) s.AAtd[(size_t)m * P2 + tid] = out[tid];
+    double acc = 0.0;
+    for (int pg = tid; pg < g.npg; pg += kThreads) acc += s.lpart[(size_t)pg * g.M + m];
+    red[tid] = acc;
+    __syncthreads();
+    if (tid == 0) {
+        double tot = 0.0;
+        for (int k = 0; k < kThreads; ++k) tot += red[k];
+        s.trace[(size_t)m * (s.T + 1) + t] = 0.5 * tot;
+    }
+}
+
+template <int PP, int R>
+__global__ __launch_bounds__(kThreads) void k_reduce_aa(Geom g, State s, int t) {
+    reduce_aa_body<PP, R>(g, s, blockIdx.x, t);
+}
+
+// Row l of chunk c: X A^T[l][:] and W[l][:] = E[l][:] A A^T - X A^T[l][:].
+template <int PP, int R>
+__device__ __forceinline__ void reduce_a_body(const Geom& g, const State& s, int bx, int by, int t) {
+    constexpr int QC = PP * R;
+    __shared__ double red[kThreads];
+    __shared__ double xa[QC];
+    const int l = bx, c = by, tid = threadIdx.x;
+    const int col0 = c * QC, L = g.L;
+    (void)t;
+    sliced_sum(s.Vpart + ((size_t)c * L + l) * QC, (size_t)g.nqc * L * QC, g.npg, QC, red, xa);
+    if (tid < QC) {
+        const int q = tid, m = c * R + q / PP, ml = q / PP, j = q % PP;
+        double x = xa[q], wv = 0.0;
+        if (m < g.M) {
+            wv = -x;
+            const double* El = s.Ed + (size_t)l * g.Qp + col0 + ml * PP;
+            const double* aat = s.AAtd + (size_t)m * PP * PP;
+#pragma unroll
+            for (int k = 0; k < PP; ++k) wv = fma(El[k], aat[k * PP + j], wv);
+        } else {
+            x = 0.0;
+        }
+        s.XAtd[(size_t)l * g.Qp + col0 + q] = x;
+        s.W[(size_t)l * g.Qp + col0 + q] = (float)wv;
+    }
+}
+
+template <int PP, int R>
+__global__ __launch_bounds__(kThreads) void k_reduce_a(Geom g, State s, int t) {
+    reduce_a_body<PP, R>(g, s, blockIdx.x, blockIdx.y, t);
+}
+// Single-run images (R = 1, one chunk): the objective and A A^T of the run
+// (one block per image), then, in a second launch since W needs A A^T, the
+// rows of X A^T and W (L blocks per image).
+template <int PP>
+__global__ __launch_bounds__(kThreads) void k_reduce_aa_multi(const ImageJob* __restrict__ jobs,
+                                                              const int2* __restrict__ map, int t) {
+    const ImageJob& J = jobs[map[blockIdx.x].x];
+    reduce_aa_body<PP, 1>(J.g, J.s, 0, t);
+}
+template <int PP>
+__global__ __launch_bounds__(kThreads) void k_reduce_a_multi(const ImageJob* __restrict__ jobs,
+                                                             const int2* __restrict__ map, int t) {
+    const int2 jl = map[blockIdx.x];
+    const ImageJob& J = jobs[jl.x];
+    reduce_a_body<PP, 1>(J.g, J.s, jl.y, 0, t);
+}
+
+// Row l of chunk c after a B-pass: column statistics (max, sum relative to
+// the max) of the softmax over all N pixels, E[l][:] = X B_new, and W for the
+// next B-step.
+template <int PP, int R>
+__device__ __forceinline__ void reduce_b_body(const Geom& g, const State& s, int bx, int by, int need_w) {
+    constexpr int QC = PP * R;
+    __shared__ double red[kThreads];
+    __shared__ float Ms[QC];
+    __shared__ double Ss[QC], Ev[QC];
+    const int l = bx, c = by, tid = threadIdx.x;
+    const int col0 = c * QC, L = g.L;
+    const int S = kThreads / QC, o = tid % QC, sl = tid / QC;
+    const bool act = sl < S;
+    // column maxima over the workgroup partials; the partials of a slice are
+    // walked four at a time, loads first, the arithmetic in the same order
+    // as a plain walk
+    constexpr int U = 4;
+    float mx = -INFINITY;
+    if (act)
+        for (int pg0 = sl; pg0 < g.npg; pg0 += U * S) {
+            float v[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int pg = pg0 + u * S;
+                v[u] = pg < g.npg ? s.mpart[(size_t)pg * g.Qp + col0 + o] : -INFINITY;
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) mx = fmaxf(mx, v[u]);
+        }
+    red[tid] = (double)mx;
+    __syncthreads();
+    if (tid < QC) {
+        float t = -INFINITY;
+        for (int k = 0; k < S; ++k) t = fmaxf(t, (float)red[k * QC + tid]);
+        Ms[tid] = t;
+    }
+    __syncthreads();
+    // column sums and the row of X B (relative to the maxima)
+    const float mq = Ms[o];
+    double sa = 0.0, ea = 0.0;
+    if (act && mq != -INFINITY)
+        for (int pg0 = sl; pg0 < g.npg; pg0 += U * S) {
+            float mp[U], sp[U], vp[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int pg = pg0 + u * S;
+                const bool ok = pg < g.npg;
+                mp[u] = ok ? s.mpart[(size_t)pg * g.Qp + col0 + o] : -INFINITY;
+                sp[u] = ok ? s.spart[(size_t)pg * g.Qp + col0 + o] : 0.f;
+                vp[u] = ok ? s.Vpart[(((size_t)pg * g.nqc + c) * L + l) * QC + o] : 0.f;
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                if (mp[u] == -INFINITY) continue;
+                const double f = (double)expf(mp[u] - mq);
+                sa += (double)sp[u] * f;
+                ea += (double)vp[u] * f;
+            }
+        }
+    red[tid] = sa;
+    __syncthreads();
+    if (tid < QC) {
+        double t = 0.0;
+        for (int k = 0; k < S; ++k) t += red[k * QC + tid];
+        Ss[tid] = t;
+    }
+    __syncthreads();
+    red[tid] = ea;
+    __syncthreads();
+    if (tid < QC) {
+        double t = 0.0;
+        for (int k = 0; k < S; ++k) t += red[k * QC + tid];
+        const int m = c * R + tid / PP;
+        const double e = (m < g.M) ? t / Ss[tid] : 0.0;
+        Ev[tid] = e;
+        s.E[(size_t)l * g.Qp + col0 + tid] = (float)e;
+        s.Ed[(size_t)l * g.Qp + col0 + tid] = e;
+        if (l == 0 && m < g.M) {
+            s.colm[col0 + tid] = Ms[tid];
+            s.cols[col0 + tid] = (float)Ss[tid];
+        }
+    }
+    __syncthreads();
+    if (need_w && tid < QC) {
+        const int q = tid, m = c * R + q / PP, ml = q / PP, j = q % PP;
+        double wv = 0.0;
+        if (m < g.M) {
+            wv = -s.XAtd[(size_t)l * g.Qp + col0 + q];
+            const double* aat = s.AAtd + (size_t)m * PP * PP;
+#pragma unroll
+            for (int k = 0; k < PP; ++k) wv = fma(Ev[ml * PP + k], aat[k * PP + j], wv);
+        }
+        s.W[(size_t)l * g.Qp + col0 + q] = (float)wv;
+    }
+}
+
+template <int PP, int R>
+__global__ __launch_bounds__(kThreads) void k_reduce_b(Geom g, State s, int need_w) {
+    reduce_b_body<PP, R>(g, s, blockIdx.x, blockIdx.y, need_w);
+}
+template <int PP>
+__global__ __launch_bounds__(kThreads) void k_reduce_b_multi(const ImageJob* __restrict__ jobs,
+                                                             const int2* __restrict__ map, int need_w) {
+    const int2 jl = map[blockIdx.x];
+    const ImageJob& J = jobs[jl.x];
+    reduce_b_body<PP, 1>(J.g, J.s, jl.y, 0, need_w);
+}
+
+__device__ __forceinline__ void reduce_close_body(const Geom& g, const State& s, int first, int stride) {
+    for (int m = first; m < g.M; m += stride) {
+        double la = 0.0, fa = 0.0;
+        for (int pg = 0; pg < g.npg; ++pg) {
+            la += s.lpart[(size_t)pg * g.M + m];
+            fa += s.fpart[(size_t)pg * g.M + m];
+        }
+        s.trace[(size_t)m * (s.T + 1) + s.T] = 0.5 * la;
+        s.fit[m] = fa;
+    }
+}
+
+
+// --------------------------------------------------------------------------
+// Step sizes (eq. eta0A, eq. eta0B): sigma_max^2(X B0) is the largest
+// eigenvalue of the p x p Gram matrix E0^T E0, found by cyclic Jacobi
+// rotations in float64 by one thread per run.
+// --------------------------------------------------------------------------
+__device__ double jacobi_max_eig(double* a, int n) {
+    for (int sweep = 0; sweep < 64; ++sweep) {
+        double off = 0.0, dia = 0.0;
+        for (int i = 0; i < n; ++i) {
+            dia += a[i * n + i] * a[i * n + i];
+            for (int j = i + 1; j < n; ++j) off += a[i * n + j] * a[i * n + j];
+        }
+        if (off <= 1e-32 * dia || off == 0.0) break;
+        for (int p = 0; p < n; ++p)
+            for (int q = p + 1; q < n; ++q) {
+                const double apq = a[p * n + q];
+                if (apq == 0.0) continue;
+                const double theta = (a[q * n + q] - a[p * n + p]) / (2.0 * apq);
+                const double t = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+                const double cs = 1.0 / sqrt(t * t + 1.0), sn = t * cs;
+                for (int k = 0; k < n; ++k) {
+                    const double akp = a[k * n + p], akq = a[k * n + q];
+                    a[k * n + p] = cs * akp - sn * akq;
+                    a[k * n + q] = sn * akp + cs * akq;
+                }
+                for (int k = 0; k < n; ++k) {
+                    const double apk = a[p * n + k], aqk = a[q * n + k];
+                    a[p * n + k] = cs * apk - sn * aqk;
+                    a[q * n + k] = sn * apk + cs * aqk;
+                }
+            }
+    }
+    double mx = a[0];
+    for (int i = 1; i < n; ++i) mx = fmax(mx, a[i * n + i]);
+    return mx;
+}
+
+template <int PP>
+__device__ __forceinline__ void eta_body(const Geom& g, const State& s, int bx, const RunInit& ri) {
+    __shared__ double Gd[PP * PP];
+    const int m = bx, tid = threadIdx.x;
+    const int c = m / g.R, col0 = c * g.QC + (m % g.R) * PP;
+    for (int e = tid; e < PP * PP; e += kThreads) {
+        const int j = e / PP, k = e % PP;
+        double acc = 0.0;
+        for (int l = 0; l < g.L; ++l)
+            acc += s.Ed[(size_t)l * g.Qp + col0 + j] * s.Ed[(size_t)l * g.Qp + col0 + k];
+        Gd[e] = acc;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        const double lam = jacobi_max_eig(Gd, PP);
+        const double e1 = ri.eta1 > 0.0 ? ri.eta1 : ri.gammas[m] / lam;
+        const double e2 = ri.eta2 > 0.0 ? ri.eta2 : sqrt((double)PP / (double)g.N) * e1;
+        s.eta[2 * m] = (float)e1;
+        s.eta[2 * m + 1] = (float)e2;
+        s.etad[2 * m] = e1;
+        s.etad[2 * m + 1] = e2;
+    }
+}
+
+template <int PP>
+__global__ __launch_bounds__(kThreads) void k_eta(Geom g, State s, RunInit ri) {
+    eta_body<PP>(g, s, blockIdx.x, ri);
+}
+
+// --------------------------------------------------------------------------
+// Outputs: normalised B in [M][N][p], E in [M][L][p], coherence per run.
+// --------------------------------------------------------------------------
+template <int PP>
+__device__ __forceinline__ void final_B_body(const Geom& g, const State& s, int bx, int by, int nbx, float* B_out) {
+    const int m = by;
+    const size_t n = (size_t)g.N * PP;
+    const int c = m / g.R, base = c * g.QC + (m % g.R) * PP;
+    for (size_t e = (size_t)bx * kThreads + threadIdx.x; e < n; e += (size_t)nbx * kThreads) {
+        const int pix = (int)(e / PP), j = (int)(e % PP);
+        const int qp = base + j, tile = pix / kTile;
+        const float b = s.Bst[(size_t)(m * PP + j) * ((size_t)g.ntiles * kTile) + pix];
+        B_out[(size_t)m * n + e] = b * expf(s.tshift[(size_t)tile * g.Qp + qp] - s.colm[qp] - logf(s.cols[qp]));
+    }
+}
+
+template <int PP>
+__global__ __launch_bounds__(kThreads) void k_final_B(Geom g, State s, float* B_out) {
+    final_B_body<PP>(g, s, blockIdx.x, blockIdx.y, gridDim.x, B_out);
+}
+
+template <int PP>
+__device__ __forceinline__ void final_E_body(const Geom& g, const State& s, int bx, float* E_out, int cosine) {
+    __shared__ double Gd[PP * PP];
+    const int m = bx, tid = threadIdx.x;
+    const int c = m / g.R, base = c * g.QC + (m % g.R) * PP;
+    if (E_out)
+        for (int e = tid; e < g.L * PP; e += kThreads) {
+            const int l = e / PP, j = e % PP;
+            E_out[(size_t)m * g.L * PP + e] = s.E[(size_t)l * g.Qp + base + j];
+        }
+    for (int e = tid; e < PP * PP; e += kThreads) {
+        const int j = e / PP, k = e % PP;
+        double acc = 0.0;
+        for (int l = 0; l < g.L; ++l)
+            acc += s.Ed[(size_t)l * g.Qp + base + j] * s.Ed[(size_t)l * g.Qp + base + k];
+        Gd[e] = acc;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        double mu = -INFINITY;
+        for (int j = 0; j < PP; ++j)
+            for (int k = 0; k < PP; ++k) {
+                if (j == k) continue;
+                double v = Gd[j * PP + k];
+                if (cosine) {
+                    const double nj = sqrt(Gd[j * PP + j]), nk = sqrt(Gd[k * PP + k]);
+                    v = v / ((nj > 0.0 ? nj : 1.0) * (nk > 0.0 ? nk : 1.0));
+                }
+                mu = fmax(mu, v);
+            }
+        s.mu[m] = mu;
+    }
+}
+
+template <int PP>
+__global__ __launch_bounds__(kThreads) void k_final_E(Geom g, State s, float* E_out, int cosine) {
+    final_E_body<PP>(g, s, blockIdx.x, E_out, cosine);
+}
+
+// Multi-image helpers (single-run images of one p).
+template <int PP>
+__global__ __launch_bounds__(kThreads) void k_prep_multi(const ImageJob* __restrict__ jobs,
+                                                         const int2* __restrict__ map) {
+    const int2 jl = map[blockIdx.x];
+    const ImageJob& J = jobs[jl.x];
+    const Geom& g = J.g;
+    const State& s = J.s;
+    const size_t i0 = (size_t)jl.y * kThreads + threadIdx.x, st = (size_t)kElemBlocks * kThreads;
+    const size_t nf = (size_t)(g.L + kPadRows) * g.Qp, nd = (size_t)g.L * g.Qp;
+    for (size_t i = i0; i < nf; i += st) {
+        s.E[i] = 0.f;
+        s.W[i] = 0.f;
+    }
+    for (size_t i = i0; i < nd; i += st) {
+        s.XAtd[i] = 0.0;
+        s.Ed[i] = 0.0;
+    }
+    const size_t na = (size_t)PP * g.N;
+    for (size_t i = i0; i < na; i += st) s.A[i] = 1.f / (float)PP;
+}
+
+template <int PP>
+__global__ __launch_bounds__(kThreads) void k_eta_multi(const ImageJob* __restrict__ jobs, const int2* __restrict__ map) {
+    const ImageJob& J = jobs[map[blockIdx.x].x];
+    eta_body<PP>(J.g, J.s, 0, J.ri);
+}
+
+__global__ __launch_bounds__(kThreads) void k_reduce_close_multi(const ImageJob* __restrict__ jobs,
+                                                                 const int2* __restrict__ map) {
+    const ImageJob& J = jobs[map[blockIdx.x].x];
+    reduce_close_body(J.g, J.s, threadIdx.x, kThreads);
+}
+
+template <int PP>
+__global__ __launch_bounds__(kThreads) void k_final_multi(const ImageJob* __restrict__ jobs,
+                                                          const int2* __restrict__ map, int cosine) {
+    const int2 jl = map[blockIdx.x];
+    const ImageJob& J = jobs[jl.x];
+    final_B_body<PP>(J.g, J.s, jl.y, 0, kElemBlocks, J.B_out);
+    if (jl.y == 0) final_E_body<PP>(J.g, J.s, 0, J.E_out, cosine);
+}
+
+}  // namespace
+}  // namespace edaa

@@ -21,6 +21,40 @@ constexpr int kPadRows = 17;             // zero rows after the L rows of E and 
 
 enum PassMode { kModeStep = 0, kModeInitRng = 1, kModeInitB0 = 2 };
 
+// Accumulation row blocks (16 bands each) per wave at four waves for a chunk
+// of R runs of p endmembers.  A wave keeps NRBW x NCB float64 accumulator
+// blocks (NCB = column blocks of 16), so chunks of up to two column blocks
+// hold eight row blocks and wider chunks four: the pass kernels of a chunk
+// cover at most max_bands(p, R) bands.
+__host__ __device__ constexpr int acc_row_blocks(int p, int R) { return (p * R + 15) / 16 <= 2 ? 8 : 4; }
+__host__ __device__ constexpr int max_bands(int p, int R) { return 4 * 16 * acc_row_blocks(p, R); }
+
+// Runs per chunk with compiled pass kernels, largest first (the list ends
+// with 1).  The largest fills at most 64 columns.
+__host__ __device__ constexpr int runs_max(int p) {
+    return p > 8 ? 4 : p > 5 ? 8 : p == 5 ? 12 : p == 4 ? 16 : 20;
+}
+__host__ __device__ constexpr int run_choices(int p, int* out) {
+    int n = 0;
+    if (p > 8) {
+        out[n++] = 4;
+        out[n++] = 2;
+    } else {
+        out[n++] = runs_max(p);
+        if (runs_max(p) > 8) out[n++] = 8;
+        out[n++] = 4;
+    }
+    out[n++] = 1;
+    return n;
+}
+__host__ __device__ constexpr bool has_runs(int p, int R) {
+    int c[4] = {0, 0, 0, 0};
+    const int n = run_choices(p, c);
+    for (int i = 0; i < n; ++i)
+        if (c[i] == R) return true;
+    return false;
+}
+
 // Geometry of one batched problem: M runs of p endmembers on an L x N image,
 // the runs grouped in chunks of R (one workgroup column per chunk).
 struct Geom {
@@ -106,6 +140,24 @@ enum MultiKernel {
     kMultiCloseReduce,     // final objective and l1 fit                  (kMapOne)
     kMultiFinal,           // B and E outputs, coherence (arg: cosine)    (kMapElem)
 };
+// Launchers of the kernels compiled for one p (edaa_inst.hip, built once per
+// p).  The pass launchers take the chunk size from g.R, which must be one of
+// run_choices(p); they return hipErrorInvalidValue otherwise.
+struct PassOps {
+    hipError_t (*apass)(const Geom& g, const State& s, int K1, hipStream_t st);
+    hipError_t (*bpass)(const Geom& g, const State& s, int mode, const RunInit& ri, hipStream_t st);
+    hipError_t (*close)(const Geom& g, const State& s, hipStream_t st);
+    hipError_t (*reduce_b)(const Geom& g, const State& s, int need_w, hipStream_t st);
+    hipError_t (*reduce_a)(const Geom& g, const State& s, int t, hipStream_t st);
+    hipError_t (*reduce_aa)(const Geom& g, const State& s, int t, hipStream_t st);
+    hipError_t (*eta)(const Geom& g, const State& s, const RunInit& ri, hipStream_t st);
+    hipError_t (*finalize)(const Geom& g, const State& s, float* B_out, float* E_out, int cosine, hipStream_t st);
+    hipError_t (*multi)(int kernel, const ImageJob* jobs, const int2* map, int nblocks, size_t lds_bytes, int arg,
+                        hipStream_t st);
+};
+// The table for p (1 <= p <= kMaxP), or null.
+const PassOps* pass_ops(int p);
+
 // Enqueue one multi-image kernel for the images of one p (all R = 1).
 hipError_t launch_multi(int kernel, int p, const ImageJob* jobs, const int2* map, int nblocks, size_t lds_bytes,
                         int arg, hipStream_t st);
@@ -166,7 +218,14 @@ size_t launch_lds_bytes(const Geom& g, int kind);
 constexpr size_t kMaxLdsBytes = 160 * 1024;
 
 // Geometry helpers (edaa_kernels.hip).
+// Whether chunks of R runs have compiled kernels that fit L bands (LDS of all
+// three pass kernels and the accumulators' band capacity).
+bool runs_fit(int p, int R, int L);
+// Default runs per chunk for M runs (1 when M = 1 or when nothing else fits).
 int runs_per_chunk(int p, int M, int L);
-Geom make_geom(int L, int N, int M, int p);
+// Geometry with R runs per chunk and npg pixel groups (0: defaults).
+Geom make_geom(int L, int N, int M, int p, int R = 0, int npg = 0);
+// Whether the pass kernels can run geometry g.
+bool geom_valid(const Geom& g);
 
 }  // namespace edaa

@@ -51,7 +51,7 @@ def _check_selection(sel, fit_ref, mu_ref, fit_tol=1e-4, mu_tol=1e-4):
 @gpu
 @pytest.mark.parametrize("M,p,L,N,T", [
     (3, 3, 40, 333, 10),      # 4 runs per chunk, one unused slot
-    (6, 3, 40, 333, 10),      # 20 runs per chunk, 14 unused slots
+    (6, 3, 40, 333, 10),      # 8 runs per chunk, 2 unused slots
     (10, 6, 37, 500, 8),      # 8 runs per chunk: two chunks, 6 unused slots
     (20, 12, 60, 257, 6),     # 4 runs per chunk: five full chunks
     (8, 9, 45, 300, 6),       # p = 9: eight-wave A-pass, 4 runs per chunk (waves 4-7 hold no run)
@@ -76,6 +76,58 @@ def test_ensemble_matches_oracle_runs(api, M, p, L, N, T):
     assert np.max(np.abs(r["fit"] - ref["fit"]) / ref["fit"]) < 1e-4
     assert np.max(np.abs(r["mu"] - ref["mu"])) < 1e-4
     _check_selection(r["selected"], ref["fit"], ref["mu"])
+
+
+def _check_runs_vs_oracle(r, ref, N):
+    A, B, E = _np(r["A"]), _np(r["B"]), _np(r["E"])
+    for m, rr in enumerate(ref["runs"]):
+        rel = np.max(np.abs(r["loss"][m] - rr["loss"]) / rr["loss"])
+        assert rel < 1e-4, (m, rel)
+        assert np.max(np.abs(A[m] - rr["A"])) < 1e-3, m
+        assert N * np.max(np.abs(B[m] - rr["B"])) < 1e-2, m
+        assert np.max(np.abs(E[m] - rr["E"])) < 1e-4, m
+    assert np.all(r["status"] == 0)
+    assert np.max(np.abs(r["fit"] - ref["fit"]) / ref["fit"]) < 1e-4
+    # coherence has no pair at p = 1: both sides report -inf
+    assert np.allclose(r["mu"], ref["mu"], rtol=0.0, atol=1e-4)
+
+
+@gpu
+@pytest.mark.parametrize("M,p,L,N", [
+    (4, 4, 300, 400),      # 4 runs per chunk (one column block): 512-band accumulators
+    (6, 1, 300, 400),      # 8 runs per chunk of p = 1
+    (8, 4, 285, 500),      # APEX-shaped bands, 8 runs per chunk (two column blocks)
+    (8, 6, 280, 400),      # 4 runs per chunk (two column blocks), two chunks
+    (4, 12, 300, 300),     # 2 runs per chunk of p = 12
+])
+def test_ensemble_above_256_bands(api, M, p, L, N):
+    """Stacked-run chunks above 256 bands: every band row of X A^T and of the
+    new E is accumulated (rows >= 256 used to be dropped)."""
+    plan = api.plan(L, N, p, M)
+    _say(f"ensemble M={M} p={p} L={L} N={N} plan {plan}")
+    assert plan["runs_per_chunk"] > 1
+    s = synth.small_case(seed=40 + M + p, L=L, N=N, p=min(p, 8))
+    Xg, X = _prep(s.X)
+    seeds = [m // 2 for m in range(M)]
+    gammas = [(0.5, 2.0)[m % 2] for m in range(M)]
+    r = api.ensemble(Xg, p, seeds, gammas, T=5)
+    _check_runs_vs_oracle(r, O.ensemble(X, p, seeds, gammas, T=5), N)
+
+
+@gpu
+@pytest.mark.parametrize("p,R", [(1, 20), (3, 20), (3, 8), (3, 4), (3, 1), (4, 16), (5, 12), (5, 8),
+                                 (7, 8), (9, 2), (12, 2), (12, 4), (16, 2), (16, 4)])
+def test_every_chunk_size_matches_oracle(api, p, R):
+    """Each compiled chunk size, pinned through runs_per_chunk, on M = R + 1
+    runs (one full chunk and one with a single run)."""
+    M, L, N = R + 1, 50, 300
+    _say(f"ensemble p={p} runs_per_chunk={R} M={M}")
+    s = synth.small_case(seed=60 + p, L=L, N=N, p=min(p, 8))
+    Xg, X = _prep(s.X)
+    seeds = list(range(M))
+    gammas = [(0.5, 1.0, 2.0)[m % 3] for m in range(M)]
+    r = api.ensemble(Xg, p, seeds, gammas, T=5, runs_per_chunk=R)
+    _check_runs_vs_oracle(r, O.ensemble(X, p, seeds, gammas, T=5), N)
 
 
 @gpu
@@ -178,6 +230,9 @@ def test_urban_long_horizon_vs_fp64_traces(api):
         rel_bs = abs(r["loss"][m][-1] - one["loss"][-1]) / one["loss"][-1]
         _say(f"run {m}: batched {rel_b:.2e} single {rel_s:.2e} batched-vs-single final {rel_bs:.2e}")
         assert rel_b <= tol and rel_s <= tol and rel_bs <= 1e-3
+
+
+GOLD_ENVELOPE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "hundred_fp32_envelope.txt")
 
 
 @gpu

@@ -1,0 +1,78 @@
+"""CPU checks of the launch-shape logic (edaa_plan, a host-only call): every
+shape the library would launch has pass kernels whose accumulators cover all
+L bands and whose LDS fits, explicit requests are honoured or refused with
+EDAA_EUNSUPPORTED, and stacked-run chunks stay available at large L."""
+import itertools
+
+import pytest
+
+from paper_2209_11002_amd import _lib as L_
+from paper_2209_11002_amd import api
+
+# compiled runs per chunk, largest first (as the library lists them)
+def _choices(p):
+    if p > 8:
+        return [4, 2, 1]
+    rmax = 8 if p > 5 else 12 if p == 5 else 16 if p == 4 else 20
+    return [rmax] + ([8] if rmax > 8 else []) + [4, 1]
+
+
+def _band_capacity(p, R):
+    """Bands the accumulators of a chunk of R runs hold: 16-band row blocks,
+    8 per wave-quarter for chunks of at most two 16-column blocks, else 4."""
+    col_blocks = (p * R + 15) // 16
+    return 4 * 16 * (8 if col_blocks <= 2 else 4)
+
+
+def test_default_shapes_cover_every_band():
+    for L, p, M in itertools.product((1, 16, 100, 162, 224, 256, 257, 272, 285, 300, 352, 400, 448),
+                                     range(1, 17), (1, 2, 4, 5, 8, 13, 50, 100)):
+        N = 4096
+        try:
+            pl = api.plan(L, N, p, M)
+        except L_.EdaaError as e:
+            assert e.status == L_.EDAA_EUNSUPPORTED, (L, p, M)
+            continue
+        R = pl["runs_per_chunk"]
+        assert R in _choices(p), (L, p, M, R)
+        assert L <= _band_capacity(p, R), (L, p, M, R)
+        assert pl["chunks"] == -(-M // R)
+        assert 1 <= pl["pixel_groups"] <= N // 64
+        if M == 1:
+            assert R == 1
+
+
+@pytest.mark.parametrize("L,p,M", [(300, 4, 4), (300, 1, 6), (285, 4, 50), (280, 6, 8), (300, 12, 4)])
+def test_large_L_keeps_stacked_runs(L, p, M):
+    """Above 256 bands a chunk of at most two column blocks still stacks
+    runs (an APEX-shaped L=285, p=4, M=50 ensemble no longer drops to one run
+    per chunk)."""
+    pl = api.plan(L, 13542, p, M)
+    assert pl["runs_per_chunk"] > 1
+    assert L <= _band_capacity(p, pl["runs_per_chunk"])
+
+
+def test_requests_are_honoured_or_refused():
+    assert api.plan(162, 94249, 6, 50, runs_per_chunk=4)["runs_per_chunk"] == 4
+    assert api.plan(162, 94249, 6, 50, runs_per_chunk=4)["source"] == "requested"
+    assert api.plan(162, 94249, 6, 50, pixel_groups=40)["pixel_groups"] == 40
+    assert api.plan(162, 1000, 6, 50, pixel_groups=400)["pixel_groups"] == 16     # capped at the tile count
+    for R in (3, 5, 16):                       # not compiled for p = 6
+        with pytest.raises(L_.EdaaError) as e:
+            api.plan(162, 94249, 6, 50, runs_per_chunk=R)
+        assert e.value.status == L_.EDAA_EUNSUPPORTED
+    with pytest.raises(L_.EdaaError) as e:     # three column blocks hold 256 bands only
+        api.plan(300, 1000, 6, 8, runs_per_chunk=8)
+    assert e.value.status == L_.EDAA_EUNSUPPORTED
+    with pytest.raises(L_.EdaaError) as e:
+        api.plan(162, 1000, 6, 8, runs_per_chunk=-1)
+    assert e.value.status == L_.EDAA_EINVAL
+    with pytest.raises(L_.EdaaError) as e:
+        api.plan(500, 1000, 6, 8)
+    assert e.value.status == L_.EDAA_EINVAL
+
+
+def test_every_compiled_chunk_size_is_plannable_at_small_L():
+    for p in range(1, 17):
+        for R in _choices(p):
+            assert api.plan(64, 2000, p, 2 * R, runs_per_chunk=R)["runs_per_chunk"] == R
