@@ -242,39 +242,47 @@ def test_hundred_runs_gamma_drawn_from_S(api):
     oracle, and the selection of Algorithm 2 against the oracle's fits and
     coherences (allowing the ties float32 cannot separate).
 
-    The gate is conditioned per run.  The oracle run in float32 (same steps,
-    plain float32 arithmetic) measures how much rounding alone moves each
-    trajectory: at gamma <= 0.5 it stays within about 1e-7, while at gamma
-    of 1 and above the larger steps amplify it up to about 1e-4 by T = 10.
-    Every run must agree to the float32 gate of 1e-4 relative, or to ten
-    times its own float32 drift where that is larger (the GPU rounds in a
-    different order, so on an amplifying run its deviation is another draw
-    of the same noise); the calm runs must agree to 1e-6."""
+    Gates, per run and for each of the objective trace, the l1 fit and the
+    coherence.  tests/golden/hundred_fp32_envelope.txt holds how far plain
+    float32 arithmetic lands from float64 on each run: the oracle's own steps
+    in float32 with the pixels in 8 orders (an exact symmetry, so each order
+    is an equally valid float32 evaluation).
+      * Runs where float32 arithmetic stays within 1e-4 in all 8 orders (81
+        of 100): the float32 gate of 1e-4.
+      * Runs where it does not (the large steps, gamma >= 2, amplify rounding
+        from the first iterations on; float32 lands up to 4.9e-4 away): the
+        GPU must stay inside that measured float32 spread, and on average be
+        at least as close to float64 as the median float32 evaluation.
+      * Calm runs (gamma <= 0.5): 1e-6."""
     s = synth.small_case(seed=90, L=40, N=333, p=3)
     Xg, X = _prep(s.X)
     rng = np.random.default_rng(2209)
     gammas = [float(g) for g in rng.choice(O.GAMMA_SET, size=100)]
     seeds = list(range(100))
+    env = np.loadtxt(GOLD_ENVELOPE)
+    assert np.array_equal(env[:, 0], np.arange(100)) and np.allclose(env[:, 1], gammas)
     _say("M=100, gamma ~ U(S), T=10")
     r = api.ensemble(Xg, 3, seeds, gammas, T=10)
-    fit_ref, mu_ref, d32, dl = np.zeros(100), np.zeros(100), np.zeros(100), np.zeros(100)
+    fit_ref, mu_ref, dl = np.zeros(100), np.zeros(100), np.zeros(100)
     for m in range(100):
         ref = O.edaa_fit(X, 3, T=10, gamma=gammas[m], seed=seeds[m])
-        r32 = O.edaa_fit(X, 3, T=10, gamma=gammas[m], seed=seeds[m], dtype=np.float32)
-        d32[m] = np.max(np.abs(r32["loss"] - ref["loss"]) / ref["loss"])
         dl[m] = np.max(np.abs(r["loss"][m] - ref["loss"]) / ref["loss"])
         fit_ref[m] = O.fit_l1(X, ref["E"], ref["A"])
         mu_ref[m] = O.coherence(ref["E"])
     df = np.abs(r["fit"] - fit_ref) / fit_ref
     dm = np.abs(r["mu"] - mu_ref)
-    tol = np.maximum(1e-4, 10.0 * d32)
     calm = np.array(gammas) <= 0.5
-    w = int(np.argmax(dl / tol))
-    _say(f"loss rel: calm runs {dl[calm].max():.2e}, others {dl[~calm].max():.2e}; tightest run {w} "
-         f"(gamma {gammas[w]}) {dl[w]:.2e} of {tol[w]:.2e}; selected {r['selected']} "
-         f"(oracle {O.select(fit_ref, mu_ref)})")
-    assert calm.sum() >= 20 and d32[calm].max() <= 1e-6
-    for d in (dl, df, dm):
-        assert np.all(d <= tol)
-        assert d[calm].max() <= 1e-6
+    assert calm.sum() >= 20
+    for name, d, med, mx in (("loss", dl, env[:, 2], env[:, 3]), ("fit", df, env[:, 4], env[:, 5]),
+                             ("mu", dm, env[:, 6], env[:, 7])):
+        well = mx <= 1e-4
+        _say(f"{name}: {well.sum()} runs where float32 meets 1e-4: max {d[well].max():.2e}; "
+             f"{(~well).sum()} others: max ratio to the float32 spread "
+             f"{(d[~well] / mx[~well]).max() if (~well).any() else 0:.2f}, mean {d[~well].mean() if (~well).any() else 0:.2e} "
+             f"vs float32 median {med[~well].mean() if (~well).any() else 0:.2e}; calm max {d[calm].max():.2e}")
+        assert np.all(d[well] <= 1e-4), name
+        assert np.all(d[~well] <= mx[~well]), name
+        if (~well).any():
+            assert d[~well].mean() <= med[~well].mean(), name
+        assert d[calm].max() <= 1e-6, name
     _check_selection(r["selected"], fit_ref, mu_ref)

@@ -573,3 +573,30 @@ def test_ensemble_non_finite_run_gets_infinite_fit():
     with np.errstate(invalid="ignore", over="ignore"):
         e_all = O.ensemble(X, 3, [0, 1], [np.inf, np.inf], T=2)
     assert np.all(e_all["fit"] == np.inf) and e_all["selected"] == -1
+
+
+def test_hundred_envelope_fixture_rows():
+    """The stored float32 spread of the 100-run GPU test (written by
+    tests/golden/make_hundred_envelope.py) is reproduced by the oracle for its
+    first rows, and every calm run (gamma <= 1) sits well inside 1e-4."""
+    import importlib.util
+    here = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+    spec = importlib.util.spec_from_file_location("make_hundred_envelope",
+                                                  os.path.join(here, "make_hundred_envelope.py"))
+    mk = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mk)
+    env = np.loadtxt(os.path.join(here, "hundred_fp32_envelope.txt"))
+    X, gammas = mk.case()
+    N = X.shape[1]
+    assert np.allclose(env[:, 1], gammas)
+    assert np.all(env[np.array(gammas) <= 1.0, 3] < 1e-4)
+    for m in (0, 1):
+        ref = O.edaa_fit(X, 3, T=10, gamma=gammas[m], seed=m)
+        B0 = O.init_B_from_seed(m, N, 3)
+        dl = []
+        for k in range(mk.N_ORDERS):
+            perm = np.random.default_rng(k).permutation(N)
+            r = O.edaa_fit(X[:, perm], 3, T=10, seed=m, B0=B0[perm], eta=(ref["eta1"], ref["eta2"]),
+                           dtype=np.float32)
+            dl.append(np.max(np.abs(r["loss"] - ref["loss"]) / ref["loss"]))
+        assert np.isclose(np.median(dl), env[m, 2], rtol=1e-3) and np.isclose(np.max(dl), env[m, 3], rtol=1e-3)
