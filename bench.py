@@ -12,8 +12,12 @@ timed region starts.
 Printed: one JSON line with run-iterations/s (M * T per step), the
 algorithmic HBM rate, the roofline of the dominant kernel (the B-pass, timed
 with HIP events recorded around each of its launches on its launch stream),
-the plain path (single runs on the same data, at equal final loss) and the
-float64 oracle timed on this host's cores on a bounded sample.
+the error of the headline runs against stored float64 traces, the plain path
+(single runs on the same data, at equal final loss, with its own HBM roofline
+on the Urban-shaped scene and on the large L=224, N=512x614, p=12 scene), the
+Samson- and Jasper-shaped single runs, the BF16-X ensemble on the large scene
+with its error against float64, the ragged batch against per-image launches,
+and the float64 oracle timed on this host's cores on a bounded sample.
 """
 import argparse
 import json
@@ -27,8 +31,12 @@ if ROOT not in sys.path:
 
 FP32_MFMA_TFLOPS = 157.3          # MI355X dense FP32 matrix peak (v_mfma_f32_16x16x4f32: 32 cycles/SIMD)
 HBM_GBS = 8000.0
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_bpass_urban_ensemble_traffic.txt")
-KERNEL_SOURCE = os.path.join(ROOT, "paper_2209_11002_amd", "csrc", "edaa_kernels.hip")
+PROFILES = os.path.join(ROOT, "profiles")
+TRAFFIC_FILE = os.path.join(PROFILES, "k_bpass_urban_ensemble_traffic.txt")
+PLAIN_TRAFFIC_FILE = os.path.join(PROFILES, "k_bpass_large_single_traffic.txt")
+GOLDEN = os.path.join(ROOT, "tests", "golden")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2209_11002_amd", "csrc", f)
+                  for f in ("edaa_device.h", "edaa_inst.hip", "edaa_kernels.hip")]
 
 
 def log(*a):
@@ -36,17 +44,22 @@ def log(*a):
 
 
 def kernel_source_sha256():
+    """SHA-256 over the pass-kernel sources (the device code and its
+    launchers), which the stored counter summaries record."""
     import hashlib
-    with open(KERNEL_SOURCE, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()
+    h = hashlib.sha256()
+    for path in KERNEL_SOURCES:
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
 
 
-def stored_traffic():
-    """HBM bytes per B-pass launch from the committed counter summary, or None
+def stored_traffic(path):
+    """HBM bytes per B-pass launch from a committed counter summary, or None
     when it is missing or was taken from another version of the kernels."""
     try:
         fields = {}
-        with open(TRAFFIC_FILE) as f:
+        with open(path) as f:
             for line in f:
                 if ":" in line and not line.startswith(" "):
                     k, v = line.split(":", 1)
@@ -58,10 +71,12 @@ def stored_traffic():
         return None
 
 
-def profile_run(T):
-    """Workload for rocprofv3 counter passes: a plain device copy of known size
-    (the calibration of FETCH_SIZE / WRITE_SIZE) and then a short ensemble on
-    the bench scene (T outer iterations, so 5 T B-pass launches)."""
+def profile_run(T, workload):
+    """Workload for rocprofv3 passes: a plain device copy of known size (the
+    calibration of FETCH_SIZE / WRITE_SIZE) and then T outer iterations of
+    'urban_ensemble' (the headline ensemble), 'urban_single' (one run on the
+    same scene) or 'large_single' (one run on the L=224, N=512x614, p=12
+    scene, float32 X)."""
     import torch
     from paper_2209_11002_amd import api, synth
     dev = torch.device("cuda:0")
@@ -70,12 +85,21 @@ def profile_run(T):
     dst = torch.empty_like(src)
     torch.mul(src, 1.0, out=dst)          # reads and writes exactly nbytes
     torch.cuda.synchronize()
+    del src, dst
     log(f"calibration copy: {nbytes} bytes read, {nbytes} bytes written")
-    scene, cfg = synth.urban_ensemble()
+    if workload == "large_single":
+        scene, cfg = synth.large_smooth()
+        p = 12
+    else:
+        scene, cfg = synth.urban_ensemble()
+        p = 6
     X = api.normalize_pixels(torch.from_numpy(scene.X).to(dev))
-    api.ensemble(X, 6, cfg["seeds"], cfg["gammas"], T=T, K1=cfg["K1"], K2=cfg["K2"])
+    if workload == "urban_ensemble":
+        api.ensemble(X, p, cfg["seeds"], cfg["gammas"], T=T, K1=cfg["K1"], K2=cfg["K2"])
+    else:
+        api.fit(X, p, T=T, K1=cfg["K1"], K2=cfg["K2"], gamma=1.0, seed=0)
     torch.cuda.synchronize()
-    log(f"profile run done (T={T})")
+    log(f"profile run done ({workload}, T={T})")
 
 
 def summarize(paths):
@@ -98,11 +122,57 @@ def summarize(paths):
             print(f"    {c:24s} mean {sum(v) / len(v):16.6g}   dispatches {len(v)}")
 
 
+def pass_bytes(L, N, Q, x_bytes=4):
+    """Algorithmic HBM bytes of one pass: X read once, Q rows of pixel
+    weights (or abundances) read and written in float32."""
+    return L * N * x_bytes + 2 * Q * N * 4
+
+
+def time_single_runs(X, p, T, runs, gammas, seeds, out):
+    """run-iterations/s of `runs` single fits replayed from one captured
+    graph (outputs preallocated, so every call replays the same graph)."""
+    import torch
+    from paper_2209_11002_amd import api
+    api.fit(X, p, T=T, gamma=gammas[0], seed=seeds[0], graph=True, out=out)      # capture
+    torch.cuda.synchronize()
+    losses = []
+    t0 = time.perf_counter()
+    for m in range(runs):
+        r = api.fit(X, p, T=T, gamma=gammas[m % len(gammas)], seed=seeds[m % len(seeds)], graph=True, out=out)
+        losses.append(r["loss"][-1])
+    torch.cuda.synchronize()
+    return runs * T / (time.perf_counter() - t0), losses
+
+
+def plain_pass_roofline(X, p, T, label, traffic_path=None):
+    """Pass durations of one eager single run (HIP events around each launch)
+    and the B-pass HBM roofline: algorithmic bytes per launch / its mean
+    duration against 8 TB/s."""
+    import torch
+    from paper_2209_11002_amd import api
+    dev = X.device
+    L, N = X.shape
+    api.fit(X, p, T=T, gamma=1.0, seed=0, time_passes=True)
+    nb, bms = api.pass_times(dev, 1)
+    na, ams = api.pass_times(dev, 0)
+    torch.cuda.synchronize()
+    b_s, a_s = bms / nb / 1e3, ams / na / 1e3
+    nbytes = pass_bytes(L, N, p, 2 if X.dtype == torch.bfloat16 else 4)
+    gbs = nbytes / b_s / 1e9
+    return dict(bound="hbm", kernel=f"k_bpass<{p}, 1, true> (B-pass, one run)", workload=label,
+                achieved=round(gbs, 1), peak=HBM_GBS, unit="GB/s", frac=round(gbs / HBM_GBS, 4),
+                traffic=stored_traffic(traffic_path) if traffic_path else None,
+                algorithmic_bytes_per_launch=nbytes, avg_launch_us=round(b_s * 1e6, 2),
+                apass_avg_launch_us=round(a_s * 1e6, 2),
+                apass_achieved_gbs=round(nbytes / a_s / 1e9, 1))
+
+
 def bench_ragged(n_images, T):
     """Ragged batch: single runs (gamma 1, seed = image index) on n_images
     images of different (L, N, p), batched (one launch per kernel and group of
     equal p, replayed from a HIP graph) against per-image fits (each replayed
-    from its own graph).  Returns image-iterations/s of both."""
+    from its own graph; outputs preallocated and every graph captured before
+    the timed region).  Returns image-iterations/s of both."""
     import numpy as np
     import torch
     from paper_2209_11002_amd import api, synth
@@ -112,43 +182,78 @@ def bench_ragged(n_images, T):
     ps = [sc.M.shape[1] for sc in scenes]
     seeds = list(range(n_images))
     gammas = [1.0] * n_images
+    api.set_graph_cache(dev, n_images + 8)
     api.fit_ragged(X, ps, seeds, gammas, T=T, graph=True)            # capture
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     rb = api.fit_ragged(X, ps, seeds, gammas, T=T, graph=True)
     torch.cuda.synchronize()
     tb = time.perf_counter() - t0
-    for k in range(n_images):                                         # capture
-        api.fit(X[k], ps[k], T=T, gamma=1.0, seed=k, graph=True)
+    outs = [dict(A=torch.empty((ps[k], x.shape[1]), device=dev), B=torch.empty((x.shape[1], ps[k]), device=dev),
+                 E=torch.empty((x.shape[0], ps[k]), device=dev)) for k, x in enumerate(X)]
+    for k in range(n_images):                                         # capture every per-image graph
+        api.fit(X[k], ps[k], T=T, gamma=1.0, seed=k, graph=True, out=outs[k])
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    rs = [api.fit(X[k], ps[k], T=T, gamma=1.0, seed=k, graph=True) for k in range(n_images)]
+    rs = [api.fit(X[k], ps[k], T=T, gamma=1.0, seed=k, graph=True, out=outs[k]) for k in range(n_images)]
     torch.cuda.synchronize()
     ts = time.perf_counter() - t0
     same = all(np.array_equal(a["loss"], b["loss"]) for a, b in zip(rb, rs))
     pixels = sum(sc.X.shape[1] for sc in scenes)
+    nbytes = sum(pass_bytes(sc.X.shape[0], sc.X.shape[1], ps[k]) for k, sc in enumerate(scenes))
+    per_outer = 6 * nbytes
+    gbs = per_outer * T / tb / 1e9
     return dict(unit="image-iterations/s", images=n_images, T=T, pixels=pixels,
                 batched=round(n_images * T / tb, 2), per_image=round(n_images * T / ts, 2),
-                speedup=round(ts / tb, 3), identical_to_per_image=bool(same))
+                speedup=round(ts / tb, 3), identical_to_per_image=bool(same),
+                algorithmic_bytes_per_outer_iteration=per_outer, batched_gbs=round(gbs, 1),
+                batched_hbm_frac=round(gbs / HBM_GBS, 4))
 
 
-def bench_bf16_large(T):
-    """BF16 X on the large smooth scene (L=224, N=512x614, p=12, M=20): the
-    batched ensemble with X stored in bf16, against the same ensemble with
-    float32 X (run-iterations/s of both, and the largest relative difference
-    of the final objective between them)."""
+def rel_err(a, b):
+    import numpy as np
+    return float(np.max(np.abs(np.asarray(a) - np.asarray(b)) / np.abs(np.asarray(b))))
+
+
+def errors_vs_reference(r, ref, runs, T, idx, suffix):
+    """Max errors of GPU runs against the stored float64 results: objective
+    (relative, whole trace), E (max-abs), A and N*B (max-abs on the sampled
+    pixels)."""
+    import numpy as np
+    N = r["A"].shape[2]
+    out = dict(loss_rel=0.0, E_abs=0.0, A_abs=0.0, NB_abs=0.0)
+    for k, m in enumerate(runs):
+        out["loss_rel"] = max(out["loss_rel"], rel_err(r["loss"][m][:T + 1], ref[f"loss{suffix}"][k]))
+        out["E_abs"] = max(out["E_abs"], float(np.max(np.abs(r["E"][m].cpu().numpy() - ref[f"E{suffix}"][k]))))
+        A = r["A"][m][:, idx].cpu().numpy()
+        B = r["B"][m][idx, :].cpu().numpy()
+        out["A_abs"] = max(out["A_abs"], float(np.max(np.abs(A - ref[f"A{suffix}"][k]))))
+        out["NB_abs"] = max(out["NB_abs"], float(N * np.max(np.abs(B - ref[f"B{suffix}"][k]))))
+    return {k: float(f"{v:.3g}") for k, v in out.items()}
+
+
+def bench_large(T, error_T=10):
+    """The large smooth scene (L=224, N=512x614, p=12, M=20): the batched
+    ensemble with bf16 X and with float32 X (run-iterations/s), and their
+    errors against the stored float64 results (every run at T = 10; runs 0
+    and 4 at T = 100), plus the plain single-run path on float32 X with its
+    B-pass HBM roofline."""
     import numpy as np
     import torch
     from paper_2209_11002_amd import api, synth
     scene, cfg = synth.large_smooth()
     dev = torch.device("cuda:0")
     Xraw = torch.from_numpy(scene.X).to(dev)
+    del scene
     X32 = api.normalize_pixels(Xraw)
     X16 = api.normalize_pixels(Xraw, out_dtype=torch.bfloat16)
     del Xraw
     seeds, gammas = cfg["seeds"], cfg["gammas"]
     M, p = len(seeds), 12
-    res = {}
+    L, N = X32.shape
+    ref_path = os.path.join(GOLDEN, "large_fp64_ref.npz")
+    ref = dict(np.load(ref_path)) if os.path.exists(ref_path) else None
+    res, errs = {}, {}
     for name, X in (("bf16", X16), ("f32", X32)):
         api.ensemble(X, p, seeds, gammas, T=T, graph=True)
         torch.cuda.synchronize()
@@ -156,27 +261,79 @@ def bench_bf16_large(T):
         r = api.ensemble(X, p, seeds, gammas, T=T, graph=True)
         torch.cuda.synchronize()
         res[name] = (M * T / (time.perf_counter() - t0), r["loss"][:, -1].copy())
+        if ref is not None:
+            e = {}
+            long_runs = [int(m) for m in ref["long_runs"]]
+            if T >= 100:
+                e["T100_runs_0_4"] = errors_vs_reference(r, ref, long_runs, 100, ref["idx"], "100")
+            r10 = api.ensemble(X, p, seeds, gammas, T=error_T)
+            e["T10_all_runs"] = errors_vs_reference(r10, ref, list(range(M)), error_T, ref["idx"], "10")
+            errs[name] = e
+        log(f"large scene {name}: {res[name][0]:.1f} run-it/s")
     rel = float(np.max(np.abs(res["bf16"][1] - res["f32"][1]) / res["f32"][1]))
-    L, N = X32.shape
-    return dict(unit="run-iterations/s", L=L, N=N, p=p, M=M, T=T, bf16=round(res["bf16"][0], 2),
-                f32=round(res["f32"][0], 2), final_loss_max_rel_diff_bf16_vs_f32=rel)
+    Q = M * p
+    per_outer_bf16 = 6 * pass_bytes(L, N, Q, 2)
+    out = dict(unit="run-iterations/s", L=L, N=N, p=p, M=M, T=T, bf16=round(res["bf16"][0], 2),
+               f32=round(res["f32"][0], 2), final_loss_max_rel_diff_bf16_vs_f32=rel,
+               bf16_gbs=round(per_outer_bf16 * res["bf16"][0] / M / 1e9, 1),
+               bf16_hbm_frac=round(per_outer_bf16 * res["bf16"][0] / M / 1e9 / HBM_GBS, 4),
+               error_vs_fp64=errs or None)
+    del X16
+    plain = plain_pass_roofline(X32, p, 5, f"one run, L={L} N={N} p={p}, float32 X (X > 256 MB MALL)",
+                                PLAIN_TRAFFIC_FILE)
+    outp = dict(A=torch.empty((p, N), device=dev), B=torch.empty((N, p), device=dev),
+                E=torch.empty((L, p), device=dev))
+    v, _ = time_single_runs(X32, p, 10, 3, [1.0], [0], outp)
+    plain["run_iterations_per_s"] = round(v, 2)
+    return out, plain
 
 
-def cpu_baseline(Xraw, p, seed, gamma, T_sample):
-    """The float64 oracle as it stands, on the same scene, for T_sample outer
-    iterations of one run; returns run-iterations/s and the threads used."""
+def bench_small_plain(which):
+    """Samson-shaped (T=200) or Jasper-shaped (T=100) single runs, replayed
+    from a captured graph: run-iterations/s."""
+    import torch
+    from paper_2209_11002_amd import api, synth
+    scene, cfg = (synth.samson_like() if which == "samson" else synth.jasper_like())
+    dev = torch.device("cuda:0")
+    X = api.normalize_pixels(torch.from_numpy(scene.X).to(dev))
+    L, N = X.shape
+    p = scene.M.shape[1]
+    out = dict(A=torch.empty((p, N), device=dev), B=torch.empty((N, p), device=dev),
+               E=torch.empty((L, p), device=dev))
+    v, _ = time_single_runs(X, p, cfg["T"], 5, cfg["gammas"], cfg["seeds"], out)
+    per_outer = 6 * pass_bytes(L, N, p)
+    return dict(unit="run-iterations/s", L=L, N=N, p=p, T=cfg["T"], value=round(v, 2),
+                algorithmic_gbs=round(per_outer * v / 1e9, 1))
+
+
+def cpu_baseline(Xraw, p, seed, gamma, T_all, T_one):
+    """The float64 oracle as it stands, on the same scene: T_all outer
+    iterations of one run with every host thread, then T_one with one BLAS
+    thread; run-iterations/s of both."""
+    import platform
     import numpy as np
     from oracle import edaa as O
+    from threadpoolctl import threadpool_info, threadpool_limits
+    threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    model = platform.processor() or ""
     try:
-        from threadpoolctl import threadpool_info
-        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
-    except Exception:
-        threads = 1
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
     X, _ = O.normalize_pixels(Xraw.astype(np.float64))
     t0 = time.perf_counter()
-    O.edaa_fit(X, p, T=T_sample, gamma=gamma, seed=seed)
-    dt = time.perf_counter() - t0
-    return T_sample / dt, threads, dt
+    O.edaa_fit(X, p, T=T_all, gamma=gamma, seed=seed)
+    dt_all = time.perf_counter() - t0
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        O.edaa_fit(X, p, T=T_one, gamma=gamma, seed=seed)
+        dt_one = time.perf_counter() - t0
+    return dict(all_threads=T_all / dt_all, threads=threads, one_thread=T_one / dt_one,
+                s_all=dt_all, s_one=dt_one, cpu_model=model, cpu_count=os.cpu_count())
 
 
 def main():
@@ -185,12 +342,17 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--plain-runs", type=int, default=5, help="single runs timed for the plain path (0: skip)")
-    ap.add_argument("--cpu-sample-T", type=int, default=40, help="oracle outer iterations timed (0: skip)")
+    ap.add_argument("--cpu-sample-T", type=int, default=20,
+                    help="oracle outer iterations timed with all threads (0: skip); a quarter with one thread")
     ap.add_argument("--n-seeds", type=int, default=10)
     ap.add_argument("--ragged-images", type=int, default=64, help="images of the ragged batch (0: skip)")
-    ap.add_argument("--bf16-T", type=int, default=100, help="outer iterations of the BF16 large-scene runs (0: skip)")
+    ap.add_argument("--large-T", "--bf16-T", dest="large_T", type=int, default=100,
+                    help="outer iterations of the large-scene ensembles (0: skip the large scene)")
+    ap.add_argument("--small-plain", type=int, default=1, help="time the Samson- and Jasper-shaped runs (0: skip)")
     ap.add_argument("--profile-run", type=int, default=0, metavar="T",
-                    help="run the counter-profiling workload with T outer iterations and exit")
+                    help="run a counter-profiling workload with T outer iterations and exit")
+    ap.add_argument("--profile-workload", default="urban_ensemble",
+                    choices=("urban_ensemble", "urban_single", "large_single"))
     ap.add_argument("--summarize", nargs="+", metavar="CSV", help="summarise rocprofv3 CSV files and exit")
     args = ap.parse_args()
     if args.summarize:
@@ -201,7 +363,7 @@ def main():
               "(run it with --gpus 1)", file=sys.stderr)
         sys.exit(2)
     if args.profile_run > 0:
-        profile_run(args.profile_run)
+        profile_run(args.profile_run, args.profile_workload)
         return
 
     import numpy as np
@@ -214,7 +376,7 @@ def main():
     p, T, K1, K2 = 6, cfg["T"], cfg["K1"], cfg["K2"]
     seeds, gammas = cfg["seeds"], cfg["gammas"]
     M = len(seeds)
-    log(f"scene L={L} N={N} p={p} M={M} T={T}")
+    log(f"scene L={L} N={N} p={p} M={M} T={T}, plan {api.plan(L, N, p, M)}")
     Xraw = torch.from_numpy(scene.X).to(dev)
     out = dict(A=torch.empty((M, p, N), device=dev), B=torch.empty((M, N, p), device=dev),
                E=torch.empty((M, L, p), device=dev))
@@ -233,7 +395,6 @@ def main():
     # Timed region: eager launches, with HIP events recorded around every pass
     # launch on the library's stream (events inside a replayed graph carry no
     # timestamps on this runtime).
-
     b_ms, b_n, a_ms, a_n = 0.0, 0, 0.0, 0
     t0 = time.perf_counter()
     for k in range(args.steps):
@@ -263,19 +424,18 @@ def main():
     # algorithmic bytes and flops (float32 state, X read once per pass)
     Q = M * p
     xb = L * N * 4
-    bpass_bytes = xb + 2 * Q * N * 4
+    bpass_bytes = pass_bytes(L, N, Q)
     bpass_flops = 4.0 * L * N * Q
-    apass_bytes = xb + 2 * Q * N * 4
     step_bytes = (2 * xb                       # normalisation
                   + xb + 2 * Q * N * 4         # A0 fill + init pass (writes B)
-                  + T * (apass_bytes + K2 * bpass_bytes)
+                  + T * (1 + K2) * bpass_bytes
                   + xb + Q * N * 4             # closing pass
                   + 2 * Q * N * 4)             # B output
     b_avg_s = b_ms / max(b_n, 1) / 1e3
     a_avg_s = a_ms / max(a_n, 1) / 1e3
     achieved = bpass_flops / b_avg_s / 1e12
     roofline = dict(bound="mfma", achieved=round(achieved, 3), peak=FP32_MFMA_TFLOPS, unit="TFLOP/s",
-                    frac=round(achieved / FP32_MFMA_TFLOPS, 4), traffic=stored_traffic(),
+                    frac=round(achieved / FP32_MFMA_TFLOPS, 4), traffic=stored_traffic(TRAFFIC_FILE),
                     kernel="k_bpass (B-pass)", avg_launch_us=round(b_avg_s * 1e6, 2),
                     algorithmic_bytes_per_launch=bpass_bytes, flops_per_launch=bpass_flops,
                     achieved_gbs=round(bpass_bytes / b_avg_s / 1e9, 1),
@@ -283,44 +443,59 @@ def main():
     final_loss_batched = r["loss"][:, -1].copy()
     log(f"batched: {value:.1f} run-it/s, {ms_per_step:.1f} ms/step, B-pass {b_avg_s * 1e6:.1f} us")
 
+    # error of the headline runs 0 (gamma 0.25) and 4 (gamma 4) against the
+    # stored float64 traces (input normalised on the GPU)
+    gold = np.loadtxt(os.path.join(GOLDEN, "urban_fp64_traces.txt"))
+    headline_err = None
+    if args.n_seeds >= 1:
+        headline_err = {f"run_{m}_gamma_{gammas[m]}_loss_rel_max_over_trace": float(f"{rel_err(r['loss'][m], gold[:, c]):.3g}")
+                        for c, m in ((1, 0), (2, 4))}
+
     plain = None
     if args.plain_runs > 0:
         Xn = api.normalize_pixels(Xraw)
-        api.fit(Xn, p, T=T, gamma=gammas[0], seed=seeds[0], graph=True)   # capture
-        torch.cuda.synchronize()
-        losses = []
-        t0 = time.perf_counter()
-        for m in range(args.plain_runs):
-            rr = api.fit(Xn, p, T=T, K1=K1, K2=K2, gamma=gammas[m], seed=seeds[m], graph=True)
-            losses.append(rr["loss"][-1])
-        torch.cuda.synchronize()
-        pdt = time.perf_counter() - t0
-        pval = args.plain_runs * T / pdt
-        rel = float(np.max(np.abs(np.array(losses) - final_loss_batched[:args.plain_runs])
-                           / final_loss_batched[:args.plain_runs]))
+        outp = dict(A=torch.empty((p, N), device=dev), B=torch.empty((N, p), device=dev),
+                    E=torch.empty((L, p), device=dev))
+        pval, losses = time_single_runs(Xn, p, T, args.plain_runs, gammas, seeds, outp)
+        diffs = np.abs(np.array(losses) - final_loss_batched[:args.plain_runs]) / final_loss_batched[:args.plain_runs]
         plain = dict(value=round(pval, 2), unit="run-iterations/s", runs=args.plain_runs,
-                     batched_speedup=round(value / pval, 2), final_loss_max_rel_diff=rel)
-        log(f"plain: {pval:.1f} run-it/s (speedup {value / pval:.2f}x, final-loss rel diff {rel:.2e})")
+                     batched_speedup=round(value / pval, 2),
+                     final_loss_rel_diff_per_run={f"gamma_{gammas[m]}": float(f"{d:.3g}") for m, d in enumerate(diffs)},
+                     roofline_urban=plain_pass_roofline(Xn, p, 5, f"one run, L={L} N={N} p={p} (X fits the MALL)"))
+        log(f"plain: {pval:.1f} run-it/s (speedup {value / pval:.2f}x, final-loss rel diffs {diffs})")
+
+    small = None
+    if args.small_plain:
+        small = dict(samson_shaped=bench_small_plain("samson"), jasper_shaped=bench_small_plain("jasper"))
+        log(f"small plain: {small}")
+
+    large, plain_large = None, None
+    if args.large_T > 0:
+        log("large smooth scene: bf16 and float32 X ensembles, plain single run")
+        large, plain_large = bench_large(args.large_T)
+        log(f"large: {large}")
+        log(f"plain large: {plain_large}")
 
     ragged = None
     if args.ragged_images > 0:
         log(f"ragged batch: {args.ragged_images} images")
         ragged = bench_ragged(args.ragged_images, T)
         log(f"ragged: batched {ragged['batched']} vs per-image {ragged['per_image']} image-it/s")
-    bf16 = None
-    if args.bf16_T > 0:
-        log("bf16 X, large smooth scene")
-        bf16 = bench_bf16_large(args.bf16_T)
-        log(f"bf16: {bf16['bf16']} run-it/s (f32 {bf16['f32']}), final-loss rel diff {bf16['final_loss_max_rel_diff_bf16_vs_f32']:.2e}")
 
     cpu = None
     if args.cpu_sample_T > 0:
         log("timing the float64 oracle on the host")
-        v, threads, cdt = cpu_baseline(scene.X, p, seeds[0], gammas[0], args.cpu_sample_T)
-        cpu = dict(value=round(v, 4), unit="run-iterations/s", cores=threads, kind="oracle",
+        t_one = max(1, args.cpu_sample_T // 4)
+        c = cpu_baseline(scene.X, p, seeds[0], gammas[0], args.cpu_sample_T, t_one)
+        cpu = dict(value=round(c["all_threads"], 4), unit="run-iterations/s", cores=c["threads"], kind="oracle",
                    sample=f"1 run x {args.cpu_sample_T} outer iterations (K1=K2=5) of the float64 oracle "
-                          f"on the full {L}x{N} scene, {cdt:.1f} s")
-        log(f"oracle: {v:.4f} run-it/s on {threads} threads")
+                          f"on the full {L}x{N} scene with {c['threads']} BLAS threads, {c['s_all']:.1f} s; "
+                          f"{t_one} outer iterations with 1 thread, {c['s_one']:.1f} s",
+                   one_thread=round(c["one_thread"], 4), cpu_model=c["cpu_model"], cpu_count=c["cpu_count"])
+        log(f"oracle: {c['all_threads']:.4f} run-it/s on {c['threads']} threads, {c['one_thread']:.4f} on 1")
+
+    if plain is not None and plain_large is not None:
+        plain["roofline"] = plain_large
 
     line = {
         "metric": "EDAA run-iterations/sec + HBM GB/s; batched vs plain at equal loss",
@@ -342,9 +517,11 @@ def main():
         "hbm_gbs": round(step_bytes / (ms_per_step / 1e3) / 1e9, 1),
         "value_graph_replay": round(value_graph, 2),
         "roofline": roofline,
+        "error_vs_fp64": headline_err,
         "plain": plain,
+        "small_plain": small,
+        "large_scene": large,
         "ragged": ragged,
-        "bf16_large": bf16,
         "cpu_baseline": cpu,
         "selected_run": int(r["selected"]),
     }
