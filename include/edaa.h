@@ -170,6 +170,28 @@ edaa_status edaa_fit(edaa_ctx* ctx, const void* X, int L, int N, int p,
                      float* A, float* B, float* E,
                      double* loss_trace, double* eta_out);
 
+/* edaa_fit for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same run on the same kernels, with every intermediate in a fixed 256 MiB
+ * device array that the library holds on each GPU until the process ends,
+ * and no host transfer.  It calls no hipMalloc, hipFree or other allocating
+ * routine.  Differences from edaa_fit:
+ *   loss_trace_dev  out (device, float64, T+1 values, may be NULL)
+ *   eta_dev         out (device, float64, {eta1, eta2}, may be NULL)
+ *   params->flags   must not hold EDAA_FLAG_GRAPH or EDAA_FLAG_TIME_PASSES.
+ * Returns EDAA_EUNSUPPORTED (nothing enqueued) when the run needs more than
+ * the 256 MiB (about L * N * 4 bytes for the padded copy of X plus the run's
+ * state, e.g. L = 224 with N up to about 250 000).  Nothing is synchronised.
+ * All calls on one GPU share that array: two calls whose work overlaps in
+ * time on one GPU (different streams or host threads) race and corrupt each
+ * other; calls ordered on one stream are safe.  Each call initialises every
+ * part of the array it reads. */
+edaa_status edaa_fit_noalloc(edaa_ctx* ctx, const void* X, int L, int N, int p,
+                             const edaa_params* params, uint64_t seed,
+                             const float* A0, const float* B0,
+                             float* A, float* B, float* E,
+                             double* loss_trace_dev, double* eta_dev);
+
 /* M runs of Algorithm 1 on the same X, all advanced together (one pass over
  * X serves every run), then the l1 fit ||X - E_m A_m||_1 (entrywise), the
  * coherence mu_m of E_m (eq. coherence, reading params->coherence_mode) and

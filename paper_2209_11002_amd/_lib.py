@@ -53,6 +53,8 @@ SIGNATURES = {
     "edaa_fit": (c_int, [c_void_p, c_void_p, c_int, c_int, c_int, POINTER(EdaaParams), c_uint64,
                          c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
                          POINTER(c_double), POINTER(c_double)]),
+    "edaa_fit_noalloc": (c_int, [c_void_p, c_void_p, c_int, c_int, c_int, POINTER(EdaaParams), c_uint64,
+                                 c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     "edaa_abundances": (c_int, [c_void_p, c_void_p, c_int, c_int, c_int, POINTER(EdaaParams),
                                 c_void_p, c_void_p, c_void_p, POINTER(c_double), POINTER(c_double)]),
     "edaa_ensemble": (c_int, [c_void_p, c_void_p, c_int, c_int, c_int, POINTER(EdaaParams), c_int,

@@ -153,6 +153,32 @@ def fit(X, p, T=100, K1=5, K2=5, gamma=1.0, seed=0, A0=None, B0=None, eta=None,
                 status=st, launches=lib.edaa_last_launch_count(_ctx(dev)))
 
 
+def fit_noalloc(X, p, out, T=100, K1=5, K2=5, gamma=1.0, seed=0, A0=None, B0=None, eta=None, init_scale=0.1):
+    """fit() through the entry point that allocates nothing (edaa_fit_noalloc):
+    every output is a preallocated GPU tensor in `out` -- A [p, N], B [N, p],
+    E [L, p] float32, loss [T+1] and eta [2] float64 -- and nothing is
+    synchronised or copied to the host.  Returns `out`."""
+    Lb, N = _check_x(X)
+    dev = X.device
+    for k, shp in (("A", (p, N)), ("B", (N, p)), ("E", (Lb, p))):
+        if k not in out:
+            raise ValueError(f"out must hold '{k}'")
+        _check_f32(f"out['{k}']", out[k], shp, dev)
+    for k, n in (("loss", T + 1), ("eta", 2)):
+        t = out.get(k)
+        if t is not None and not (isinstance(t, torch.Tensor) and t.dtype == torch.float64 and t.is_contiguous()
+                                  and tuple(t.shape) == (n,) and t.device == dev):
+            raise ValueError(f"out['{k}'] must be a contiguous float64 tensor of shape ({n},) on {dev}")
+    for name, t, shp in (("A0", A0, (p, N)), ("B0", B0, (N, p))):
+        if t is not None:
+            _check_f32(name, t, shp, dev)
+    P = _params(T, K1, K2, gamma, eta, init_scale, 1.05, _x_dtype(X), "cosine", False)
+    check(L_.load().edaa_fit_noalloc(_ctx(dev), _ptr(X), Lb, N, p, byref(P), c_uint64(seed), _ptr(A0), _ptr(B0),
+                                     _ptr(out["A"]), _ptr(out["B"]), _ptr(out["E"]), _ptr(out.get("loss")),
+                                     _ptr(out.get("eta"))))
+    return out
+
+
 def abundances(X, E, T=100, K1=5, gamma=1.0, A0=None, eta1=None, graph=False):
     """Abundances for given endmembers E [L, p] (float32, GPU): T outer
     iterations of K1 entropic A-steps (eq. update_A with E fixed) on

@@ -7,6 +7,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -60,8 +61,39 @@ struct PassTimer {
 
 }  // namespace
 
+// Device memory of the no-allocation entry point (edaa_fit_noalloc): one
+// copy of this array on every GPU the library runs on, held until the process
+// ends.  Host code never passes the array's name to a kernel or a copy (on
+// the host it is only a stand-in): it uses the device address that
+// hipGetSymbolAddress returns for the current device, looked up once per
+// device by edaa_create and kept in g_scratch_ptr.
+constexpr size_t kScratchBytes = (size_t)256 << 20;
+static __device__ __align__(256) char scratch[kScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on `device` (which must be current); null and
+// a HIP error on failure.
+hipError_t scratch_address(int device, void** out) {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    if (!g_scratch_ptr[device]) {
+        void* p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[device] = p;
+    }
+    *out = g_scratch_ptr[device];
+    return hipSuccess;
+}
+}  // namespace
+
 struct edaa_ctx {
     int device = 0;
+    void* scratch = nullptr;           // this device's copy of `scratch` (device address)
     hipStream_t stream = nullptr;      // the caller's stream
     hipStream_t cap_stream = nullptr;  // private stream used for graph capture
     bool poisoned = false;
@@ -673,8 +705,16 @@ edaa_status edaa_create(edaa_ctx** out, int device, void* stream) {
     }
     if (device < 0 || device >= n) return fail(EDAA_EINVAL, "device %d out of range [0, %d)", device, n);
     if (hipSetDevice(device) != hipSuccess) return fail(EDAA_EDEVICE, "hipSetDevice(%d) failed", device);
+    void* sp = nullptr;
+    const hipError_t se = scratch_address(device, &sp);
+    if (se != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(EDAA_EDEVICE, "hipGetSymbolAddress(scratch) on device %d failed: %s", device,
+                    hipGetErrorString(se));
+    }
     edaa_ctx* ctx = new edaa_ctx();
     ctx->device = device;
+    ctx->scratch = sp;
     ctx->stream = (hipStream_t)stream;
     *out = ctx;
     return EDAA_OK;
@@ -780,6 +820,68 @@ edaa_status edaa_fit(edaa_ctx* ctx, const void* X, int L, int N, int p, const ed
     if (st != EDAA_OK) return st;
     if (loss_trace && !isfinite(loss_trace[params->T]))
         return fail(EDAA_ENUMERIC, "the objective is not finite after %d outer iterations", params->T);
+    return EDAA_OK;
+}
+
+edaa_status edaa_fit_noalloc(edaa_ctx* ctx, const void* X, int L, int N, int p, const edaa_params* params,
+                             uint64_t seed, const float* A0, const float* B0, float* A, float* B, float* E,
+                             double* loss_trace_dev, double* eta_dev) {
+    edaa_status st = check_ctx(ctx);
+    if (st != EDAA_OK) return st;
+    if ((st = check_params(params)) != EDAA_OK) return st;
+    if ((st = check_shape(L, N, p, 1)) != EDAA_OK) return st;
+    EDAA_REQUIRE(X && A && B, "X, A and B must not be null");
+    EDAA_REQUIRE(params->eta1 > 0.0 || (isfinite(params->gamma) && params->gamma > 0.0),
+                 "gamma must be finite and > 0 (got %g)", params->gamma);
+    EDAA_REQUIRE((params->flags & (EDAA_FLAG_GRAPH | EDAA_FLAG_TIME_PASSES)) == 0,
+                 "edaa_fit_noalloc takes neither EDAA_FLAG_GRAPH nor EDAA_FLAG_TIME_PASSES (both allocate)");
+    EDAA_REQUIRE(ctx->scratch != nullptr, "context has no scratch memory");
+    Geom g;
+    if ((st = plan_geom(L, N, p, 1, params, &g, nullptr)) != EDAA_OK) return st;
+    const int x_bytes = params->x_dtype == EDAA_X_BF16 ? 2 : 4;
+    const size_t need = layout(g, params->T, x_bytes, nullptr, nullptr);
+    if (need > kScratchBytes)
+        return fail(EDAA_EUNSUPPORTED,
+                    "L=%d, N=%d, p=%d needs %zu bytes of scratch; edaa_fit_noalloc holds at most %zu (use edaa_fit)",
+                    L, N, p, need, kScratchBytes);
+    RunBuffers rb;
+    memset(&rb, 0, sizeof(rb));
+    layout(g, params->T, x_bytes, (char*)ctx->scratch, &rb);
+    State& s = rb.s;
+    s.A = A;
+    if (loss_trace_dev) s.trace = loss_trace_dev;     // [1][T+1]: the caller's array is the trace
+    if (eta_dev) s.etad = eta_dev;
+    EDAA_HIP(ctx, launch_set_run(rb.seeds, rb.gammas, seed, params->gamma, ctx->stream));
+
+    Seq q;
+    PassTimer off;
+    q.timer = &off;
+    q.g = &g;
+    q.s = &s;
+    q.X = X;
+    q.ri.seeds = rb.seeds;
+    q.ri.gammas = rb.gammas;
+    q.ri.init_scale = (float)params->init_scale;
+    q.ri.B0 = B0;
+    q.ri.A0 = A0;
+    q.ri.eta1 = params->eta1;
+    q.ri.eta2 = params->eta2;
+    q.mode = B0 ? kModeInitB0 : kModeInitRng;
+    q.A0 = A0;
+    q.T = params->T;
+    q.K1 = params->K1;
+    q.K2 = params->K2;
+    q.B_out = B;
+    q.E_out = E;
+    q.coherence_mode = params->coherence_mode;
+    q.E_given = nullptr;
+    long long n = 0;
+    const hipError_t e = enqueue_sequence(q, ctx->stream, &n);
+    if (e != hipSuccess) {
+        ctx->poisoned = true;
+        return fail(EDAA_EDEVICE, "kernel launch failed: %s", hipGetErrorString(e));
+    }
+    ctx->last_launches = n + 1;
     return EDAA_OK;
 }
 

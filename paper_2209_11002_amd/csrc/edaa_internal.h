@@ -175,6 +175,7 @@ hipError_t launch_reduce_a(const Geom& g, const State& s, int t, hipStream_t st)
 hipError_t launch_reduce_aa(const Geom& g, const State& s, int t, hipStream_t st);
 hipError_t launch_set_e(const float* E_given, const Geom& g, const State& s, hipStream_t st);
 hipError_t launch_close(const Geom& g, const State& s, hipStream_t st);
+hipError_t launch_set_run(uint64_t* seeds, double* gammas, uint64_t seed, double gamma, hipStream_t st);
 hipError_t launch_reduce_close(const Geom& g, const State& s, hipStream_t st);
 hipError_t launch_finalize(const Geom& g, const State& s, float* B_out, float* E_out,
                            int coherence_mode, hipStream_t st);

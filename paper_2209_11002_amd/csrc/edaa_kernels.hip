@@ -65,6 +65,15 @@ __global__ void k_set_e(const float* __restrict__ Eg, float* __restrict__ E, dou
     }
 }
 
+// Seed and gamma of a single run into device memory (used where no host copy
+// may be enqueued).
+__global__ void k_set_run(uint64_t* __restrict__ seeds, double* __restrict__ gammas, uint64_t seed, double gamma) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        seeds[0] = seed;
+        gammas[0] = gamma;
+    }
+}
+
 }  // namespace
 
 #define EDAA_DECL_OPS(P) const PassOps* ops_p##P();
@@ -224,6 +233,10 @@ hipError_t launch_set_e(const float* E_given, const Geom& g, const State& s, hip
     const int n = g.L * g.p;
     hipLaunchKernelGGL(k_set_e, dim3(std::max(1, std::min((n + 255) / 256, 1024))), dim3(256), 0, st, E_given, s.E,
                        s.Ed, g.L, g.p, g.Qp);
+    return hipGetLastError();
+}
+hipError_t launch_set_run(uint64_t* seeds, double* gammas, uint64_t seed, double gamma, hipStream_t st) {
+    hipLaunchKernelGGL(k_set_run, dim3(1), dim3(64), 0, st, seeds, gammas, seed, gamma);
     return hipGetLastError();
 }
 hipError_t launch_reduce_close(const Geom& g, const State& s, hipStream_t st) {
