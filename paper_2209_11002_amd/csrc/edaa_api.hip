@@ -530,7 +530,7 @@ hipError_t enqueue_ragged(const std::vector<RaggedGroup>& groups, const std::vec
     if ((e = L_(kMultiEta, kMapOne, 0, 0)) != hipSuccess) return e;
     for (int t = 0; t < T; ++t) {
         if ((e = Lp(kMultiApass, &RaggedGroup::lds_a, K1)) != hipSuccess) return e;
-        if ((e = L_(kMultiRedAA, kMapOne, 0, t)) != hipSuccess) return e;
+        if ((e = L_(kMultiRedAA, kMapAA, 0, t)) != hipSuccess) return e;
         if ((e = L_(kMultiRedA, kMapRows, 0, t)) != hipSuccess) return e;
         for (int k = 0; k < K2; ++k) {
             if ((e = Lp(kMultiBpassStep, &RaggedGroup::lds_b, 0)) != hipSuccess) return e;
@@ -577,6 +577,7 @@ edaa_status run_ragged(edaa_ctx* ctx, int n, const edaa_image_desc* images, cons
             for (int b = 0; b < g.L; ++b) maps[gi * kMapKinds + kMapRows].push_back(make_int2(k, b));
             maps[gi * kMapKinds + kMapOne].push_back(make_int2(k, 0));
             for (int b = 0; b < kElemBlocks; ++b) maps[gi * kMapKinds + kMapElem].push_back(make_int2(k, b));
+            for (int b = 0; b < aa_blocks(g.p); ++b) maps[gi * kMapKinds + kMapAA].push_back(make_int2(k, b));
         }
     std::vector<size_t> o_maps(maps.size());
     for (size_t i = 0; i < maps.size(); ++i) o_maps[i] = a.take<int2>(maps[i].size());

@@ -259,6 +259,99 @@ __device__ __forceinline__ void a_steps(float (&a)[PP], const float (&P)[PP], co
     }
 }
 
+// Sum, maximum and broadcast over the S consecutive lanes (S = 2 or 4) that
+// share one pixel, with quad DPP permutes.  The XOR butterflies leave every
+// lane of the group with the same value (each stage adds the same two
+// operands in either lane).
+template <int S>
+__device__ __forceinline__ float group_sum(float v) {
+    v += dpp<0xB1>(v);                              // lane ^ 1
+    if (S == 4) v += dpp<0x4E>(v);                  // lane ^ 2
+    return v;
+}
+template <int S>
+__device__ __forceinline__ float group_max(float v) {
+    v = fmaxf(v, dpp<0xB1>(v));
+    if (S == 4) v = fmaxf(v, dpp<0x4E>(v));
+    return v;
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffff), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+template <int S>
+__device__ __forceinline__ double group_sum(double v) {
+    v += dpp_d<0xB1>(v);
+    if (S == 4) v += dpp_d<0x4E>(v);
+    return v;
+}
+// Value of sub-lane K of this lane's group of S.
+template <int S, int K>
+__device__ __forceinline__ float group_bcast(float v) {
+    constexpr int c = (S == 4) ? (K | K << 2 | K << 4 | K << 6) : (K | K << 2 | (2 + K) << 4 | (2 + K) << 6);
+    return dpp<c>(v);
+}
+
+// a[j] = ao[j / S] of sub-lane j % S, for the sub-lanes K, K + 1, ... < S.
+template <int PP, int S, int K>
+__device__ __forceinline__ void gather_rows(float (&a)[PP], const float (&ao)[(PP + S - 1) / S]) {
+    if constexpr (K < S) {
+#pragma unroll
+        for (int jj = 0; jj < (PP + S - 1) / S; ++jj)
+            if (S * jj + K < PP) a[S * jj + K] = group_bcast<S, K>(ao[jj]);
+        gather_rows<PP, S, K + 1>(a, ao);
+    }
+}
+
+// K1 entropic steps of eq. update_A for one pixel whose p rows are spread
+// over S consecutive lanes (S = 2 or 4): sub-lane `sub` owns rows
+// j = sub + S jj.  Every lane keeps the whole abundance vector `a` (for G a)
+// and, for its own rows, the entries `ao`, their logarithms and the rows of
+// G (`Gr`) and of P = E^T x (`Po`).  The softmax maximum and sum are
+// combined over the S lanes; after each step every entry is broadcast from
+// its owner.
+template <int PP, int S>
+__device__ __forceinline__ void a_steps_split(float (&a)[PP], float (&ao)[(PP + S - 1) / S],
+                                              const float (&Po)[(PP + S - 1) / S],
+                                              const float (&Gr)[(PP + S - 1) / S][PP], float eta1, int K1, int sub) {
+    static_assert(S == 2 || S == 4, "two or four lanes per pixel");
+    constexpr int JW = (PP + S - 1) / S;
+    float la[JW];
+#pragma unroll
+    for (int jj = 0; jj < JW; ++jj) la[jj] = fast_log(ao[jj]);
+    for (int k = 0; k < K1; ++k) {
+        float v[JW];
+        float mx = -INFINITY;
+#pragma unroll
+        for (int jj = 0; jj < JW; ++jj) {
+            float gj = -Po[jj];
+#pragma unroll
+            for (int kk = 0; kk < PP; ++kk) gj = fmaf(Gr[jj][kk], a[kk], gj);
+            v[jj] = fmaf(-eta1, gj, la[jj]);
+            if (sub + S * jj < PP) mx = fmaxf(mx, v[jj]);
+        }
+        mx = group_max<S>(mx);
+        float ssum = 0.f;
+#pragma unroll
+        for (int jj = 0; jj < JW; ++jj) {
+            v[jj] -= mx;
+            ao[jj] = (sub + S * jj < PP) ? fast_exp(v[jj]) : 0.f;
+            ssum += ao[jj];
+        }
+        ssum = group_sum<S>(ssum);
+        const float inv = 1.f / ssum, lsum = fast_log(ssum);
+#pragma unroll
+        for (int jj = 0; jj < JW; ++jj) {
+            ao[jj] *= inv;
+            la[jj] = v[jj] - lsum;
+        }
+        gather_rows<PP, S, 0>(a, ao);
+    }
+}
+
 template <int PP, int R>
 struct Shape {
     static constexpr int QC = PP * R;                   // columns per chunk
@@ -356,13 +449,23 @@ __device__ __forceinline__ void mfma_accumulate(d4 (&acc)[NRBW][NCB], d4 (&gram)
     for (int j = 0; j < NRBW; ++j) {
         const int rb = w + NW * j;
         if (rb < nrb) {
-            f4 t[NCB];
+            f4 t[NCB], t2[NCB];
 #pragma unroll
-            for (int cb = 0; cb < NCB; ++cb) t[cb] = f4{0.f, 0.f, 0.f, 0.f};
+            for (int cb = 0; cb < NCB; ++cb) t[cb] = t2[cb] = f4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
             for (int k = 0; k < 16; ++k) {
 #pragma unroll
-                for (int cb = 0; cb < NCB; ++cb) t[cb] = mfma16(xa[k], bop[k][cb], t[cb]);
+                for (int cb = 0; cb < NCB; ++cb) {
+                    // a single column block alternates two chains (independent MFMAs)
+                    if (NCB == 1 && (k & 1))
+                        t2[cb] = mfma16(xa[k], bop[k][cb], t2[cb]);
+                    else
+                        t[cb] = mfma16(xa[k], bop[k][cb], t[cb]);
+                }
+            }
+            if (NCB == 1) {
+#pragma unroll
+                for (int cb = 0; cb < NCB; ++cb) t[cb] += t2[cb];
             }
             float xn[16];
             if (j + 1 < NRBW) {
@@ -439,13 +542,18 @@ __device__ __forceinline__ void store_acc(const d4 (&acc)[NRBW][NCB], float* Vp,
 // u, u + 4, u + 8, u + 12 (lane group kk gets u + 4 kk): the four rows a
 // wave reads are then 4 rows apart, which with the pitches kXS = 68 and
 // ECS = QCP + 4 puts the 64 lanes on 64 distinct LDS banks.
-template <int NCB, int WTS, bool QMAJOR = false, int CB0 = 0>
+// BS: stride between the 16-band blocks this wave takes, from block kb0
+// (BS = 32: two wave groups take alternate blocks).  DUAL: the blocks
+// alternate between two accumulators, summed at the end, so that consecutive
+// MFMAs do not depend on each other (used with a single column block, where
+// one chain would leave the matrix pipe waiting on each result).
+template <int NCB, int WTS, bool QMAJOR = false, int CB0 = 0, int BS = 16, bool DUAL = false>
 __device__ __forceinline__ float mfma_project(const float* Ec, int ECS, const float* Xs, float* Sc, int LP, int w,
-                                              int lane) {
+                                              int lane, int kb0 = 0) {
     const int m = lane & 15, kk = lane >> 4;
-    f4 s[NCB];
+    f4 s[NCB], s2[NCB];
 #pragma unroll
-    for (int cb = 0; cb < NCB; ++cb) s[cb] = f4{0.f, 0.f, 0.f, 0.f};
+    for (int cb = 0; cb < NCB; ++cb) s[cb] = s2[cb] = f4{0.f, 0.f, 0.f, 0.f};
     float xx = 0.f;
     const float* xb = Xs + 4 * kk * kXS + 16 * w + m;
     const float* eb = Ec + 4 * kk * ECS + 16 * CB0 + m;
@@ -461,31 +569,40 @@ __device__ __forceinline__ float mfma_project(const float* Ec, int ECS, const fl
             for (int cb = 0; cb < NCB; ++cb) e[u][cb] = eb[(k0 + u) * ECS + 16 * cb];
         }
     };
-    auto mma = [&](const float (&b)[4], const float (&e)[4][NCB]) {
+    auto mma = [&](const float (&b)[4], const float (&e)[4][NCB], f4 (&acc)[NCB]) {
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             xx = fmaf(b[u], b[u], xx);
 #pragma unroll
-            for (int cb = 0; cb < NCB; ++cb) s[cb] = mfma16(e[u][cb], b[u], s[cb]);
+            for (int cb = 0; cb < NCB; ++cb) acc[cb] = mfma16(e[u][cb], b[u], acc[cb]);
         }
     };
     // One block per trip, no branch in the body: a branch (or a body that
     // alternates two accumulation orders) made the compiler copy the
     // accumulators out of and back into AGPRs on every trip, which drains
     // the MFMA pipeline.  Only the operands are copied between sets.
-    load(b0, e0, 0);
-    int k0 = 0;
-    for (; k0 + 16 < LP; k0 += 32) {
-        load(b1, e1, k0 + 16);
-        __builtin_amdgcn_sched_barrier(0);
-        mma(b0, e0);
-        __builtin_amdgcn_sched_barrier(0);
-        load(b0, e0, (k0 + 32 < LP) ? k0 + 32 : k0);
-        __builtin_amdgcn_sched_barrier(0);
-        mma(b1, e1);
-        __builtin_amdgcn_sched_barrier(0);
+    if (kb0 < LP) {
+        load(b0, e0, kb0);
+        int k0 = kb0;
+        for (; k0 + BS < LP; k0 += 2 * BS) {
+            load(b1, e1, k0 + BS);
+            __builtin_amdgcn_sched_barrier(0);
+            mma(b0, e0, s);
+            __builtin_amdgcn_sched_barrier(0);
+            load(b0, e0, (k0 + 2 * BS < LP) ? k0 + 2 * BS : k0);
+            __builtin_amdgcn_sched_barrier(0);
+            if constexpr (DUAL)
+                mma(b1, e1, s2);
+            else
+                mma(b1, e1, s);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        if (k0 < LP) mma(b0, e0, s);
     }
-    if (k0 < LP) mma(b0, e0);
+    if constexpr (DUAL) {
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb) s[cb] += s2[cb];
+    }
 #pragma unroll
     for (int cb = 0; cb < NCB; ++cb)
 #pragma unroll
@@ -505,13 +622,14 @@ __device__ __forceinline__ float mfma_project(const float* Ec, int ECS, const fl
 // P is kept as a float pair, hi = fl(P) (used by the A-steps) and
 // lo = fl(P - hi), which carries it to about 48 bits; returns the partial
 // ||x||^2 of this lane's bands.
-template <int NCB, int WTS, int CB0 = 0>
+// DUAL as for mfma_project: alternate blocks accumulate into two chains.
+template <int NCB, int WTS, int CB0 = 0, bool DUAL = false>
 __device__ __forceinline__ double mfma_project_f64(const float* Ec, int ECS, const float* Xs, float* Sc, float* Plo,
                                                    int LP, int w, int lane) {
     const int m = lane & 15, kk = lane >> 4;
-    d4 s[NCB];
+    d4 s[NCB], s2[NCB];
 #pragma unroll
-    for (int cb = 0; cb < NCB; ++cb) s[cb] = d4{0.0, 0.0, 0.0, 0.0};
+    for (int cb = 0; cb < NCB; ++cb) s[cb] = s2[cb] = d4{0.0, 0.0, 0.0, 0.0};
     double xx = 0.0;
     const float* xb = Xs + 4 * kk * kXS + 16 * w + m;
     const float* eb = Ec + 4 * kk * ECS + 16 * CB0 + m;
@@ -525,13 +643,13 @@ __device__ __forceinline__ double mfma_project_f64(const float* Ec, int ECS, con
             for (int cb = 0; cb < NCB; ++cb) e[u][cb] = eb[(k0 + u) * ECS + 16 * cb];
         }
     };
-    auto mma = [&](const float (&b)[4], const float (&e)[4][NCB]) {
+    auto mma = [&](const float (&b)[4], const float (&e)[4][NCB], d4 (&acc)[NCB]) {
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             const double bd = (double)b[u];
             xx = fma(bd, bd, xx);
 #pragma unroll
-            for (int cb = 0; cb < NCB; ++cb) s[cb] = mfma16d((double)e[u][cb], bd, s[cb]);
+            for (int cb = 0; cb < NCB; ++cb) acc[cb] = mfma16d((double)e[u][cb], bd, acc[cb]);
         }
     };
     // One block per trip, no branch in the body: a branch (or a body that
@@ -543,14 +661,21 @@ __device__ __forceinline__ double mfma_project_f64(const float* Ec, int ECS, con
     for (; k0 + 16 < LP; k0 += 32) {
         load(b1, e1, k0 + 16);
         __builtin_amdgcn_sched_barrier(0);
-        mma(b0, e0);
+        mma(b0, e0, s);
         __builtin_amdgcn_sched_barrier(0);
         load(b0, e0, (k0 + 32 < LP) ? k0 + 32 : k0);
         __builtin_amdgcn_sched_barrier(0);
-        mma(b1, e1);
+        if constexpr (DUAL)
+            mma(b1, e1, s2);
+        else
+            mma(b1, e1, s);
         __builtin_amdgcn_sched_barrier(0);
     }
-    if (k0 < LP) mma(b0, e0);
+    if (k0 < LP) mma(b0, e0, s);
+    if constexpr (DUAL) {
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb) s[cb] += s2[cb];
+    }
 #pragma unroll
     for (int cb = 0; cb < NCB; ++cb)
 #pragma unroll
@@ -582,6 +707,18 @@ __device__ __forceinline__ void apass_body(const Geom& g, const State& s, int bi
     constexpr int NW = apass_waves(PP), NT = 64 * NW;
     constexpr int QC = S::QC, QCP = S::QCP, NCB = S::NCB, WTS = S::WTS;
     constexpr int RW = (R + NW - 1) / NW;          // runs per wave in the A-step phase (r = w + NW k < R)
+    // With fewer runs than waves the A-steps of a (run, pixel) are spread
+    // over SPL = min(NW / R, 4) consecutive lanes, so that (up to) four
+    // waves per run take part: thread t < 64 R SPL handles run t / (64 SPL),
+    // pixel (t / SPL) % 64 and the rows j = t % SPL + SPL jj of that pixel
+    // (a_steps_split; quad permutes exchange the values).  This is done for
+    // single runs and for the four-wave kernels; the eight-wave kernels with
+    // 2 or 4 runs per chunk keep one lane per pixel (their float rows of G
+    // would not fit the registers left at two waves per SIMD).
+    constexpr int SPL = (R < NW && (R == 1 || NW == 4)) ? (NW / R < 4 ? NW / R : 4) : 1;
+    constexpr bool SPLIT = SPL > 1;
+    constexpr int JW = (PP + SPL - 1) / SPL;
+    static_assert(!SPLIT || NW % R == 0, "runs per chunk must divide the waves");
     constexpr int NRBW = S::NRBW * 4 / NW;          // accumulation row blocks per wave
     constexpr int NGBW = (S::NGB + NW - 1) / NW;    // Gram blocks per wave
     // projection: waves w and w + 4 share the pixel block w & 3 (eight
@@ -638,6 +775,21 @@ __device__ __forceinline__ void apass_body(const Geom& g, const State& s, int bi
     double lacc[RW];
 #pragma unroll
     for (int r = 0; r < RW; ++r) lacc[r] = 0.0;
+    // split A-steps: this thread's run, pixel and sub-lane, and its rows of
+    // the run's Gram matrix in float (the steps; the objective reads the
+    // float64 rows from LDS)
+    const int sr = SPLIT ? tid / (64 * SPL) : 0, si = SPLIT ? (tid / SPL) % 64 : lane, ss = SPLIT ? tid % SPL : 0;
+    const bool sact = !SPLIT || sr < R;            // uniform per wave
+    float Gfr[JW][PP];
+    if constexpr (SPLIT) {
+#pragma unroll
+        for (int jj = 0; jj < JW; ++jj)
+#pragma unroll
+            for (int kk = 0; kk < PP; ++kk) {
+                const int j = ss + SPL * jj;
+                Gfr[jj][kk] = (sact && j < PP) ? (float)Gd[min(sr, R - 1) * PP * PP + j * PP + kk] : 0.f;
+            }
+    }
 
     // Pipeline: the X tile and this thread's abundances (registers) of tile
     // t + npg are requested while tile t is processed.
@@ -647,13 +799,23 @@ __device__ __forceinline__ void apass_body(const Geom& g, const State& s, int bi
     XRegs<kRX, NW> xr;
 
     float an[RW][PP];
+    float ano[JW];      // split: this thread's own rows
     auto load_a = [&](int tile) {
-        const size_t pixc = (size_t)min(tile * kTile + lane, N - 1);
+        if constexpr (SPLIT) {
+            const size_t pixc = (size_t)min(tile * kTile + si, N - 1);
+            const int m = min(c * R + min(sr, R - 1), g.M - 1);
 #pragma unroll
-        for (int k = 0; k < RW; ++k) {
-            const int m = c * R + min(w + NW * k, R - 1);
+            for (int j = 0; j < PP; ++j) an[0][j] = A[(size_t)(m * PP + j) * N + pixc];
 #pragma unroll
-            for (int j = 0; j < PP; ++j) an[k][j] = A[(size_t)(min(m, g.M - 1) * PP + j) * N + pixc];
+            for (int jj = 0; jj < JW; ++jj) ano[jj] = A[(size_t)(m * PP + min(ss + SPL * jj, PP - 1)) * N + pixc];
+        } else {
+            const size_t pixc = (size_t)min(tile * kTile + lane, N - 1);
+#pragma unroll
+            for (int k = 0; k < RW; ++k) {
+                const int m = c * R + min(w + NW * k, R - 1);
+#pragma unroll
+                for (int j = 0; j < PP; ++j) an[k][j] = A[(size_t)(min(m, g.M - 1) * PP + j) * N + pixc];
+            }
         }
     };
     __syncthreads();
@@ -676,15 +838,24 @@ __device__ __forceinline__ void apass_body(const Geom& g, const State& s, int bi
         }
         __builtin_amdgcn_s_waitcnt(0);
         lds_barrier();
-        const int pix = tile * kTile + lane;
+        const int pix = tile * kTile + si;
         const bool pok = pix < N;
         float a[RW][PP];
+        float ao[JW];
+        if constexpr (SPLIT) {
+            const bool ok = sact && c * R + sr < g.M && pok;
 #pragma unroll
-        for (int k = 0; k < RW; ++k) {
-            const int m = c * R + w + NW * k;
-            const bool mok = m < g.M && w + NW * k < R;
+            for (int j = 0; j < PP; ++j) a[0][j] = ok ? an[0][j] : 0.f;
 #pragma unroll
-            for (int j = 0; j < PP; ++j) a[k][j] = (mok && pok) ? an[k][j] : 0.f;
+            for (int jj = 0; jj < JW; ++jj) ao[jj] = (ok && ss + SPL * jj < PP) ? ano[jj] : 0.f;
+        } else {
+#pragma unroll
+            for (int k = 0; k < RW; ++k) {
+                const int m = c * R + w + NW * k;
+                const bool mok = m < g.M && w + NW * k < R;
+#pragma unroll
+                for (int j = 0; j < PP; ++j) a[k][j] = (mok && pok) ? an[k][j] : 0.f;
+            }
         }
         const int nt = tile + g.npg;
         if (nt < g.ntiles) {
@@ -696,7 +867,7 @@ __device__ __forceinline__ void apass_body(const Geom& g, const State& s, int bi
             // projection on the matrix cores: P for pixels 16w..16w+15
             // (16 (w - 4).. with eight waves, w >= 4)
             if (w < 4) {
-                double xx = mfma_project_f64<NC0, WTS>(Ec, ECS, Xs, Wt, Plo, LP, w, lane);
+                double xx = mfma_project_f64<NC0, WTS, 0, NCB == 1>(Ec, ECS, Xs, Wt, Plo, LP, w, lane);
                 xx += __shfl_xor(xx, 16);       // the 4 band classes of the pixel
                 xx += __shfl_xor(xx, 32);
                 if (lane < 16) XX[16 * w + lane] = xx;
@@ -704,6 +875,39 @@ __device__ __forceinline__ void apass_body(const Geom& g, const State& s, int bi
                 (void)mfma_project_f64<NC1, WTS, NC0>(Ec, ECS, Xs, Wt, Plo, LP, w - 4, lane);
             }
             lds_barrier();
+            if constexpr (SPLIT) {
+                // A-steps of run sr, pixel si, rows ss + SPL jj (see a_steps_split)
+                const int m = c * R + sr;
+                const bool ok = sact && m < g.M && pok;
+                if (sact) {
+                float Po[JW];
+                double q = 0.0;
+#pragma unroll
+                for (int jj = 0; jj < JW; ++jj) {
+                    const int j = ss + SPL * jj;
+                    const int jc = min(j, PP - 1);
+                    Po[jj] = j < PP ? Wt[si * WTS + sr * PP + jc] : 0.f;
+                    // this thread's terms of ||x||^2 - 2 a.P + a.G a, in float64
+                    const double* Gj = Gd + sr * PP * PP + jc * PP;
+                    double ga = 0.0;
+#pragma unroll
+                    for (int kk = 0; kk < PP; ++kk) ga = fma(Gj[kk], (double)a[0][kk], ga);
+                    const double pj = (double)Po[jj] + (double)(j < PP ? Plo[si * WTS + sr * PP + jc] : 0.f);
+                    q = fma((double)ao[jj], ga - 2.0 * pj, q);
+                }
+                q = group_sum<SPL>(q);
+                if (ok && ss == 0) lacc[0] += XX[si] + q;
+                if (m < g.M) a_steps_split<PP, SPL>(a[0], ao, Po, Gfr, s.eta[2 * m], K1, ss);
+#pragma unroll
+                for (int jj = 0; jj < JW; ++jj) {
+                    const int j = ss + SPL * jj;
+                    if (j < PP) {
+                        if (ok) A[(size_t)(m * PP + j) * N + pix] = ao[jj];
+                        Wt[si * WTS + sr * PP + j] = ok ? ao[jj] : 0.f;
+                    }
+                }
+                }
+            } else {
             // A-steps: lane = pixel, runs r = w + NW k of the chunk
             const double xnorm = XX[lane];
 #pragma unroll
@@ -739,6 +943,7 @@ __device__ __forceinline__ void apass_body(const Geom& g, const State& s, int bi
                     if (mok && pok) A[(size_t)(m * PP + j) * N + pix] = a[k][j];
                     Wt[lane * WTS + r * PP + j] = (mok && pok) ? a[k][j] : 0.f;
                 }
+            }
             }
         }
         lds_barrier();
@@ -777,12 +982,24 @@ __device__ __forceinline__ void apass_body(const Geom& g, const State& s, int bi
             }
         }
     }
+    if constexpr (SPLIT) {
+        const double tot = wave_sum(lacc[0]);
+        __syncthreads();
+        if (lane == 0) XX[w] = tot;
+        __syncthreads();
+        if (tid < R) {                              // waves r SPL .. r SPL + SPL - 1 hold run r
+            double t = 0.0;
+            for (int w2 = tid * SPL; w2 < (tid + 1) * SPL; ++w2) t += XX[w2];
+            if (c * R + tid < g.M) s.lpart[(size_t)pg * g.M + c * R + tid] = t;
+        }
+    } else {
 #pragma unroll
-    for (int k = 0; k < RW; ++k) {
-        const int r = w + NW * k, m = c * R + r;
-        if (r >= R) continue;
-        const double tot = wave_sum(lacc[k]);
-        if (lane == 0 && m < g.M) s.lpart[(size_t)pg * g.M + m] = tot;
+        for (int k = 0; k < RW; ++k) {
+            const int r = w + NW * k, m = c * R + r;
+            if (r >= R) continue;
+            const double tot = wave_sum(lacc[k]);
+            if (lane == 0 && m < g.M) s.lpart[(size_t)pg * g.M + m] = tot;
+        }
     }
 }
 
@@ -829,6 +1046,7 @@ __device__ __forceinline__ void bpass_body(const Geom& g, const State& s, int bi
     extern __shared__ float smem[];
     const PassLds lo = pass_lds(PP, R, g.L, g.dbuf, g.ecs, g.gf);
     float* Wq = smem + lo.wt;                      // [QCP][kXS]
+    float* Wq2 = smem + lo.pd;                     // [QCP][kXS] second projection half (one column block)
     float* F = smem + lo.f;
     float* FG = smem + lo.fg;
     float* Ec = smem + lo.ec;
@@ -918,10 +1136,17 @@ __device__ __forceinline__ void bpass_body(const Geom& g, const State& s, int bi
         }
 
         if (STEP) {
-            if (w < 4)
-                (void)mfma_project<NC0, WTS, true>(Ec, ECS, Xs, Wq, LP, w, lane);
-            else if constexpr (NC1 > 0)
-                (void)mfma_project<NC1, WTS, true, NC0>(Ec, ECS, Xs, Wq, LP, w - 4, lane);
+            if constexpr (NCB == 1) {
+                // one column block: waves w and w + 4 take alternate 16-band
+                // blocks of pixel block w & 3, into Wq and Wq2 (summed below)
+                (void)mfma_project<1, WTS, true, 0, 32, true>(Ec, ECS, Xs, (w < 4) ? Wq : Wq2, LP, w & 3, lane,
+                                                              16 * (w >> 2));
+            } else {
+                if (w < 4)
+                    (void)mfma_project<NC0, WTS, true>(Ec, ECS, Xs, Wq, LP, w, lane);
+                else if constexpr (NC1 > 0)
+                    (void)mfma_project<NC1, WTS, true, NC0>(Ec, ECS, Xs, Wq, LP, w - 4, lane);
+            }
             lds_barrier();
         }
 
@@ -933,7 +1158,8 @@ __device__ __forceinline__ void bpass_body(const Geom& g, const State& s, int bi
                 const float sh = ts + lzc;
 #pragma unroll
                 for (int u = 0; u < SV; ++u) {
-                    const f4 gv = *(const f4*)(wrow + 4 * u);
+                    f4 gv = *(const f4*)(wrow + 4 * u);
+                    if constexpr (NCB == 1) gv += *(const f4*)(wrow - Wq + Wq2 + 4 * u);
 #pragma unroll
                     for (int e = 0; e < 4; ++e) v[4 * u + e] = fast_log(bv[u][e]) + sh - eta2 * gv[e];
                 }
@@ -1144,10 +1370,22 @@ __global__ __launch_bounds__(kThreads, 2) void k_close_multi(const ImageJob* __r
 // of the partial index (one slice per thread) whose results are combined in
 // slice order, so the result does not depend on scheduling.
 
-// out[o] = sum over pg of src[pg * stride + o] for o < no (no <= 256).
+// Threads of the row reductions (reduce_a, reduce_b): with 1024 slices of
+// the partial index each slice walks a handful of the npg <= 512 partials.
+constexpr int kRedThreads = 1024;
+
+// Slices of the partial index for `no` outputs of npg partials each: as many
+// as the workgroup holds, but no more than one per four partials (the slice
+// results are combined serially).  Depends on (npg, no) only, so the order
+// of every sum is fixed.
+__device__ __forceinline__ int red_slices(int npg, int no) {
+    return max(1, min(kRedThreads / no, (npg + 3) / 4));
+}
+
+// out[o] = sum over pg of src[pg * stride + o] for o < no (no <= kRedThreads).
 __device__ __forceinline__ void sliced_sum(const float* __restrict__ src, size_t stride, int npg, int no,
                                            double* red, double* out) {
-    const int tid = threadIdx.x, S = kThreads / no;
+    const int tid = threadIdx.x, S = red_slices(npg, no);
     const int o = tid % no, sl = tid / no;
     double acc = 0.0;
     if (sl < S)
@@ -1169,37 +1407,45 @@ __device__ __forceinline__ void sliced_sum(const float* __restrict__ src, size_t
     __syncthreads();
 }
 
-// A A^T of run m (blockIdx.x) and its objective at the incoming state
-// (trace[t]), each summed over the npg workgroup partials in fixed slices.
+// A A^T of run m and its objective at the incoming state (trace[t]), summed
+// over the npg workgroup partials.  Each output is summed by one wave: lane
+// l takes the partials l, l + 64, ... in order and the lanes are combined by
+// a fixed butterfly (lane 0's result), so the sums do not depend on
+// scheduling.  The waves of this workgroup take the outputs o0 + w,
+// o0 + w + ostride, ... (w = wave index).
 template <int PP, int R>
-__device__ __forceinline__ void reduce_aa_body(const Geom& g, const State& s, int bx, int t) {
+__device__ __forceinline__ void reduce_aa_body(const Geom& g, const State& s, int m, int o0, int ostride, int t) {
     constexpr int P2 = PP * PP;
-    __shared__ double red[kThreads];
-    __shared__ double out[P2 > 1 ? P2 : 1];
-    const int m = bx, tid = threadIdx.x;
-    sliced_sum(s.AApart + (size_t)m * P2, (size_t)g.nqc * R * P2, g.npg, P2, red, out);   // [npg][nqc R][p][p]
-    if (tid < P2) s.AAtd[(size_t)m * P2 + tid] = out[tid];
-    double acc = 0.0;
-    for (int pg = tid; pg < g.npg; pg += kThreads) acc += s.lpart[(size_t)pg * g.M + m];
-    red[tid] = acc;
-    __syncthreads();
-    if (tid == 0) {
-        double tot = 0.0;
-        for (int k = 0; k < kThreads; ++k) tot += red[k];
-        s.trace[(size_t)m * (s.T + 1) + t] = 0.5 * tot;
+    const int lane = threadIdx.x & 63, w = uniform_int(threadIdx.x >> 6);
+    for (int o = o0 + w; o <= P2; o += ostride) {
+        double acc = 0.0;
+        if (o < P2) {
+            const float* src = s.AApart + (size_t)m * P2 + o;          // [npg][nqc R][p][p]
+            const size_t st = (size_t)g.nqc * R * P2;
+            for (int pg = lane; pg < g.npg; pg += 64) acc += (double)src[(size_t)pg * st];
+        } else {
+            for (int pg = lane; pg < g.npg; pg += 64) acc += s.lpart[(size_t)pg * g.M + m];
+        }
+        acc = wave_sum(acc);
+        if (lane == 0) {
+            if (o < P2)
+                s.AAtd[(size_t)m * P2 + o] = acc;
+            else
+                s.trace[(size_t)m * (s.T + 1) + t] = 0.5 * acc;
+        }
     }
 }
 
 template <int PP, int R>
 __global__ __launch_bounds__(kThreads) void k_reduce_aa(Geom g, State s, int t) {
-    reduce_aa_body<PP, R>(g, s, blockIdx.x, t);
+    reduce_aa_body<PP, R>(g, s, blockIdx.x, 4 * blockIdx.y, 4 * gridDim.y, t);
 }
 
 // Row l of chunk c: X A^T[l][:] and W[l][:] = E[l][:] A A^T - X A^T[l][:].
 template <int PP, int R>
 __device__ __forceinline__ void reduce_a_body(const Geom& g, const State& s, int bx, int by, int t) {
     constexpr int QC = PP * R;
-    __shared__ double red[kThreads];
+    __shared__ double red[kRedThreads];
     __shared__ double xa[QC];
     const int l = bx, c = by, tid = threadIdx.x;
     const int col0 = c * QC, L = g.L;
@@ -1223,20 +1469,21 @@ __device__ __forceinline__ void reduce_a_body(const Geom& g, const State& s, int
 }
 
 template <int PP, int R>
-__global__ __launch_bounds__(kThreads) void k_reduce_a(Geom g, State s, int t) {
+__global__ __launch_bounds__(kRedThreads) void k_reduce_a(Geom g, State s, int t) {
     reduce_a_body<PP, R>(g, s, blockIdx.x, blockIdx.y, t);
 }
 // Single-run images (R = 1, one chunk): the objective and A A^T of the run
-// (one block per image), then, in a second launch since W needs A A^T, the
-// rows of X A^T and W (L blocks per image).
+// (aa_blocks(p) workgroups per image), then, in a second launch since W needs
+// A A^T, the rows of X A^T and W (L workgroups per image).
 template <int PP>
 __global__ __launch_bounds__(kThreads) void k_reduce_aa_multi(const ImageJob* __restrict__ jobs,
                                                               const int2* __restrict__ map, int t) {
-    const ImageJob& J = jobs[map[blockIdx.x].x];
-    reduce_aa_body<PP, 1>(J.g, J.s, 0, t);
+    const int2 jl = map[blockIdx.x];
+    const ImageJob& J = jobs[jl.x];
+    reduce_aa_body<PP, 1>(J.g, J.s, 0, 4 * jl.y, 4 * aa_blocks(PP), t);
 }
 template <int PP>
-__global__ __launch_bounds__(kThreads) void k_reduce_a_multi(const ImageJob* __restrict__ jobs,
+__global__ __launch_bounds__(kRedThreads) void k_reduce_a_multi(const ImageJob* __restrict__ jobs,
                                                              const int2* __restrict__ map, int t) {
     const int2 jl = map[blockIdx.x];
     const ImageJob& J = jobs[jl.x];
@@ -1249,12 +1496,12 @@ __global__ __launch_bounds__(kThreads) void k_reduce_a_multi(const ImageJob* __r
 template <int PP, int R>
 __device__ __forceinline__ void reduce_b_body(const Geom& g, const State& s, int bx, int by, int need_w) {
     constexpr int QC = PP * R;
-    __shared__ double red[kThreads];
+    __shared__ double red[kRedThreads];
     __shared__ float Ms[QC];
     __shared__ double Ss[QC], Ev[QC];
     const int l = bx, c = by, tid = threadIdx.x;
     const int col0 = c * QC, L = g.L;
-    const int S = kThreads / QC, o = tid % QC, sl = tid / QC;
+    const int S = red_slices(g.npg, QC), o = tid % QC, sl = tid / QC;
     const bool act = sl < S;
     // column maxima over the workgroup partials; the partials of a slice are
     // walked four at a time, loads first, the arithmetic in the same order
@@ -1340,11 +1587,11 @@ __device__ __forceinline__ void reduce_b_body(const Geom& g, const State& s, int
 }
 
 template <int PP, int R>
-__global__ __launch_bounds__(kThreads) void k_reduce_b(Geom g, State s, int need_w) {
+__global__ __launch_bounds__(kRedThreads) void k_reduce_b(Geom g, State s, int need_w) {
     reduce_b_body<PP, R>(g, s, blockIdx.x, blockIdx.y, need_w);
 }
 template <int PP>
-__global__ __launch_bounds__(kThreads) void k_reduce_b_multi(const ImageJob* __restrict__ jobs,
+__global__ __launch_bounds__(kRedThreads) void k_reduce_b_multi(const ImageJob* __restrict__ jobs,
                                                              const int2* __restrict__ map, int need_w) {
     const int2 jl = map[blockIdx.x];
     const ImageJob& J = jobs[jl.x];

@@ -43,17 +43,17 @@ struct Kernels {
         return hipGetLastError();
     }
     static hipError_t reduce_b(const Geom& g, const State& s, int need_w, hipStream_t st) {
-        hipLaunchKernelGGL((k_reduce_b<PP, R>), dim3(g.L, g.nqc), dim3(kThreads), 0, st, g, s, need_w);
+        hipLaunchKernelGGL((k_reduce_b<PP, R>), dim3(g.L, g.nqc), dim3(kRedThreads), 0, st, g, s, need_w);
         return hipGetLastError();
     }
     static hipError_t reduce_aa(const Geom& g, const State& s, int t, hipStream_t st) {
-        hipLaunchKernelGGL((k_reduce_aa<PP, R>), dim3(g.M), dim3(kThreads), 0, st, g, s, t);
+        hipLaunchKernelGGL((k_reduce_aa<PP, R>), dim3(g.M, aa_blocks(PP)), dim3(kThreads), 0, st, g, s, t);
         return hipGetLastError();
     }
     static hipError_t reduce_a(const Geom& g, const State& s, int t, hipStream_t st) {
         hipError_t e = reduce_aa(g, s, t, st);
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL((k_reduce_a<PP, R>), dim3(g.L, g.nqc), dim3(kThreads), 0, st, g, s, t);
+        hipLaunchKernelGGL((k_reduce_a<PP, R>), dim3(g.L, g.nqc), dim3(kRedThreads), 0, st, g, s, t);
         return hipGetLastError();
     }
 };
@@ -107,7 +107,7 @@ hipError_t op_finalize(const Geom& g, const State& s, float* B_out, float* E_out
 }
 
 hipError_t op_multi(int kernel, const ImageJob* jobs, const int2* map, int nb, size_t lds, int arg, hipStream_t st) {
-    const dim3 grid(nb), block(kThreads), bblock(64 * kBpassWaves), ablock(64 * apass_waves(PP));
+    const dim3 grid(nb), block(kThreads), rblock(kRedThreads), bblock(64 * kBpassWaves), ablock(64 * apass_waves(PP));
     switch (kernel) {
         case kMultiPrep:
             hipLaunchKernelGGL((k_prep_multi<PP>), grid, block, 0, st, jobs, map);
@@ -121,7 +121,7 @@ hipError_t op_multi(int kernel, const ImageJob* jobs, const int2* map, int nb, s
             hipLaunchKernelGGL((k_bpass_multi<PP, 1, true>), grid, bblock, lds, st, jobs, map, (int)kModeStep);
             break;
         case kMultiRedB:
-            hipLaunchKernelGGL((k_reduce_b_multi<PP>), grid, block, 0, st, jobs, map, arg);
+            hipLaunchKernelGGL((k_reduce_b_multi<PP>), grid, rblock, 0, st, jobs, map, arg);
             break;
         case kMultiEta:
             hipLaunchKernelGGL((k_eta_multi<PP>), grid, block, 0, st, jobs, map);
@@ -134,7 +134,7 @@ hipError_t op_multi(int kernel, const ImageJob* jobs, const int2* map, int nb, s
             hipLaunchKernelGGL((k_reduce_aa_multi<PP>), grid, block, 0, st, jobs, map, arg);
             break;
         case kMultiRedA:
-            hipLaunchKernelGGL((k_reduce_a_multi<PP>), grid, block, 0, st, jobs, map, arg);
+            hipLaunchKernelGGL((k_reduce_a_multi<PP>), grid, rblock, 0, st, jobs, map, arg);
             break;
         case kMultiClose:
             set_max_lds((const void*)k_close_multi<PP, 1>, (int)lds);

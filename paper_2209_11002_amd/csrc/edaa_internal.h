@@ -55,6 +55,11 @@ __host__ __device__ constexpr bool has_runs(int p, int R) {
     return false;
 }
 
+// Workgroups (of four waves) of the A A^T reduction per run: output o of a
+// run (o < p^2: an entry of A A^T; o = p^2: the objective) goes to wave o % 4
+// of workgroup o / 4.
+__host__ __device__ constexpr int aa_blocks(int p) { return (p * p + 1 + 3) / 4; }
+
 // Geometry of one batched problem: M runs of p endmembers on an L x N image,
 // the runs grouped in chunks of R (one workgroup column per chunk).
 struct Geom {
@@ -124,8 +129,8 @@ struct ImageJob {
 };
 
 // Multi-image launch maps; per image: kMapPass: npg workgroups; kMapRows:
-// L (one per band); kMapOne: 1; kMapElem: kElemBlocks.
-enum MultiMap { kMapPass = 0, kMapRows = 1, kMapOne = 2, kMapElem = 3, kMapKinds = 4 };
+// L (one per band); kMapOne: 1; kMapElem: kElemBlocks; kMapAA: aa_blocks(p).
+enum MultiMap { kMapPass = 0, kMapRows = 1, kMapOne = 2, kMapElem = 3, kMapAA = 4, kMapKinds = 5 };
 constexpr int kElemBlocks = 32;
 enum MultiKernel {
     kMultiPrep = 0,        // zero E, W, X A^T, E (f64); A = 1/p            (kMapElem)
@@ -134,7 +139,7 @@ enum MultiKernel {
     kMultiRedB,            // column statistics, E, W (arg: need_w)       (kMapRows)
     kMultiEta,             // step sizes                                  (kMapOne)
     kMultiApass,           // A-pass (arg: K1)                            (kMapPass)
-    kMultiRedAA,           // A A^T and the objective (arg: t)            (kMapOne)
+    kMultiRedAA,           // A A^T and the objective (arg: t)            (kMapAA)
     kMultiRedA,            // X A^T and W (arg: t)                        (kMapRows)
     kMultiClose,           // closing pass                                (kMapPass)
     kMultiCloseReduce,     // final objective and l1 fit                  (kMapOne)

@@ -132,8 +132,11 @@ def test_every_chunk_size_matches_oracle(api, p, R):
 
 @gpu
 def test_ensemble_equals_single_runs(api):
-    """Batched runs follow the same arithmetic as single runs (up to the
-    order of the cross-workgroup sums)."""
+    """Batched runs follow the same arithmetic as single runs, up to the
+    order of the sums (the stacked-run kernels and the single-run kernels
+    split their contractions differently): the float32 gate of 1e-4 on every
+    run, 1e-6 on the calm runs (gamma <= 0.5), where rounding is not
+    amplified."""
     _say("ensemble vs single runs M=5 p=4")
     s = synth.small_case(seed=31, L=50, N=700, p=4)
     Xg, X = _prep(s.X)
@@ -141,8 +144,10 @@ def test_ensemble_equals_single_runs(api):
     r = api.ensemble(Xg, 4, seeds, gammas, T=12)
     for m in range(5):
         one = api.fit(Xg, 4, T=12, gamma=gammas[m], seed=seeds[m])
-        assert np.max(np.abs(r["loss"][m] - one["loss"]) / one["loss"]) < 1e-5
-        assert torch.max(torch.abs(r["A"][m] - one["A"])).item() < 1e-4
+        rel = np.max(np.abs(r["loss"][m] - one["loss"]) / one["loss"])
+        _say(f"gamma {gammas[m]}: batched vs single {rel:.2e}")
+        assert rel < (1e-6 if gammas[m] <= 0.5 else 1e-4)
+        assert torch.max(torch.abs(r["A"][m] - one["A"])).item() < 1e-3
 
 
 @gpu
