@@ -52,9 +52,12 @@ enum { EDAA_COHERENCE_COSINE = 0, EDAA_COHERENCE_RAW = 1 }; /* reading of eq. co
 enum {
     EDAA_FLAG_GRAPH = 1,     /* record the whole run sequence in a HIP graph once
                                 per (shape, buffers) and replay it afterwards */
-    EDAA_FLAG_TIME_PASSES = 2 /* record HIP events around every A-pass, B-pass
+    EDAA_FLAG_TIME_PASSES = 2, /* record HIP events around every A-pass, B-pass
                                 and closing-pass launch (eager launches only;
                                 see edaa_pass_times) */
+    EDAA_FLAG_RAGGED_GROUPED = 4 /* edaa_fit_ragged: run every image with one
+                                launch per kernel and group of equal p instead
+                                of the persistent kernel */
 };
 
 /* Parameters of Algorithm 1 / Algorithm 2.  edaa_default_params fills the
@@ -77,6 +80,8 @@ typedef struct {
                                 compiled sizes, EDAA_EUNSUPPORTED otherwise)    */
     int pixel_groups;        /* launch shape: workgroups per chunk of runs
                                 (0: tuned or default; capped at ceil(N / 64))    */
+    int tiles_per_item;      /* edaa_fit_ragged: 64-pixel tiles per work item of
+                                the persistent kernel (0: tuned or default 8)   */
 } edaa_params;
 
 /* One image of a ragged batch (edaa_fit_ragged).  All pointers are device
@@ -90,6 +95,8 @@ typedef struct {
     float* B;                /* out [N][p]                                        */
     float* E;                /* out [L][p], may be NULL                           */
     double* loss_trace;      /* out, host, T+1 values, may be NULL               */
+    int pixel_groups;        /* in: work items (pixel groups) per pass, 0 for
+                                the default; out: the number used             */
 } edaa_image_desc;
 
 /* Launch shape of a batched problem (edaa_plan). */
@@ -213,10 +220,20 @@ edaa_status edaa_ensemble(edaa_ctx* ctx, const void* X, int L, int N, int p,
                           int* run_status, int* selected);
 
 /* Independent EDAA runs (Algorithm 1) on n_images images of different
- * (L, N, p), all advanced together: each pass is one launch over the
- * concatenated pixel tiles of every image.  params->T, K1, K2, init_scale and
- * x_dtype apply to every image; gamma and seed come from each descriptor. */
-edaa_status edaa_fit_ragged(edaa_ctx* ctx, int n_images, const edaa_image_desc* images,
+ * (L, N, p), all advanced together.  Images with p <= 9 run in one persistent
+ * launch: the passes of every image are cut into work items (a pixel group
+ * of params->tiles_per_item 64-pixel tiles, a block of band rows of a
+ * reduction, ...) that the resident workgroups take in a fixed order, each
+ * item starting once its image has finished the items it depends on, so
+ * images advance through their outer iterations independently.  Images with
+ * p > 9 (and every image under EDAA_FLAG_RAGGED_GROUPED) run with one launch
+ * per kernel and group of equal p.  Each image's results equal those of
+ * edaa_fit with params->pixel_groups set to that image's pixel_groups.
+ * params->T, K1, K2, init_scale and x_dtype apply to every image; gamma and
+ * seed come from each descriptor, which also receives pixel_groups.
+ * Synchronises the stream.  EDAA_EDEVICE if a wait of the persistent kernel
+ * exceeds its bound (a fault of the schedule; the kernel still ends). */
+edaa_status edaa_fit_ragged(edaa_ctx* ctx, int n_images, edaa_image_desc* images,
                             const edaa_params* params);
 
 /* Abundance estimation with the endmembers given: minimise

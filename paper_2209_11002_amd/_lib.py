@@ -17,6 +17,7 @@ EDAA_X_F32, EDAA_X_BF16 = 0, 1
 EDAA_COHERENCE_COSINE, EDAA_COHERENCE_RAW = 0, 1
 EDAA_FLAG_GRAPH = 1
 EDAA_FLAG_TIME_PASSES = 2
+EDAA_FLAG_RAGGED_GROUPED = 4
 
 
 class EdaaParams(ctypes.Structure):
@@ -24,14 +25,14 @@ class EdaaParams(ctypes.Structure):
                 ("gamma", c_double), ("eta1", c_double), ("eta2", c_double),
                 ("init_scale", c_double), ("select_threshold", c_double),
                 ("x_dtype", c_int), ("coherence_mode", c_int), ("flags", c_int),
-                ("runs_per_chunk", c_int), ("pixel_groups", c_int)]
+                ("runs_per_chunk", c_int), ("pixel_groups", c_int), ("tiles_per_item", c_int)]
 
 
 class EdaaImageDesc(ctypes.Structure):
     _fields_ = [("X", c_void_p), ("L", c_int), ("N", c_int), ("p", c_int),
                 ("seed", c_uint64), ("gamma", c_double),
                 ("A", c_void_p), ("B", c_void_p), ("E", c_void_p),
-                ("loss_trace", POINTER(c_double))]
+                ("loss_trace", POINTER(c_double)), ("pixel_groups", c_int)]
 
 
 class EdaaLaunchPlan(ctypes.Structure):

@@ -243,14 +243,22 @@ def ensemble(X, p, seeds, gammas, T=100, K1=5, K2=5, coherence="cosine", thresho
                 selected=sel.value, launches=lib.edaa_last_launch_count(_ctx(dev)))
 
 
-def fit_ragged(images, ps, seeds, gammas, T=100, K1=5, K2=5, init_scale=0.1, graph=False):
+def fit_ragged(images, ps, seeds, gammas, T=100, K1=5, K2=5, init_scale=0.1, graph=False, grouped=False,
+               tiles_per_item=0, pixel_groups=None):
     """Independent runs of Algorithm 1 on images of different (L, N, p), all
-    advanced together (one launch per kernel and group of equal p).
-    images: list of l2-normalised [L_k, N_k] GPU tensors (one dtype).
-    Returns a list of dicts with A, B, E (tensors) and loss (numpy)."""
+    advanced together: images with p <= 9 in one persistent launch (work
+    items of `tiles_per_item` 64-pixel tiles, 0 for the tuned or default
+    size), the others (every image with grouped=True) one launch per kernel
+    and group of equal p.  images: list of l2-normalised [L_k, N_k] GPU
+    tensors (one dtype); pixel_groups: optional per-image item counts.
+    Returns a list of dicts with A, B, E (tensors), loss (numpy) and the
+    pixel_groups used (a single fit with that many pixel groups gives the
+    same results)."""
     n = len(images)
     if n < 1 or len(ps) != n or len(seeds) != n or len(gammas) != n:
         raise ValueError("images, ps, seeds and gammas must be non-empty and of equal length")
+    if pixel_groups is not None and len(pixel_groups) != n:
+        raise ValueError("pixel_groups must have one entry per image")
     dt, dev0 = images[0].dtype, images[0].device
     for k, X in enumerate(images):
         if not isinstance(X, torch.Tensor):
@@ -272,12 +280,17 @@ def fit_ragged(images, ps, seeds, gammas, T=100, K1=5, K2=5, init_scale=0.1, gra
         d.seed, d.gamma = int(seeds[k]), float(gammas[k])
         d.A, d.B, d.E = o["A"].data_ptr(), o["B"].data_ptr(), o["E"].data_ptr()
         d.loss_trace = tr
+        d.pixel_groups = int(pixel_groups[k]) if pixel_groups is not None else 0
         outs.append(o)
         traces.append(tr)
     P = _params(T, K1, K2, 1.0, None, init_scale, 1.05, _x_dtype(images[0]), "cosine", graph)
+    P.tiles_per_item = int(tiles_per_item)
+    if grouped:
+        P.flags |= L_.EDAA_FLAG_RAGGED_GROUPED
     check(L_.load().edaa_fit_ragged(_ctx(images[0].device), n, descs, byref(P)))
-    for o, tr in zip(outs, traces):
+    for k, (o, tr) in enumerate(zip(outs, traces)):
         o["loss"] = np.array(tr[:])
+        o["pixel_groups"] = descs[k].pixel_groups
     return outs
 
 

@@ -14,7 +14,8 @@ LIB = os.path.join(HERE, "libedaa.so")
 # (source, extra defines, object name); edaa_inst.hip is compiled once per p
 MAX_P = 16
 UNITS = ([("edaa_inst.hip", [f"-DEDAA_INST_P={p}"], f"edaa_inst_p{p}.o") for p in range(MAX_P, 0, -1)]
-         + [("edaa_kernels.hip", [], "edaa_kernels.o"), ("edaa_grad.hip", [], "edaa_grad.o"),
+         + [("edaa_persist.hip", [], "edaa_persist.o"), ("edaa_kernels.hip", [], "edaa_kernels.o"),
+            ("edaa_grad.hip", [], "edaa_grad.o"),
             ("edaa_api.hip", [], "edaa_api.o")])
 ARCH = os.environ.get("EDAA_OFFLOAD_ARCH", "gfx950")
 

@@ -173,7 +173,8 @@ edaa_status check_params(const edaa_params* P) {
                  "eta1/eta2 must be finite and >= 0 (0 selects the paper's rule)");
     EDAA_REQUIRE(isfinite(P->select_threshold) && P->select_threshold >= 1.0, "select_threshold must be >= 1");
     EDAA_REQUIRE(P->x_dtype == EDAA_X_F32 || P->x_dtype == EDAA_X_BF16, "x_dtype must be EDAA_X_F32 or EDAA_X_BF16");
-    EDAA_REQUIRE(P->runs_per_chunk >= 0 && P->pixel_groups >= 0, "runs_per_chunk and pixel_groups must be >= 0");
+    EDAA_REQUIRE(P->runs_per_chunk >= 0 && P->pixel_groups >= 0 && P->tiles_per_item >= 0,
+                 "runs_per_chunk, pixel_groups and tiles_per_item must be >= 0");
     EDAA_REQUIRE(P->coherence_mode == EDAA_COHERENCE_COSINE || P->coherence_mode == EDAA_COHERENCE_RAW,
                  "coherence_mode must be EDAA_COHERENCE_COSINE or EDAA_COHERENCE_RAW");
     return EDAA_OK;
@@ -499,13 +500,22 @@ struct PadJob {
 };
 
 hipError_t enqueue_ragged(const std::vector<RaggedGroup>& groups, const std::vector<PadJob>& pads,
-                          const ImageJob* jobs, int T, int K1, int K2, int cosine, hipStream_t st,
-                          long long* launches) {
+                          const ImageJob* jobs, const PersistPlan* plan, size_t plan_lds, int plan_wgs, int T, int K1,
+                          int K2, int cosine, hipStream_t st, long long* launches) {
     long long n = 0;
     hipError_t e;
     for (const PadJob& pj : pads) {
         if ((e = launch_pad_x(pj.X, pj.Xp, pj.L, pj.N, pj.ldx, pj.bf16, st)) != hipSuccess) return e;
         ++n;
+    }
+    if (plan) {
+        // every image of p <= kPersistMaxP: one persistent launch (after the start-state kernel)
+        if ((e = launch_ragged_persistent(*plan, plan_lds, plan_wgs, st)) != hipSuccess) return e;
+        n += 2;
+    }
+    if (groups.empty()) {
+        *launches = n;
+        return hipSuccess;
     }
     auto L_ = [&](int kernel, int mapk, size_t lds, int arg) -> hipError_t {
         for (const RaggedGroup& G : groups) {
@@ -544,13 +554,98 @@ hipError_t enqueue_ragged(const std::vector<RaggedGroup>& groups, const std::vec
     return hipSuccess;
 }
 
-edaa_status run_ragged(edaa_ctx* ctx, int n, const edaa_image_desc* images, const edaa_params* P) {
-    const int T = P->T;
+// Host tables of a persistent launch over the images `idx` (see PersistPlan).
+struct PersistTables {
+    int sub_stride = 0;
+    int nsub[3] = {0, 0, 0};
+    long long seg_len[3] = {0, 0, 0};
+    std::vector<int> kind, arg;           // [3][sub_stride]
+    std::vector<long long> base;          // [3][sub_stride]
+    std::vector<int> cnt;                 // [kPkKinds][n]
+    std::vector<long long> pre;           // [kPkKinds][n + 1]
+    std::vector<long long> need0, iter;   // [3][n], [n]
+};
+
+PersistTables persist_tables(const std::vector<Geom>& geoms, const std::vector<int>& idx, int T, int K2) {
+    PersistTables pt;
+    const int n = (int)idx.size();
+    pt.sub_stride = std::max(3, 3 + 2 * K2);
+    pt.kind.assign(3 * pt.sub_stride, 0);
+    pt.arg.assign(3 * pt.sub_stride, 0);
+    pt.base.assign(3 * pt.sub_stride, 0);
+    auto add = [&](int g, int kind, int arg) {
+        pt.kind[g * pt.sub_stride + pt.nsub[g]] = kind;
+        pt.arg[g * pt.sub_stride + pt.nsub[g]] = arg;
+        ++pt.nsub[g];
+    };
+    add(0, kPkBpassInit, 0);
+    add(0, kPkRowsB, 0);
+    add(0, kPkEta, 0);
+    add(1, kPkApass, 0);
+    add(1, kPkAA, 0);
+    add(1, kPkRowsA, 0);
+    for (int k = 0; k < K2; ++k) {
+        add(1, kPkBpassStep, 0);
+        add(1, kPkRowsB, k + 1 < K2 ? 1 : 0);
+    }
+    add(2, kPkClose, 0);
+    add(2, kPkCloseRed, 0);
+    add(2, kPkFinal, 0);
+    pt.cnt.assign((size_t)kPkKinds * n, 0);
+    pt.pre.assign((size_t)kPkKinds * (n + 1), 0);
+    for (int k = 0; k < n; ++k) {
+        const Geom& g = geoms[idx[k]];
+        const int rows = (g.L + kPersistRows - 1) / kPersistRows;
+        const int c[kPkKinds] = {g.npg, g.npg, g.npg, rows, (g.p * g.p + 1 + 7) / 8, rows, 1, g.npg, 1,
+                                 kPersistFinal};
+        for (int kd = 0; kd < kPkKinds; ++kd) pt.cnt[(size_t)kd * n + k] = c[kd];
+    }
+    for (int kd = 0; kd < kPkKinds; ++kd)
+        for (int k = 0; k < n; ++k)
+            pt.pre[(size_t)kd * (n + 1) + k + 1] = pt.pre[(size_t)kd * (n + 1) + k] + pt.cnt[(size_t)kd * n + k];
+    for (int g = 0; g < 3; ++g) {
+        long long b = 0;
+        for (int j = 0; j < pt.nsub[g]; ++j) {
+            pt.base[g * pt.sub_stride + j] = b;
+            b += pt.pre[(size_t)pt.kind[g * pt.sub_stride + j] * (n + 1) + n];
+        }
+        pt.seg_len[g] = b;
+    }
+    pt.need0.assign(3 * (size_t)n, 0);
+    pt.iter.assign(n, 0);
+    for (int k = 0; k < n; ++k) {
+        long long pro = 0, it = 0;
+        for (int j = 0; j < pt.nsub[0]; ++j) pro += pt.cnt[(size_t)pt.kind[j] * n + k];
+        for (int j = 0; j < pt.nsub[1]; ++j) it += pt.cnt[(size_t)pt.kind[pt.sub_stride + j] * n + k];
+        pt.need0[k] = 0;
+        pt.need0[n + k] = pro;
+        pt.need0[2 * n + k] = pro + (long long)T * it;
+        pt.iter[k] = it;
+    }
+    return pt;
+}
+
+int tiles_per_item_default(int n, const edaa_image_desc* images) {
+    (void)n;
+    (void)images;
+    return kDefaultTilesPerItem;
+}
+
+edaa_status run_ragged(edaa_ctx* ctx, int n, edaa_image_desc* images, const edaa_params* P) {
+    const int T = P->T, K1 = P->K1, K2 = P->K2;
     const int x_bytes = P->x_dtype == EDAA_X_BF16 ? 2 : 4;
-    // groups of equal p, in order of first appearance
+    const bool grouped_only = (P->flags & EDAA_FLAG_RAGGED_GROUPED) != 0;
+    const int tpi = P->tiles_per_item > 0 ? P->tiles_per_item : tiles_per_item_default(n, images);
+    // images for the persistent kernel, and groups of equal p (order of first
+    // appearance) for the launch-per-kernel path
+    std::vector<int> pidx;
     std::vector<int> ps;
     std::vector<std::vector<int>> members;
     for (int k = 0; k < n; ++k) {
+        if (!grouped_only && images[k].p <= kPersistMaxP) {
+            pidx.push_back(k);
+            continue;
+        }
         size_t gi = 0;
         while (gi < ps.size() && ps[gi] != images[k].p) ++gi;
         if (gi == ps.size()) {
@@ -559,16 +654,24 @@ edaa_status run_ragged(edaa_ctx* ctx, int n, const edaa_image_desc* images, cons
         }
         members[gi].push_back(k);
     }
-    // workspace: per-image state, then the job table and the maps
+    // geometry: a persistent image has one item per pixel group of about
+    // `tpi` tiles; an image's own pixel_groups > 0 pins its item count
     std::vector<Geom> geoms(n);
+    std::vector<char> is_p(n, 0);
+    for (int k : pidx) is_p[k] = 1;
+    for (int k = 0; k < n; ++k) {
+        const edaa_image_desc& d = images[k];
+        const int ntiles = (d.N + kTile - 1) / kTile;
+        const int req = d.pixel_groups > 0 ? d.pixel_groups : (is_p[k] ? (ntiles + tpi - 1) / tpi : 0);
+        geoms[k] = make_geom(d.L, d.N, 1, d.p, 1, req);
+        images[k].pixel_groups = geoms[k].npg;
+    }
+    // workspace: per-image state, the job tables, the maps, the persistent tables
     std::vector<size_t> off(n);
     Arena a;
-    for (int k = 0; k < n; ++k) {
-        geoms[k] = make_geom(images[k].L, images[k].N, 1, images[k].p);
-        const size_t bytes = layout(geoms[k], T, x_bytes, nullptr, nullptr);
-        off[k] = a.take<char>(bytes);
-    }
+    for (int k = 0; k < n; ++k) off[k] = a.take<char>(layout(geoms[k], T, x_bytes, nullptr, nullptr));
     const size_t o_jobs = a.take<ImageJob>(n);
+    const size_t o_pjobs = a.take<ImageJob>(std::max<size_t>(pidx.size(), 1));
     std::vector<std::vector<int2>> maps(ps.size() * kMapKinds);
     for (size_t gi = 0; gi < ps.size(); ++gi)
         for (int k : members[gi]) {
@@ -581,6 +684,19 @@ edaa_status run_ragged(edaa_ctx* ctx, int n, const edaa_image_desc* images, cons
         }
     std::vector<size_t> o_maps(maps.size());
     for (size_t i = 0; i < maps.size(); ++i) o_maps[i] = a.take<int2>(maps[i].size());
+    PersistTables pt;
+    size_t o_kind = 0, o_arg = 0, o_base = 0, o_cnt = 0, o_pre = 0, o_need = 0, o_iter = 0, o_ctr = 0;
+    if (!pidx.empty()) {
+        pt = persist_tables(geoms, pidx, T, K2);
+        o_kind = a.take<int>(pt.kind.size());
+        o_arg = a.take<int>(pt.arg.size());
+        o_base = a.take<long long>(pt.base.size());
+        o_cnt = a.take<int>(pt.cnt.size());
+        o_pre = a.take<long long>(pt.pre.size());
+        o_need = a.take<long long>(pt.need0.size());
+        o_iter = a.take<long long>(pt.iter.size());
+        o_ctr = a.take<unsigned long long>(pidx.size() + 2);
+    }
     edaa_status st = ensure_ws(ctx, a.off + 256);
     if (st != EDAA_OK) return st;
     char* base = (char*)ctx->ws;
@@ -613,6 +729,8 @@ edaa_status run_ragged(edaa_ctx* ctx, int n, const edaa_image_desc* images, cons
         seeds[k] = d.seed;
         gammas[k] = d.gamma;
     }
+    std::vector<ImageJob> pjobs;
+    for (int k : pidx) pjobs.push_back(jobs[k]);
     // host -> device copies happen outside any graph
     for (int k = 0; k < n; ++k) {
         EDAA_HIP(ctx, hipMemcpyAsync(rbs[k].seeds, &seeds[k], sizeof(uint64_t), hipMemcpyHostToDevice, ctx->stream));
@@ -639,36 +757,91 @@ edaa_status run_ragged(edaa_ctx* ctx, int n, const edaa_image_desc* images, cons
             G.lds_c = std::max(G.lds_c, launch_lds_bytes(g, 2));
         }
     }
+    PersistPlan plan;
+    memset(&plan, 0, sizeof(plan));
+    size_t plan_lds = 0;
+    int plan_wgs = 0;
+    const int cosine = P->coherence_mode == EDAA_COHERENCE_COSINE ? 1 : 0;
+    if (!pidx.empty()) {
+        auto up = [&](size_t o, const void* src, size_t bytes) -> hipError_t {
+            return hipMemcpyAsync(base + o, src, bytes, hipMemcpyHostToDevice, ctx->stream);
+        };
+        EDAA_HIP(ctx, up(o_pjobs, pjobs.data(), sizeof(ImageJob) * pjobs.size()));
+        EDAA_HIP(ctx, up(o_kind, pt.kind.data(), sizeof(int) * pt.kind.size()));
+        EDAA_HIP(ctx, up(o_arg, pt.arg.data(), sizeof(int) * pt.arg.size()));
+        EDAA_HIP(ctx, up(o_base, pt.base.data(), sizeof(long long) * pt.base.size()));
+        EDAA_HIP(ctx, up(o_cnt, pt.cnt.data(), sizeof(int) * pt.cnt.size()));
+        EDAA_HIP(ctx, up(o_pre, pt.pre.data(), sizeof(long long) * pt.pre.size()));
+        EDAA_HIP(ctx, up(o_need, pt.need0.data(), sizeof(long long) * pt.need0.size()));
+        EDAA_HIP(ctx, up(o_iter, pt.iter.data(), sizeof(long long) * pt.iter.size()));
+        plan.jobs = (const ImageJob*)(base + o_pjobs);
+        plan.n_images = (int)pidx.size();
+        plan.T = T;
+        plan.K1 = K1;
+        plan.cosine = cosine;
+        for (int g = 0; g < 3; ++g) {
+            plan.seg_len[g] = pt.seg_len[g];
+            plan.nsub[g] = pt.nsub[g];
+        }
+        plan.sub_stride = pt.sub_stride;
+        plan.seg_kind = (const int*)(base + o_kind);
+        plan.seg_arg = (const int*)(base + o_arg);
+        plan.seg_base = (const long long*)(base + o_base);
+        plan.cnt = (const int*)(base + o_cnt);
+        plan.pre = (const long long*)(base + o_pre);
+        plan.need0 = (const long long*)(base + o_need);
+        plan.iter = (const long long*)(base + o_iter);
+        unsigned long long* ctr = (unsigned long long*)(base + o_ctr);
+        plan.ticket = ctr;
+        plan.status = (int*)(ctr + 1);
+        plan.done = ctr + 2;
+        plan_lds = (size_t)4 * 512 * sizeof(double);
+        for (int k : pidx) {
+            const Geom& g = geoms[k];
+            plan_lds = std::max({plan_lds, launch_lds_bytes(g, 0), launch_lds_bytes(g, 1), launch_lds_bytes(g, 2)});
+        }
+        int cus = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device) != hipSuccess || cus <= 0)
+            cus = 256;
+        plan_wgs = cus;
+    }
     // the copies read host vectors of this frame: finish them before any
     // return path releases those vectors
     EDAA_HIP(ctx, hipStreamSynchronize(ctx->stream));
 
     std::string key = "ragged";
     {
-        char buf[160];
-        snprintf(buf, sizeof(buf), "|%d,%d,%d,%d,%d,%a,%p", T, P->K1, P->K2, P->coherence_mode, P->x_dtype,
-                 P->init_scale, ctx->ws);
+        char buf[192];
+        snprintf(buf, sizeof(buf), "|%d,%d,%d,%d,%d,%a,%p,%d", T, K1, K2, P->coherence_mode, P->x_dtype,
+                 P->init_scale, ctx->ws, P->flags & EDAA_FLAG_RAGGED_GROUPED);
         key += buf;
         for (int k = 0; k < n; ++k) {
             const edaa_image_desc& d = images[k];
-            snprintf(buf, sizeof(buf), "|%d,%d,%d,%p,%p,%p,%p", d.L, d.N, d.p, d.X, (void*)d.A, (void*)d.B,
-                     (void*)d.E);
+            snprintf(buf, sizeof(buf), "|%d,%d,%d,%d,%p,%p,%p,%p", d.L, d.N, d.p, geoms[k].npg, d.X, (void*)d.A,
+                     (void*)d.B, (void*)d.E);
             key += buf;
         }
     }
-    const int K1 = P->K1, K2 = P->K2, cosine = P->coherence_mode == EDAA_COHERENCE_COSINE ? 1 : 0;
+    const PersistPlan* planp = pidx.empty() ? nullptr : &plan;
     st = run_captured(ctx, key, (P->flags & EDAA_FLAG_GRAPH) != 0, [&](hipStream_t s, long long* nl) {
-        return enqueue_ragged(groups, pads, jobs_dev, T, K1, K2, cosine, s, nl);
+        return enqueue_ragged(groups, pads, jobs_dev, planp, plan_lds, plan_wgs, T, K1, K2, cosine, s, nl);
     });
     if (st != EDAA_OK) return st;
-    bool any = false;
     for (int k = 0; k < n; ++k)
-        if (images[k].loss_trace) {
+        if (images[k].loss_trace)
             EDAA_HIP(ctx, hipMemcpyAsync(images[k].loss_trace, rbs[k].s.trace, sizeof(double) * (T + 1),
                                          hipMemcpyDeviceToHost, ctx->stream));
-            any = true;
+    if (planp) {
+        int status = 0;
+        EDAA_HIP(ctx, hipMemcpyAsync(&status, plan.status, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+        EDAA_HIP(ctx, hipStreamSynchronize(ctx->stream));
+        if (status != 0) {
+            ctx->poisoned = true;
+            return fail(EDAA_EDEVICE, "persistent ragged kernel: a wait for earlier items exceeded its bound");
         }
-    if (any) EDAA_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    } else {
+        EDAA_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    }
     return EDAA_OK;
 }
 
@@ -692,6 +865,7 @@ void edaa_default_params(edaa_params* P) {
     P->flags = 0;
     P->runs_per_chunk = 0;
     P->pixel_groups = 0;
+    P->tiles_per_item = 0;
 }
 
 const char* edaa_last_error(void) { return g_last_error.c_str(); }
@@ -959,7 +1133,7 @@ edaa_status edaa_ensemble(edaa_ctx* ctx, const void* X, int L, int N, int p, con
     return EDAA_OK;
 }
 
-edaa_status edaa_fit_ragged(edaa_ctx* ctx, int n_images, const edaa_image_desc* images, const edaa_params* params) {
+edaa_status edaa_fit_ragged(edaa_ctx* ctx, int n_images, edaa_image_desc* images, const edaa_params* params) {
     edaa_status st = check_ctx(ctx);
     if (st != EDAA_OK) return st;
     if ((st = check_params(params)) != EDAA_OK) return st;

@@ -1247,13 +1247,16 @@ __global__ __launch_bounds__(64 * kBpassWaves, 1) void k_bpass_multi(const Image
 // Closing pass: objective and l1 fit of every run at the final (A, E), from
 // the per-band residual (the l1 fit needs it band by band).
 // --------------------------------------------------------------------------
-template <int PP, int R>
+// Workgroups of NW waves (R == 1: 8, the band sums of a pixel split over the
+// waves; R > 1: 4, R / 4 runs per wave).
+template <int PP, int R, int NW>
 __device__ __forceinline__ void close_body(const Geom& g, const State& s, int bid, const float* __restrict__ E) {
     constexpr int QC = PP * R;
     constexpr int RW = (R + 3) / 4;                   // runs per wave (R > 1): w RW + r < R
+    static_assert(R == 1 || NW == 4, "stacked runs use four waves");
     extern __shared__ float smem[];
     float* Xs = smem;                                  // [L][kXS]
-    float* Ls = Xs + g.L * kXS;                        // R == 1: [2][4][kTile]
+    float* Ls = Xs + g.L * kXS;                        // R == 1: [2][NW][kTile]
 
     int pg, c;
     wg_coords(g, bid, pg, c);
@@ -1276,7 +1279,7 @@ __device__ __forceinline__ void close_body(const Geom& g, const State& s, int bi
 #pragma unroll
             for (int j = 0; j < PP; ++j) a[j] = pok ? s.A[(size_t)(m * PP + j) * N + pix] : 0.f;
             float ls = 0.f, fs = 0.f;
-            const int Lq = (L + 3) >> 2, l0 = min(L, w * Lq), l1 = min(L, l0 + Lq);
+            const int Lq = (L + NW - 1) / NW, l0 = min(L, w * Lq), l1 = min(L, l0 + Lq);
             for (int l = l0; l < l1; ++l) {
                 const float* El = E + (size_t)l * g.Qp + col0;
                 float r = Xs[l * kXS + lane];
@@ -1286,12 +1289,17 @@ __device__ __forceinline__ void close_body(const Geom& g, const State& s, int bi
                 fs += fabsf(r);
             }
             Ls[w * kTile + lane] = ls;
-            Ls[(4 + w) * kTile + lane] = fs;
+            Ls[(NW + w) * kTile + lane] = fs;
             __syncthreads();
             if (w == 0 && pok) {
-                lacc[0] += (double)(Ls[lane] + Ls[kTile + lane] + Ls[2 * kTile + lane] + Ls[3 * kTile + lane]);
-                facc[0] += (double)(Ls[4 * kTile + lane] + Ls[5 * kTile + lane] + Ls[6 * kTile + lane] +
-                                    Ls[7 * kTile + lane]);
+                float lt = Ls[lane], ft = Ls[NW * kTile + lane];
+#pragma unroll
+                for (int k = 1; k < NW; ++k) {
+                    lt += Ls[k * kTile + lane];
+                    ft += Ls[(NW + k) * kTile + lane];
+                }
+                lacc[0] += (double)lt;
+                facc[0] += (double)ft;
             }
         } else {
             float a[RW][PP], ls[RW], fs[RW];
@@ -1345,16 +1353,16 @@ __device__ __forceinline__ void close_body(const Geom& g, const State& s, int bi
     }
 }
 
+constexpr int close_waves(int R) { return R == 1 ? 8 : 4; }
 template <int PP, int R>
-__global__ __launch_bounds__(kThreads, 2) void k_close(Geom g, State s, const float* __restrict__ E) {
-    close_body<PP, R>(g, s, blockIdx.x, E);
+__global__ __launch_bounds__(64 * close_waves(R)) void k_close(Geom g, State s, const float* __restrict__ E) {
+    close_body<PP, R, close_waves(R)>(g, s, blockIdx.x, E);
 }
-template <int PP, int R>
-__global__ __launch_bounds__(kThreads, 2) void k_close_multi(const ImageJob* __restrict__ jobs,
-                                                             const int2* __restrict__ map) {
+template <int PP>
+__global__ __launch_bounds__(512) void k_close_multi(const ImageJob* __restrict__ jobs, const int2* __restrict__ map) {
     const int2 jl = map[blockIdx.x];
     const ImageJob& J = jobs[jl.x];
-    close_body<PP, R>(J.g, J.s, jl.y, J.s.E);
+    close_body<PP, 1, 8>(J.g, J.s, jl.y, J.s.E);
 }
 
 
@@ -1370,38 +1378,49 @@ __global__ __launch_bounds__(kThreads, 2) void k_close_multi(const ImageJob* __r
 // of the partial index (one slice per thread) whose results are combined in
 // slice order, so the result does not depend on scheduling.
 
-// Threads of the row reductions (reduce_a, reduce_b): with 1024 slices of
-// the partial index each slice walks a handful of the npg <= 512 partials.
-constexpr int kRedThreads = 1024;
+// Threads of the row reductions (reduce_a, reduce_b).  The same code runs
+// as its own kernel (one row per workgroup) and inside the persistent ragged
+// kernel (several rows per workgroup); both have 512 threads.
+constexpr int kRedThreads = 512;
 
 // Slices of the partial index for `no` outputs of npg partials each: as many
 // as the workgroup holds, but no more than one per four partials (the slice
 // results are combined serially).  Depends on (npg, no) only, so the order
-// of every sum is fixed.
+// of every sum is fixed whatever the workgroup computes besides.
 __device__ __forceinline__ int red_slices(int npg, int no) {
     return max(1, min(kRedThreads / no, (npg + 3) / 4));
 }
 
-// out[o] = sum over pg of src[pg * stride + o] for o < no (no <= kRedThreads).
-__device__ __forceinline__ void sliced_sum(const float* __restrict__ src, size_t stride, int npg, int no,
-                                           double* red, double* out) {
+// Rows of the partial arrays reduced together by one workgroup.
+__device__ __forceinline__ int red_rows(int npg, int no) { return max(1, kRedThreads / (red_slices(npg, no) * no)); }
+
+// For the rows r < nr packed in this workgroup: out[r * no + o] = sum over pg
+// of src(r)[pg * stride + o] (src(r) = src + r * rstride), o < no.  Thread t
+// takes row t / (S no), slice (t / no) % S and output t % no; slice sl walks
+// the partials sl, sl + S, ... in order, and the slices are then added in
+// slice order.  red: kRedThreads doubles of scratch.
+__device__ __forceinline__ void sliced_sum(const float* __restrict__ src, size_t rstride, size_t stride, int npg,
+                                           int no, int nr, double* red, double* out) {
     const int tid = threadIdx.x, S = red_slices(npg, no);
-    const int o = tid % no, sl = tid / no;
+    const int r = tid / (S * no), sl = (tid / no) % S, o = tid % no;
     double acc = 0.0;
-    if (sl < S)
+    if (r < nr) {
+        const float* sr = src + (size_t)r * rstride;
         for (int pg0 = sl; pg0 < npg; pg0 += 4 * S) {     // loads first, sums in the plain order
             float v[4];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) v[u] = pg0 + u * S < npg ? src[(size_t)(pg0 + u * S) * stride + o] : 0.f;
+            for (int u = 0; u < 4; ++u) v[u] = pg0 + u * S < npg ? sr[(size_t)(pg0 + u * S) * stride + o] : 0.f;
 #pragma unroll
             for (int u = 0; u < 4; ++u)
                 if (pg0 + u * S < npg) acc += (double)v[u];
         }
+    }
     red[tid] = acc;
     __syncthreads();
-    if (tid < no) {
+    if (tid < nr * no) {
+        const int rr = tid / no, oo = tid % no;
         double t = 0.0;
-        for (int k = 0; k < S; ++k) t += red[k * no + tid];
+        for (int k = 0; k < S; ++k) t += red[(rr * S + k) * no + oo];
         out[tid] = t;
     }
     __syncthreads();
@@ -1441,36 +1460,42 @@ __global__ __launch_bounds__(kThreads) void k_reduce_aa(Geom g, State s, int t) 
     reduce_aa_body<PP, R>(g, s, blockIdx.x, 4 * blockIdx.y, 4 * gridDim.y, t);
 }
 
-// Row l of chunk c: X A^T[l][:] and W[l][:] = E[l][:] A A^T - X A^T[l][:].
+// Rows l0 .. l0 + nl - 1 of chunk c: X A^T[l][:] and W[l][:] = E[l][:] A A^T
+// - X A^T[l][:].  scratch: kRedThreads + red_rows * QC doubles.
 template <int PP, int R>
-__device__ __forceinline__ void reduce_a_body(const Geom& g, const State& s, int bx, int by, int t) {
+__device__ __forceinline__ void reduce_a_rows(const Geom& g, const State& s, int l0, int nl, int c, double* scratch) {
     constexpr int QC = PP * R;
-    __shared__ double red[kRedThreads];
-    __shared__ double xa[QC];
-    const int l = bx, c = by, tid = threadIdx.x;
-    const int col0 = c * QC, L = g.L;
-    (void)t;
-    sliced_sum(s.Vpart + ((size_t)c * L + l) * QC, (size_t)g.nqc * L * QC, g.npg, QC, red, xa);
-    if (tid < QC) {
-        const int q = tid, m = c * R + q / PP, ml = q / PP, j = q % PP;
-        double x = xa[q], wv = 0.0;
-        if (m < g.M) {
-            wv = -x;
-            const double* El = s.Ed + (size_t)l * g.Qp + col0 + ml * PP;
-            const double* aat = s.AAtd + (size_t)m * PP * PP;
+    double* red = scratch;
+    double* xa = scratch + kRedThreads;
+    const int tid = threadIdx.x, col0 = c * QC, L = g.L;
+    const int RP = red_rows(g.npg, QC);
+    for (int lb = l0; lb < l0 + nl; lb += RP) {
+        const int nr = min(RP, l0 + nl - lb);
+        sliced_sum(s.Vpart + ((size_t)c * L + lb) * QC, QC, (size_t)g.nqc * L * QC, g.npg, QC, nr, red, xa);
+        if (tid < nr * QC) {
+            const int l = lb + tid / QC, q = tid % QC, m = c * R + q / PP, ml = q / PP, j = q % PP;
+            double x = xa[tid], wv = 0.0;
+            if (m < g.M) {
+                wv = -x;
+                const double* El = s.Ed + (size_t)l * g.Qp + col0 + ml * PP;
+                const double* aat = s.AAtd + (size_t)m * PP * PP;
 #pragma unroll
-            for (int k = 0; k < PP; ++k) wv = fma(El[k], aat[k * PP + j], wv);
-        } else {
-            x = 0.0;
+                for (int k = 0; k < PP; ++k) wv = fma(El[k], aat[k * PP + j], wv);
+            } else {
+                x = 0.0;
+            }
+            s.XAtd[(size_t)l * g.Qp + col0 + q] = x;
+            s.W[(size_t)l * g.Qp + col0 + q] = (float)wv;
         }
-        s.XAtd[(size_t)l * g.Qp + col0 + q] = x;
-        s.W[(size_t)l * g.Qp + col0 + q] = (float)wv;
+        __syncthreads();
     }
 }
 
 template <int PP, int R>
 __global__ __launch_bounds__(kRedThreads) void k_reduce_a(Geom g, State s, int t) {
-    reduce_a_body<PP, R>(g, s, blockIdx.x, blockIdx.y, t);
+    __shared__ double scratch[kRedThreads + PP * R];
+    (void)t;
+    reduce_a_rows<PP, R>(g, s, blockIdx.x, 1, blockIdx.y, scratch);
 }
 // Single-run images (R = 1, one chunk): the objective and A A^T of the run
 // (aa_blocks(p) workgroups per image), then, in a second launch since W needs
@@ -1485,117 +1510,134 @@ __global__ __launch_bounds__(kThreads) void k_reduce_aa_multi(const ImageJob* __
 template <int PP>
 __global__ __launch_bounds__(kRedThreads) void k_reduce_a_multi(const ImageJob* __restrict__ jobs,
                                                              const int2* __restrict__ map, int t) {
+    __shared__ double scratch[kRedThreads + PP];
     const int2 jl = map[blockIdx.x];
     const ImageJob& J = jobs[jl.x];
-    reduce_a_body<PP, 1>(J.g, J.s, jl.y, 0, t);
+    (void)t;
+    reduce_a_rows<PP, 1>(J.g, J.s, jl.y, 1, 0, scratch);
 }
 
-// Row l of chunk c after a B-pass: column statistics (max, sum relative to
-// the max) of the softmax over all N pixels, E[l][:] = X B_new, and W for the
-// next B-step.
+// Rows l0 .. l0 + nl - 1 of chunk c after a B-pass: column statistics (max,
+// sum relative to the max) of the softmax over all N pixels, E[l][:] = X B_new
+// and W for the next B-step.  Several rows are packed per pass over the
+// partials (the column statistics are recomputed per row, in the same order).
+// scratch: kRedThreads + 3 * kRedThreads doubles.
 template <int PP, int R>
-__device__ __forceinline__ void reduce_b_body(const Geom& g, const State& s, int bx, int by, int need_w) {
+__device__ __forceinline__ void reduce_b_rows(const Geom& g, const State& s, int l0, int nl, int c, int need_w,
+                                              double* scratch) {
     constexpr int QC = PP * R;
-    __shared__ double red[kRedThreads];
-    __shared__ float Ms[QC];
-    __shared__ double Ss[QC], Ev[QC];
-    const int l = bx, c = by, tid = threadIdx.x;
+    double* red = scratch;
+    float* Ms = (float*)(scratch + kRedThreads);          // [rows][QC]
+    double* Ss = scratch + 2 * kRedThreads;               // [rows][QC]
+    double* Ev = scratch + 3 * kRedThreads;               // [rows][QC]
+    const int tid = threadIdx.x;
     const int col0 = c * QC, L = g.L;
-    const int S = red_slices(g.npg, QC), o = tid % QC, sl = tid / QC;
-    const bool act = sl < S;
+    const int S = red_slices(g.npg, QC), RP = red_rows(g.npg, QC);
+    const int r = tid / (S * QC), sl = (tid / QC) % S, o = tid % QC;
     // column maxima over the workgroup partials; the partials of a slice are
     // walked four at a time, loads first, the arithmetic in the same order
     // as a plain walk
     constexpr int U = 4;
-    float mx = -INFINITY;
-    if (act)
-        for (int pg0 = sl; pg0 < g.npg; pg0 += U * S) {
-            float v[U];
+    for (int lb = l0; lb < l0 + nl; lb += RP) {
+        const int nr = min(RP, l0 + nl - lb);
+        const bool act = r < nr;
+        const int l = lb + r;
+        float mx = -INFINITY;
+        if (act)
+            for (int pg0 = sl; pg0 < g.npg; pg0 += U * S) {
+                float v[U];
 #pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const int pg = pg0 + u * S;
-                v[u] = pg < g.npg ? s.mpart[(size_t)pg * g.Qp + col0 + o] : -INFINITY;
+                for (int u = 0; u < U; ++u) {
+                    const int pg = pg0 + u * S;
+                    v[u] = pg < g.npg ? s.mpart[(size_t)pg * g.Qp + col0 + o] : -INFINITY;
+                }
+#pragma unroll
+                for (int u = 0; u < U; ++u) mx = fmaxf(mx, v[u]);
             }
-#pragma unroll
-            for (int u = 0; u < U; ++u) mx = fmaxf(mx, v[u]);
+        red[tid] = (double)mx;
+        __syncthreads();
+        if (tid < nr * QC) {
+            const int rr = tid / QC, oo = tid % QC;
+            float t = -INFINITY;
+            for (int k = 0; k < S; ++k) t = fmaxf(t, (float)red[(rr * S + k) * QC + oo]);
+            Ms[tid] = t;
         }
-    red[tid] = (double)mx;
-    __syncthreads();
-    if (tid < QC) {
-        float t = -INFINITY;
-        for (int k = 0; k < S; ++k) t = fmaxf(t, (float)red[k * QC + tid]);
-        Ms[tid] = t;
-    }
-    __syncthreads();
-    // column sums and the row of X B (relative to the maxima)
-    const float mq = Ms[o];
-    double sa = 0.0, ea = 0.0;
-    if (act && mq != -INFINITY)
-        for (int pg0 = sl; pg0 < g.npg; pg0 += U * S) {
-            float mp[U], sp[U], vp[U];
+        __syncthreads();
+        // column sums and the row of X B (relative to the maxima)
+        const float mq = act ? Ms[r * QC + o] : -INFINITY;
+        double sa = 0.0, ea = 0.0;
+        if (act && mq != -INFINITY)
+            for (int pg0 = sl; pg0 < g.npg; pg0 += U * S) {
+                float mp[U], sp[U], vp[U];
 #pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const int pg = pg0 + u * S;
-                const bool ok = pg < g.npg;
-                mp[u] = ok ? s.mpart[(size_t)pg * g.Qp + col0 + o] : -INFINITY;
-                sp[u] = ok ? s.spart[(size_t)pg * g.Qp + col0 + o] : 0.f;
-                vp[u] = ok ? s.Vpart[(((size_t)pg * g.nqc + c) * L + l) * QC + o] : 0.f;
+                for (int u = 0; u < U; ++u) {
+                    const int pg = pg0 + u * S;
+                    const bool ok = pg < g.npg;
+                    mp[u] = ok ? s.mpart[(size_t)pg * g.Qp + col0 + o] : -INFINITY;
+                    sp[u] = ok ? s.spart[(size_t)pg * g.Qp + col0 + o] : 0.f;
+                    vp[u] = ok ? s.Vpart[(((size_t)pg * g.nqc + c) * L + l) * QC + o] : 0.f;
+                }
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    if (mp[u] == -INFINITY) continue;
+                    const double f = (double)expf(mp[u] - mq);
+                    sa += (double)sp[u] * f;
+                    ea += (double)vp[u] * f;
+                }
             }
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                if (mp[u] == -INFINITY) continue;
-                const double f = (double)expf(mp[u] - mq);
-                sa += (double)sp[u] * f;
-                ea += (double)vp[u] * f;
+        red[tid] = sa;
+        __syncthreads();
+        if (tid < nr * QC) {
+            const int rr = tid / QC, oo = tid % QC;
+            double t = 0.0;
+            for (int k = 0; k < S; ++k) t += red[(rr * S + k) * QC + oo];
+            Ss[tid] = t;
+        }
+        __syncthreads();
+        red[tid] = ea;
+        __syncthreads();
+        if (tid < nr * QC) {
+            const int rr = tid / QC, q = tid % QC, lr = lb + rr;
+            double t = 0.0;
+            for (int k = 0; k < S; ++k) t += red[(rr * S + k) * QC + q];
+            const int m = c * R + q / PP;
+            const double e = (m < g.M) ? t / Ss[tid] : 0.0;
+            Ev[tid] = e;
+            s.E[(size_t)lr * g.Qp + col0 + q] = (float)e;
+            s.Ed[(size_t)lr * g.Qp + col0 + q] = e;
+            if (lr == 0 && m < g.M) {
+                s.colm[col0 + q] = Ms[tid];
+                s.cols[col0 + q] = (float)Ss[tid];
             }
         }
-    red[tid] = sa;
-    __syncthreads();
-    if (tid < QC) {
-        double t = 0.0;
-        for (int k = 0; k < S; ++k) t += red[k * QC + tid];
-        Ss[tid] = t;
-    }
-    __syncthreads();
-    red[tid] = ea;
-    __syncthreads();
-    if (tid < QC) {
-        double t = 0.0;
-        for (int k = 0; k < S; ++k) t += red[k * QC + tid];
-        const int m = c * R + tid / PP;
-        const double e = (m < g.M) ? t / Ss[tid] : 0.0;
-        Ev[tid] = e;
-        s.E[(size_t)l * g.Qp + col0 + tid] = (float)e;
-        s.Ed[(size_t)l * g.Qp + col0 + tid] = e;
-        if (l == 0 && m < g.M) {
-            s.colm[col0 + tid] = Ms[tid];
-            s.cols[col0 + tid] = (float)Ss[tid];
-        }
-    }
-    __syncthreads();
-    if (need_w && tid < QC) {
-        const int q = tid, m = c * R + q / PP, ml = q / PP, j = q % PP;
-        double wv = 0.0;
-        if (m < g.M) {
-            wv = -s.XAtd[(size_t)l * g.Qp + col0 + q];
-            const double* aat = s.AAtd + (size_t)m * PP * PP;
+        __syncthreads();
+        if (need_w && tid < nr * QC) {
+            const int rr = tid / QC, q = tid % QC, lr = lb + rr, m = c * R + q / PP, ml = q / PP, j = q % PP;
+            double wv = 0.0;
+            if (m < g.M) {
+                wv = -s.XAtd[(size_t)lr * g.Qp + col0 + q];
+                const double* aat = s.AAtd + (size_t)m * PP * PP;
 #pragma unroll
-            for (int k = 0; k < PP; ++k) wv = fma(Ev[ml * PP + k], aat[k * PP + j], wv);
+                for (int k = 0; k < PP; ++k) wv = fma(Ev[rr * QC + ml * PP + k], aat[k * PP + j], wv);
+            }
+            s.W[(size_t)lr * g.Qp + col0 + q] = (float)wv;
         }
-        s.W[(size_t)l * g.Qp + col0 + q] = (float)wv;
+        __syncthreads();
     }
 }
 
 template <int PP, int R>
 __global__ __launch_bounds__(kRedThreads) void k_reduce_b(Geom g, State s, int need_w) {
-    reduce_b_body<PP, R>(g, s, blockIdx.x, blockIdx.y, need_w);
+    __shared__ double scratch[4 * kRedThreads];
+    reduce_b_rows<PP, R>(g, s, blockIdx.x, 1, blockIdx.y, need_w, scratch);
 }
 template <int PP>
 __global__ __launch_bounds__(kRedThreads) void k_reduce_b_multi(const ImageJob* __restrict__ jobs,
                                                              const int2* __restrict__ map, int need_w) {
+    __shared__ double scratch[4 * kRedThreads];
     const int2 jl = map[blockIdx.x];
     const ImageJob& J = jobs[jl.x];
-    reduce_b_body<PP, 1>(J.g, J.s, jl.y, 0, need_w);
+    reduce_b_rows<PP, 1>(J.g, J.s, jl.y, 1, 0, need_w, scratch);
 }
 
 __device__ __forceinline__ void reduce_close_body(const Geom& g, const State& s, int first, int stride) {
@@ -1649,11 +1691,10 @@ __device__ double jacobi_max_eig(double* a, int n) {
 }
 
 template <int PP>
-__device__ __forceinline__ void eta_body(const Geom& g, const State& s, int bx, const RunInit& ri) {
-    __shared__ double Gd[PP * PP];
+__device__ __forceinline__ void eta_body(const Geom& g, const State& s, int bx, const RunInit& ri, double* Gd) {
     const int m = bx, tid = threadIdx.x;
     const int c = m / g.R, col0 = c * g.QC + (m % g.R) * PP;
-    for (int e = tid; e < PP * PP; e += kThreads) {
+    for (int e = tid; e < PP * PP; e += blockDim.x) {
         const int j = e / PP, k = e % PP;
         double acc = 0.0;
         for (int l = 0; l < g.L; ++l)
@@ -1674,7 +1715,8 @@ __device__ __forceinline__ void eta_body(const Geom& g, const State& s, int bx, 
 
 template <int PP>
 __global__ __launch_bounds__(kThreads) void k_eta(Geom g, State s, RunInit ri) {
-    eta_body<PP>(g, s, blockIdx.x, ri);
+    __shared__ double Gd[PP * PP];
+    eta_body<PP>(g, s, blockIdx.x, ri, Gd);
 }
 
 // --------------------------------------------------------------------------
@@ -1685,7 +1727,7 @@ __device__ __forceinline__ void final_B_body(const Geom& g, const State& s, int 
     const int m = by;
     const size_t n = (size_t)g.N * PP;
     const int c = m / g.R, base = c * g.QC + (m % g.R) * PP;
-    for (size_t e = (size_t)bx * kThreads + threadIdx.x; e < n; e += (size_t)nbx * kThreads) {
+    for (size_t e = (size_t)bx * blockDim.x + threadIdx.x; e < n; e += (size_t)nbx * blockDim.x) {
         const int pix = (int)(e / PP), j = (int)(e % PP);
         const int qp = base + j, tile = pix / kTile;
         const float b = s.Bst[(size_t)(m * PP + j) * ((size_t)g.ntiles * kTile) + pix];
@@ -1699,16 +1741,16 @@ __global__ __launch_bounds__(kThreads) void k_final_B(Geom g, State s, float* B_
 }
 
 template <int PP>
-__device__ __forceinline__ void final_E_body(const Geom& g, const State& s, int bx, float* E_out, int cosine) {
-    __shared__ double Gd[PP * PP];
+__device__ __forceinline__ void final_E_body(const Geom& g, const State& s, int bx, float* E_out, int cosine,
+                                             double* Gd) {
     const int m = bx, tid = threadIdx.x;
     const int c = m / g.R, base = c * g.QC + (m % g.R) * PP;
     if (E_out)
-        for (int e = tid; e < g.L * PP; e += kThreads) {
+        for (int e = tid; e < g.L * PP; e += blockDim.x) {
             const int l = e / PP, j = e % PP;
             E_out[(size_t)m * g.L * PP + e] = s.E[(size_t)l * g.Qp + base + j];
         }
-    for (int e = tid; e < PP * PP; e += kThreads) {
+    for (int e = tid; e < PP * PP; e += blockDim.x) {
         const int j = e / PP, k = e % PP;
         double acc = 0.0;
         for (int l = 0; l < g.L; ++l)
@@ -1734,18 +1776,17 @@ __device__ __forceinline__ void final_E_body(const Geom& g, const State& s, int 
 
 template <int PP>
 __global__ __launch_bounds__(kThreads) void k_final_E(Geom g, State s, float* E_out, int cosine) {
-    final_E_body<PP>(g, s, blockIdx.x, E_out, cosine);
+    __shared__ double Gd[PP * PP];
+    final_E_body<PP>(g, s, blockIdx.x, E_out, cosine, Gd);
 }
 
 // Multi-image helpers (single-run images of one p).
+
+// Start state of one single-run image: E, W, X A^T and E (float64) zero, A =
+// 1/p.  Workgroup `first` of `nblk` strides over the elements.
 template <int PP>
-__global__ __launch_bounds__(kThreads) void k_prep_multi(const ImageJob* __restrict__ jobs,
-                                                         const int2* __restrict__ map) {
-    const int2 jl = map[blockIdx.x];
-    const ImageJob& J = jobs[jl.x];
-    const Geom& g = J.g;
-    const State& s = J.s;
-    const size_t i0 = (size_t)jl.y * kThreads + threadIdx.x, st = (size_t)kElemBlocks * kThreads;
+__device__ __forceinline__ void prep_body(const Geom& g, const State& s, int first, int nblk) {
+    const size_t i0 = (size_t)first * blockDim.x + threadIdx.x, st = (size_t)nblk * blockDim.x;
     const size_t nf = (size_t)(g.L + kPadRows) * g.Qp, nd = (size_t)g.L * g.Qp;
     for (size_t i = i0; i < nf; i += st) {
         s.E[i] = 0.f;
@@ -1760,9 +1801,18 @@ __global__ __launch_bounds__(kThreads) void k_prep_multi(const ImageJob* __restr
 }
 
 template <int PP>
+__global__ __launch_bounds__(kThreads) void k_prep_multi(const ImageJob* __restrict__ jobs,
+                                                         const int2* __restrict__ map) {
+    const int2 jl = map[blockIdx.x];
+    const ImageJob& J = jobs[jl.x];
+    prep_body<PP>(J.g, J.s, jl.y, kElemBlocks);
+}
+
+template <int PP>
 __global__ __launch_bounds__(kThreads) void k_eta_multi(const ImageJob* __restrict__ jobs, const int2* __restrict__ map) {
+    __shared__ double Gd[PP * PP];
     const ImageJob& J = jobs[map[blockIdx.x].x];
-    eta_body<PP>(J.g, J.s, 0, J.ri);
+    eta_body<PP>(J.g, J.s, 0, J.ri, Gd);
 }
 
 __global__ __launch_bounds__(kThreads) void k_reduce_close_multi(const ImageJob* __restrict__ jobs,
@@ -1774,10 +1824,11 @@ __global__ __launch_bounds__(kThreads) void k_reduce_close_multi(const ImageJob*
 template <int PP>
 __global__ __launch_bounds__(kThreads) void k_final_multi(const ImageJob* __restrict__ jobs,
                                                           const int2* __restrict__ map, int cosine) {
+    __shared__ double Gd[PP * PP];
     const int2 jl = map[blockIdx.x];
     const ImageJob& J = jobs[jl.x];
     final_B_body<PP>(J.g, J.s, jl.y, 0, kElemBlocks, J.B_out);
-    if (jl.y == 0) final_E_body<PP>(J.g, J.s, 0, J.E_out, cosine);
+    if (jl.y == 0) final_E_body<PP>(J.g, J.s, 0, J.E_out, cosine, Gd);
 }
 
 }  // namespace

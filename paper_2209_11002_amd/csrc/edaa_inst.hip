@@ -39,7 +39,8 @@ struct Kernels {
     static hipError_t close(const Geom& g, const State& s, hipStream_t st) {
         const size_t lds = pass_lds_bytes(PP, R, g.L, 2);
         set_max_lds((const void*)k_close<PP, R>, (int)lds);
-        hipLaunchKernelGGL((k_close<PP, R>), dim3(g.npg * g.nqc), dim3(kThreads), lds, st, g, s, (const float*)s.E);
+        hipLaunchKernelGGL((k_close<PP, R>), dim3(g.npg * g.nqc), dim3(64 * close_waves(R)), lds, st, g, s,
+                           (const float*)s.E);
         return hipGetLastError();
     }
     static hipError_t reduce_b(const Geom& g, const State& s, int need_w, hipStream_t st) {
@@ -137,8 +138,8 @@ hipError_t op_multi(int kernel, const ImageJob* jobs, const int2* map, int nb, s
             hipLaunchKernelGGL((k_reduce_a_multi<PP>), grid, rblock, 0, st, jobs, map, arg);
             break;
         case kMultiClose:
-            set_max_lds((const void*)k_close_multi<PP, 1>, (int)lds);
-            hipLaunchKernelGGL((k_close_multi<PP, 1>), grid, block, lds, st, jobs, map);
+            set_max_lds((const void*)k_close_multi<PP>, (int)lds);
+            hipLaunchKernelGGL((k_close_multi<PP>), grid, bblock, lds, st, jobs, map);
             break;
         case kMultiCloseReduce:
             hipLaunchKernelGGL(k_reduce_close_multi, grid, block, 0, st, jobs, map);

@@ -145,6 +145,50 @@ enum MultiKernel {
     kMultiCloseReduce,     // final objective and l1 fit                  (kMapOne)
     kMultiFinal,           // B and E outputs, coherence (arg: cosine)    (kMapElem)
 };
+// Persistent ragged execution (edaa_persist.hip).  Sub-stage kinds of an
+// image's sequence; the items of each kind per image are: the passes npg
+// (one per pixel group), the row reductions ceil(L / kPersistRows), the
+// A A^T reduction ceil((p^2 + 1) / 8), the outputs kPersistFinal, the rest 1.
+enum PersistKind {
+    kPkBpassInit = 0,  // B-pass from the seeded start values
+    kPkBpassStep,      // B-step pass
+    kPkApass,          // A-pass
+    kPkRowsB,          // column statistics, E, W (arg: need_w)
+    kPkAA,             // A A^T and the objective at the incoming state
+    kPkRowsA,          // X A^T and W
+    kPkEta,            // step sizes
+    kPkClose,          // closing pass
+    kPkCloseRed,       // final objective and l1 fit
+    kPkFinal,          // B and E outputs, coherence
+    kPkKinds
+};
+constexpr int kPersistRows = 8;     // band rows per reduction item
+constexpr int kPersistFinal = 8;    // items of the output stage per image
+constexpr int kPersistMaxP = 9;     // the persistent kernel holds p <= 9 (eight-wave A-pass)
+constexpr int kDefaultTilesPerItem = 8;
+
+// The schedule of a persistent launch: three segments (prologue, the outer
+// iteration repeated T times, epilogue) of sub-stages; tickets run through
+// the segments in order, sub-stage by sub-stage, image by image.
+struct PersistPlan {
+    const ImageJob* jobs;       // [n_images] device
+    int n_images, T, K1, cosine;
+    long long seg_len[3];       // tickets of each segment (one iteration for segment 1)
+    int nsub[3];                // sub-stages of each segment
+    int sub_stride;
+    const int* seg_kind;        // [3][sub_stride] PersistKind
+    const int* seg_arg;         // [3][sub_stride]
+    const long long* seg_base;  // [3][sub_stride] first ticket of each sub-stage within its segment
+    const int* cnt;             // [kPkKinds][n_images] items per image
+    const long long* pre;       // [kPkKinds][n_images + 1] prefix sums of cnt over images
+    const long long* need0;     // [3][n_images] items of an image before each segment (iteration 0)
+    const long long* iter;      // [n_images] items of an image per outer iteration
+    unsigned long long* ticket; // device counters, zeroed by the launcher's first kernel
+    unsigned long long* done;   // [n_images]
+    int* status;                // set to 1 if a wait exceeded its bound
+};
+hipError_t launch_ragged_persistent(const PersistPlan& P, size_t lds_bytes, int n_workgroups, hipStream_t st);
+
 // Launchers of the kernels compiled for one p (edaa_inst.hip, built once per
 // p).  The pass launchers take the chunk size from g.R, which must be one of
 // run_choices(p); they return hipErrorInvalidValue otherwise.

@@ -95,7 +95,7 @@ size_t launch_lds_bytes(const Geom& g, int kind) {
 }
 
 size_t pass_lds_bytes(int PP, int R, int L, int kind) {
-    if (kind == 2) return ((size_t)L * kXS + 8 * kTile) * sizeof(float);
+    if (kind == 2) return ((size_t)L * kXS + 16 * kTile) * sizeof(float);
     const int QCP = (PP * R + 15) & ~15;
     return (size_t)pass_lds(PP, R, L, 0, QCP + 1, 0).total * sizeof(float);
 }

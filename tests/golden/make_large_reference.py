@@ -10,9 +10,11 @@ float64 at full size:
 
 The input is the oracle's pixel normalisation of the scene rounded to float32
 (the float32 data the GPU receives).  Calls only oracle/ and the seeded scene
-generator.  Takes about an hour on 8 cores.
+generator.  Takes about an hour on 8 cores.  With --float32 it writes
+large_fp32_ref.npz instead: the objective traces of the same runs with the
+oracle's steps in float32 (the drift of plain float32 arithmetic).
 
-    python tests/golden/make_large_reference.py
+    python tests/golden/make_large_reference.py [--float32]
 """
 import os
 import sys
@@ -70,5 +72,32 @@ def main():
     np.savez_compressed(os.path.join(HERE, "large_fp64_ref.npz"), **out)
 
 
+def main_f32():
+    """large_fp32_ref.npz: the objective traces of the same runs with the
+    oracle's steps in float32 (how far plain float32 arithmetic lands from
+    float64 on this scene): loss10 [20, 11] and, for runs 0 and 4,
+    loss100 [2, 101]."""
+    scene, cfg = synth.large_smooth()
+    Xn, _ = O.normalize_pixels(scene.X)
+    X = Xn.astype(np.float32).astype(np.float64)
+    del scene, Xn
+    seeds, gammas = cfg["seeds"], cfg["gammas"]
+    M = len(seeds)
+    loss10 = np.zeros((M, T_ALL + 1))
+    loss100 = np.zeros((len(LONG_RUNS), T_LONG + 1))
+    for m in range(M):
+        t0 = time.time()
+        T = T_LONG if m in LONG_RUNS else T_ALL
+        r = O.edaa_fit(X, 12, T=T, K1=cfg["K1"], K2=cfg["K2"], gamma=gammas[m], seed=seeds[m], dtype=np.float32)
+        loss10[m] = r["loss"][:T_ALL + 1]
+        if m in LONG_RUNS:
+            loss100[LONG_RUNS.index(m)] = r["loss"]
+        print(f"float32 run {m}: loss[T] {r['loss'][-1]:.10g} ({time.time() - t0:.0f} s)", flush=True)
+    np.savez_compressed(os.path.join(HERE, "large_fp32_ref.npz"), loss10=loss10, loss100=loss100)
+
+
 if __name__ == "__main__":
-    main()
+    if "--float32" in sys.argv:
+        main_f32()
+    else:
+        main()

@@ -42,10 +42,10 @@ def test_library_exports_every_declared_symbol(lib):
 
 
 def test_struct_layouts_match_header():
-    # edaa_params: 3 ints, 5 doubles, 5 ints (with natural alignment)
-    assert ctypes.sizeof(L_.EdaaParams) == 3 * 4 + 4 + 5 * 8 + 5 * 4 + 4
+    # edaa_params: 3 ints, 5 doubles, 6 ints (with natural alignment)
+    assert ctypes.sizeof(L_.EdaaParams) == 3 * 4 + 4 + 5 * 8 + 6 * 4
     assert L_.EdaaParams.gamma.offset == 16
-    assert ctypes.sizeof(L_.EdaaImageDesc) == 8 + 4 * 3 + 4 + 8 + 8 + 8 * 4
+    assert ctypes.sizeof(L_.EdaaImageDesc) == 8 + 4 * 3 + 4 + 8 + 8 + 8 * 4 + 8
 
 
 def test_default_params_are_the_papers(lib):

@@ -103,6 +103,6 @@ def test_ragged_bf16_equals_single_fits(api):
         imgs.append((_prep(s.X, torch.bfloat16)[0], p))
     rr = api.fit_ragged([x for x, _ in imgs], [p for _, p in imgs], [1, 2, 3], [1.0, 0.5, 2.0], T=8)
     for k, ((Xg, p), r) in enumerate(zip(imgs, rr)):
-        one = api.fit(Xg, p, T=8, gamma=[1.0, 0.5, 2.0][k], seed=k + 1)
+        one = api.fit(Xg, p, T=8, gamma=[1.0, 0.5, 2.0][k], seed=k + 1, pixel_groups=r["pixel_groups"])
         assert torch.equal(r["A"], one["A"]) and torch.equal(r["B"], one["B"]), k
         assert np.array_equal(r["loss"], one["loss"]), k

@@ -1,7 +1,9 @@
 """Ragged batch (single runs on images of different L, N, p, advanced
-together): every image must give exactly what a single-image fit gives (the
-multi-image launches run the same kernel bodies on the same geometry), and
-agree with the float64 oracle to the float32 tolerances."""
+together): every image must give exactly what a single-image fit with the
+same number of pixel groups gives (the persistent kernel and the
+launch-per-kernel path run the same kernel bodies on the same geometry, with
+the same order of every sum), and agree with the float64 oracle to the float32
+tolerances."""
 import sys
 
 import numpy as np
@@ -41,19 +43,61 @@ def _images(dtype=torch.float32):
     return out
 
 
+def _check_equal_to_single(api, imgs, rr, T, gammas, seeds):
+    for k, ((Xg, _, p), r) in enumerate(zip(imgs, rr)):
+        single = api.fit(Xg, p, T=T, gamma=gammas[k], seed=seeds[k], pixel_groups=r["pixel_groups"])
+        assert torch.equal(r["A"], single["A"]), k
+        assert torch.equal(r["B"], single["B"]), k
+        assert torch.equal(r["E"], single["E"]), k
+        assert np.array_equal(r["loss"], single["loss"]), k
+
+
 @gpu
 def test_ragged_equals_single_image_fits(api):
+    """Images with p <= 9 run in the persistent kernel, the p = 16 image with
+    one launch per kernel."""
     _say("ragged vs single fits:", SHAPES)
     imgs = _images()
     seeds = [11 * k + 1 for k in range(len(imgs))]
     gammas = [0.5, 1.0, 2.0, 1.0, 0.25, 1.0, 4.0]
     rr = api.fit_ragged([x for x, _, _ in imgs], [p for _, _, p in imgs], seeds, gammas, T=12)
-    for k, ((Xg, _, p), r) in enumerate(zip(imgs, rr)):
-        single = api.fit(Xg, p, T=12, gamma=gammas[k], seed=seeds[k])
-        assert torch.equal(r["A"], single["A"]), k
-        assert torch.equal(r["B"], single["B"]), k
-        assert torch.equal(r["E"], single["E"]), k
-        assert np.array_equal(r["loss"], single["loss"]), k
+    _check_equal_to_single(api, imgs, rr, 12, gammas, seeds)
+
+
+@gpu
+@pytest.mark.parametrize("tiles_per_item", [1, 3, 8])
+def test_ragged_persistent_many_images(api, tiles_per_item):
+    """Sixteen images of p in [1, 9] and up to 12 000 pixels in the persistent
+    kernel (work items of 1, 3 or 8 tiles), against single fits."""
+    rng = np.random.default_rng(77)
+    imgs, shapes = [], []
+    for k in range(16):
+        L, N, p = int(rng.integers(20, 120)), int(rng.integers(60, 12000)), int(rng.integers(1, 10))
+        s = synth.small_case(seed=300 + k, L=L, N=N, p=min(p, 8))
+        Xn, _ = O.normalize_pixels(s.X)
+        Xt = torch.from_numpy(Xn.astype(np.float32))
+        imgs.append((Xt.cuda().contiguous(), None, p))
+        shapes.append((L, N, p))
+    _say(f"ragged persistent, tiles per item {tiles_per_item}: {shapes}")
+    seeds = list(range(16))
+    gammas = [(0.25, 1.0, 4.0)[k % 3] for k in range(16)]
+    rr = api.fit_ragged([x for x, _, _ in imgs], [p for _, _, p in imgs], seeds, gammas, T=6,
+                        tiles_per_item=tiles_per_item)
+    _check_equal_to_single(api, imgs, rr, 6, gammas, seeds)
+
+
+@gpu
+def test_ragged_persistent_equals_grouped(api):
+    """The persistent kernel and the launch-per-kernel path give identical
+    results for the same pixel groups."""
+    _say("ragged persistent vs grouped")
+    imgs = _images()
+    args = ([x for x, _, _ in imgs], [p for _, _, p in imgs], list(range(len(imgs))), [1.0] * len(imgs))
+    rp = api.fit_ragged(*args, T=7)
+    rg = api.fit_ragged(*args, T=7, grouped=True, pixel_groups=[r["pixel_groups"] for r in rp])
+    for k in range(len(imgs)):
+        assert torch.equal(rp[k]["A"], rg[k]["A"]) and torch.equal(rp[k]["B"], rg[k]["B"]), k
+        assert np.array_equal(rp[k]["loss"], rg[k]["loss"]), k
 
 
 @gpu
