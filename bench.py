@@ -186,6 +186,8 @@ def bench_ragged(n_images, T):
     seeds = list(range(n_images))
     gammas = [1.0] * n_images
     api.set_graph_cache(dev, n_images + 8)
+    tpi, tuned_us = api.autotune_ragged(X, ps, seeds, gammas)      # recorded for this batch's class
+    log(f"ragged: tuned {tpi} tiles per work item ({tuned_us:.0f} us per outer iteration)")
 
     def timed(fn):
         fn()                                                          # capture
@@ -215,7 +217,7 @@ def bench_ragged(n_images, T):
     return dict(unit="image-iterations/s", images=n_images, T=T, pixels=pixels,
                 batched=round(n_images * T / tb, 2), grouped=round(n_images * T / tg, 2),
                 per_image=round(n_images * T / ts, 2), speedup=round(ts / tb, 3),
-                final_loss_max_rel_diff_between_paths=float(f"{diff:.3g}"),
+                final_loss_max_rel_diff_between_paths=float(f"{diff:.3g}"), tuned_tiles_per_item=tpi,
                 pixel_groups_first_images=[r["pixel_groups"] for r in rb][:4],
                 algorithmic_bytes_per_outer_iteration=per_outer, batched_gbs=round(gbs, 1),
                 batched_hbm_frac=round(gbs / HBM_GBS, 4))
@@ -371,6 +373,7 @@ def main():
     ap.add_argument("--large-T", "--bf16-T", dest="large_T", type=int, default=100,
                     help="outer iterations of the large-scene ensembles (0: skip the large scene)")
     ap.add_argument("--small-plain", type=int, default=1, help="time the Samson- and Jasper-shaped runs (0: skip)")
+    ap.add_argument("--tune", type=int, default=1, help="autotune the headline launch shape first (0: default shape)")
     ap.add_argument("--profile-run", type=int, default=0, metavar="T",
                     help="run a counter-profiling workload with T outer iterations and exit")
     ap.add_argument("--profile-workload", default="urban_ensemble",
@@ -398,8 +401,12 @@ def main():
     p, T, K1, K2 = 6, cfg["T"], cfg["K1"], cfg["K2"]
     seeds, gammas = cfg["seeds"], cfg["gammas"]
     M = len(seeds)
-    log(f"scene L={L} N={N} p={p} M={M} T={T}, plan {api.plan(L, N, p, M)}")
     Xraw = torch.from_numpy(scene.X).to(dev)
+    if args.tune:
+        best, us = api.autotune(api.normalize_pixels(Xraw), p, M, K1=K1, K2=K2)
+        log(f"tuned launch shape {best}: {us:.0f} us per outer iteration")
+    plan = api.plan(L, N, p, M)
+    log(f"scene L={L} N={N} p={p} M={M} T={T}, plan {plan}")
     out = dict(A=torch.empty((M, p, N), device=dev), B=torch.empty((M, N, p), device=dev),
                E=torch.empty((M, L, p), device=dev))
 
@@ -536,7 +543,7 @@ def main():
         "config": {"workload": f"batched EDAA ensemble, Urban-shaped synthetic scene L={L} N={N} (307x307) "
                                f"p={p}, M={M} runs (seeds x gamma 0.25..4), T={T}, K1={K1}, K2={K2}, "
                                f"Dirichlet(0.7) abundances, noise sigma 0.02",
-                   "L": L, "N": N, "p": p, "M": M, "T": T, "K1": K1, "K2": K2},
+                   "L": L, "N": N, "p": p, "M": M, "T": T, "K1": K1, "K2": K2, "launch_shape": plan},
         "hbm_gbs": round(step_bytes / (ms_per_step / 1e3) / 1e9, 1),
         "value_graph_replay": round(value_graph, 2),
         "roofline": roofline,

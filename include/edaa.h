@@ -129,6 +129,32 @@ const char* edaa_last_error(void);
  * EDAA_EUNSUPPORTED when no compiled pass kernels fit the request. */
 edaa_status edaa_plan(int L, int N, int p, int M, const edaa_params* params, edaa_launch_plan* out);
 
+/* Launch-shape autotuner.  Times candidate shapes of an ensemble of M runs
+ * of p endmembers on X [L][N] (device, params->x_dtype): every compiled
+ * runs-per-chunk size that fits, each with half, the default and twice the
+ * default pixel groups; each candidate runs T = 2 and T = 6 outer iterations
+ * (K1, K2 from params, seeds 0..M-1, gamma params->gamma) twice after a
+ * warm-up, and scores the difference of the best times.  The fastest shape is recorded for the
+ * problem's class (L, p, M, x_dtype and ceil(log2(ceil(N / 64)))): later
+ * edaa_fit / edaa_ensemble / edaa_plan calls of that class without an
+ * explicit runs_per_chunk or pixel_groups use it (plan source
+ * EDAA_PLAN_TUNED).  Records live for the process and, if the environment
+ * variable EDAA_TUNE_CACHE names a file, are appended to it and read back by
+ * later processes.  best (may be NULL) receives the shape, best_us (may be
+ * NULL) its microseconds per outer iteration.  Allocates its trial outputs;
+ * synchronises the stream. */
+edaa_status edaa_autotune(edaa_ctx* ctx, const void* X, int L, int N, int p, int M,
+                          const edaa_params* params, edaa_launch_plan* best, double* best_us);
+
+/* The same for a ragged batch: tiles per work item of the persistent kernel
+ * (1, 2, 4, 8, 16 or 32), timed on the batch itself (the images' outputs are
+ * overwritten), recorded for the batch's class (image count,
+ * ceil(log2(total tiles)), largest p, x_dtype) and used by later
+ * edaa_fit_ragged calls of that class with params->tiles_per_item = 0. */
+edaa_status edaa_autotune_ragged(edaa_ctx* ctx, int n_images, edaa_image_desc* images,
+                                 const edaa_params* params, int* best_tiles_per_item,
+                                 double* best_us);
+
 /* Capacity of the context's cache of captured HIP graphs (EDAA_FLAG_GRAPH),
  * one per (shape, buffers, parameters) key; the least recently captured is
  * dropped when it is full.  Default 16; n >= 1. */

@@ -71,6 +71,10 @@ SIGNATURES = {
     "edaa_select": (c_int, [POINTER(c_double), POINTER(c_double), c_int, c_double]),
     "edaa_plan": (c_int, [c_int, c_int, c_int, c_int, POINTER(EdaaParams), POINTER(EdaaLaunchPlan)]),
     "edaa_set_graph_cache": (c_int, [c_void_p, c_int]),
+    "edaa_autotune": (c_int, [c_void_p, c_void_p, c_int, c_int, c_int, c_int, POINTER(EdaaParams),
+                              POINTER(EdaaLaunchPlan), POINTER(c_double)]),
+    "edaa_autotune_ragged": (c_int, [c_void_p, c_int, POINTER(EdaaImageDesc), POINTER(EdaaParams), POINTER(c_int),
+                                     POINTER(c_double)]),
 }
 
 _lib = None

@@ -243,17 +243,8 @@ def ensemble(X, p, seeds, gammas, T=100, K1=5, K2=5, coherence="cosine", thresho
                 selected=sel.value, launches=lib.edaa_last_launch_count(_ctx(dev)))
 
 
-def fit_ragged(images, ps, seeds, gammas, T=100, K1=5, K2=5, init_scale=0.1, graph=False, grouped=False,
-               tiles_per_item=0, pixel_groups=None):
-    """Independent runs of Algorithm 1 on images of different (L, N, p), all
-    advanced together: images with p <= 9 in one persistent launch (work
-    items of `tiles_per_item` 64-pixel tiles, 0 for the tuned or default
-    size), the others (every image with grouped=True) one launch per kernel
-    and group of equal p.  images: list of l2-normalised [L_k, N_k] GPU
-    tensors (one dtype); pixel_groups: optional per-image item counts.
-    Returns a list of dicts with A, B, E (tensors), loss (numpy) and the
-    pixel_groups used (a single fit with that many pixel groups gives the
-    same results)."""
+def _ragged_descs(images, ps, seeds, gammas, T, pixel_groups=None):
+    """Descriptors, output tensors and host traces of a ragged batch."""
     n = len(images)
     if n < 1 or len(ps) != n or len(seeds) != n or len(gammas) != n:
         raise ValueError("images, ps, seeds and gammas must be non-empty and of equal length")
@@ -283,15 +274,56 @@ def fit_ragged(images, ps, seeds, gammas, T=100, K1=5, K2=5, init_scale=0.1, gra
         d.pixel_groups = int(pixel_groups[k]) if pixel_groups is not None else 0
         outs.append(o)
         traces.append(tr)
+    return descs, outs, traces
+
+
+def fit_ragged(images, ps, seeds, gammas, T=100, K1=5, K2=5, init_scale=0.1, graph=False, grouped=False,
+               tiles_per_item=0, pixel_groups=None):
+    """Independent runs of Algorithm 1 on images of different (L, N, p), all
+    advanced together: images with p <= 9 in one persistent launch (work
+    items of `tiles_per_item` 64-pixel tiles, 0 for the tuned or default
+    size), the others (every image with grouped=True) one launch per kernel
+    and group of equal p.  images: list of l2-normalised [L_k, N_k] GPU
+    tensors (one dtype); pixel_groups: optional per-image item counts.
+    Returns a list of dicts with A, B, E (tensors), loss (numpy) and the
+    pixel_groups used (a single fit with that many pixel groups gives the
+    same results)."""
+    descs, outs, traces = _ragged_descs(images, ps, seeds, gammas, T, pixel_groups)
     P = _params(T, K1, K2, 1.0, None, init_scale, 1.05, _x_dtype(images[0]), "cosine", graph)
     P.tiles_per_item = int(tiles_per_item)
     if grouped:
         P.flags |= L_.EDAA_FLAG_RAGGED_GROUPED
-    check(L_.load().edaa_fit_ragged(_ctx(images[0].device), n, descs, byref(P)))
+    check(L_.load().edaa_fit_ragged(_ctx(images[0].device), len(images), descs, byref(P)))
     for k, (o, tr) in enumerate(zip(outs, traces)):
         o["loss"] = np.array(tr[:])
         o["pixel_groups"] = descs[k].pixel_groups
     return outs
+
+
+def autotune(X, p, M=1, K1=5, K2=5, gamma=1.0):
+    """Time the candidate launch shapes of an M-run problem on X (see
+    edaa_autotune) and record the fastest for its class.  Returns the plan
+    dict (as plan()) and the microseconds per outer iteration."""
+    Lb, N = _check_x(X)
+    P = _params(1, K1, K2, gamma, None, 0.1, 1.05, _x_dtype(X), "cosine", False)
+    best = L_.EdaaLaunchPlan()
+    us = c_double(0.0)
+    check(L_.load().edaa_autotune(_ctx(X.device), _ptr(X), Lb, N, int(p), int(M), byref(P), byref(best), byref(us)))
+    return dict(runs_per_chunk=best.runs_per_chunk, chunks=best.chunks, pixel_groups=best.pixel_groups,
+                double_buffer=best.double_buffer, source="tuned"), us.value
+
+
+def autotune_ragged(images, ps, seeds, gammas, K1=5, K2=5):
+    """Time the persistent kernel's work-item sizes on a ragged batch (see
+    edaa_autotune_ragged) and record the fastest for its class.  Returns
+    (tiles per item, microseconds per outer iteration)."""
+    descs, _, _ = _ragged_descs(images, ps, seeds, gammas, 1)
+    P = _params(1, K1, K2, 1.0, None, 0.1, 1.05, _x_dtype(images[0]), "cosine", False)
+    tpi = c_int(0)
+    us = c_double(0.0)
+    check(L_.load().edaa_autotune_ragged(_ctx(images[0].device), len(images), descs, byref(P), byref(tpi),
+                                         byref(us)))
+    return tpi.value, us.value
 
 
 def plan(L, N, p, M=1, runs_per_chunk=0, pixel_groups=0, x_dtype=torch.float32):

@@ -6,7 +6,10 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <stdlib.h>
+
 #include <algorithm>
+#include <map>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -189,17 +192,113 @@ edaa_status check_shape(int L, int N, int p, int M) {
     return EDAA_OK;
 }
 
-// Launch shape of an M-run problem: the caller's requests, else the default
-// (EDAA_PLAN_* in *source).
+// ---------------------------------------------------------------------------
+// Launch shapes chosen by the autotuner (edaa_autotune, edaa_autotune_ragged),
+// per problem class: for an ensemble (L, p, M, X dtype and the tile count
+// rounded up to a power of two) the runs per chunk and pixel groups, for a
+// ragged batch (image count, total tiles rounded up to a power of two,
+// largest p, X dtype) the tiles per work item.  Kept for the process; when
+// the environment variable EDAA_TUNE_CACHE names a file, entries are read
+// from it on first use and appended to it when tuned, one per line:
+//   edaa-tune-v1 <class> <value1> <value2> <microseconds per outer iteration>
+// (later lines win).
+// ---------------------------------------------------------------------------
+struct TuneTable {
+    std::mutex mu;
+    bool loaded = false;
+    std::map<std::string, std::pair<int, int>> shapes;
+};
+
+TuneTable& tune_table() {
+    static TuneTable t;
+    return t;
+}
+
+int log2_ceil(long long v) {
+    int b = 0;
+    while ((1ll << b) < v) ++b;
+    return b;
+}
+
+std::string ensemble_class(int L, int N, int p, int M, int x_dtype) {
+    char buf[96];
+    snprintf(buf, sizeof(buf), "ens:%d:%d:%d:%d:%d", L, p, M, x_dtype, log2_ceil((N + kTile - 1) / kTile));
+    return buf;
+}
+
+std::string ragged_class(int n, const edaa_image_desc* images, int x_dtype) {
+    long long tiles = 0;
+    int pmax = 0;
+    for (int k = 0; k < n; ++k) {
+        tiles += (images[k].N + kTile - 1) / kTile;
+        pmax = std::max(pmax, images[k].p);
+    }
+    char buf[96];
+    snprintf(buf, sizeof(buf), "rag:%d:%d:%d:%d", n, log2_ceil(tiles), pmax, x_dtype);
+    return buf;
+}
+
+void tune_load_locked(TuneTable& t) {
+    if (t.loaded) return;
+    t.loaded = true;
+    const char* path = getenv("EDAA_TUNE_CACHE");
+    if (!path || !*path) return;
+    FILE* f = fopen(path, "r");
+    if (!f) return;
+    char tag[32], cls[96];
+    int v1, v2;
+    double us;
+    while (fscanf(f, "%31s %95s %d %d %lf", tag, cls, &v1, &v2, &us) == 5)
+        if (strcmp(tag, "edaa-tune-v1") == 0) t.shapes[cls] = std::make_pair(v1, v2);
+    fclose(f);
+}
+
+bool tune_lookup(const std::string& cls, int* v1, int* v2) {
+    TuneTable& t = tune_table();
+    std::lock_guard<std::mutex> lk(t.mu);
+    tune_load_locked(t);
+    auto it = t.shapes.find(cls);
+    if (it == t.shapes.end()) return false;
+    *v1 = it->second.first;
+    *v2 = it->second.second;
+    return true;
+}
+
+void tune_store(const std::string& cls, int v1, int v2, double us) {
+    TuneTable& t = tune_table();
+    std::lock_guard<std::mutex> lk(t.mu);
+    tune_load_locked(t);
+    t.shapes[cls] = std::make_pair(v1, v2);
+    const char* path = getenv("EDAA_TUNE_CACHE");
+    if (!path || !*path) return;
+    FILE* f = fopen(path, "a");
+    if (!f) return;
+    fprintf(f, "edaa-tune-v1 %s %d %d %.3f\n", cls.c_str(), v1, v2, us);
+    fclose(f);
+}
+
+// Launch shape of an M-run problem: the caller's requests, else a tuned
+// shape of its class, else the default (EDAA_PLAN_* in *source).
 edaa_status plan_geom(int L, int N, int p, int M, const edaa_params* P, Geom* g, int* source) {
     if (P->runs_per_chunk > 0 && !runs_fit(p, P->runs_per_chunk, L))
         return fail(EDAA_EUNSUPPORTED, "runs_per_chunk=%d has no pass kernels for p=%d, L=%d", P->runs_per_chunk, p,
                     L);
-    *g = make_geom(L, N, M, p, P->runs_per_chunk, P->pixel_groups);
+    int R = P->runs_per_chunk, npg = P->pixel_groups, src = EDAA_PLAN_REQUESTED;
+    if (R == 0 && npg == 0) {
+        src = EDAA_PLAN_DEFAULT;
+        int tR = 0, tn = 0;
+        if (tune_lookup(ensemble_class(L, N, p, M, P->x_dtype), &tR, &tn) && runs_fit(p, tR, L) &&
+            (M > 1 || tR == 1)) {
+            R = tR;
+            npg = tn;
+            src = EDAA_PLAN_TUNED;
+        }
+    }
+    *g = make_geom(L, N, M, p, R, npg);
     if (!geom_valid(*g))
         return fail(EDAA_EUNSUPPORTED, "no pass kernels fit L=%d with p=%d (runs per chunk %d, LDS limit %zu bytes)",
                     L, p, g->R, kMaxLdsBytes);
-    if (source) *source = (P->runs_per_chunk > 0 || P->pixel_groups > 0) ? EDAA_PLAN_REQUESTED : EDAA_PLAN_DEFAULT;
+    if (source) *source = src;
     return EDAA_OK;
 }
 
@@ -625,9 +724,11 @@ PersistTables persist_tables(const std::vector<Geom>& geoms, const std::vector<i
     return pt;
 }
 
-int tiles_per_item_default(int n, const edaa_image_desc* images) {
-    (void)n;
-    (void)images;
+// Tiles per work item of the persistent kernel: tuned for the batch's class,
+// else kDefaultTilesPerItem.
+int tiles_per_item_default(int n, const edaa_image_desc* images, int x_dtype) {
+    int v1 = 0, v2 = 0;
+    if (tune_lookup(ragged_class(n, images, x_dtype), &v1, &v2) && v1 > 0) return v1;
     return kDefaultTilesPerItem;
 }
 
@@ -635,7 +736,7 @@ edaa_status run_ragged(edaa_ctx* ctx, int n, edaa_image_desc* images, const edaa
     const int T = P->T, K1 = P->K1, K2 = P->K2;
     const int x_bytes = P->x_dtype == EDAA_X_BF16 ? 2 : 4;
     const bool grouped_only = (P->flags & EDAA_FLAG_RAGGED_GROUPED) != 0;
-    const int tpi = P->tiles_per_item > 0 ? P->tiles_per_item : tiles_per_item_default(n, images);
+    const int tpi = P->tiles_per_item > 0 ? P->tiles_per_item : tiles_per_item_default(n, images, P->x_dtype);
     // images for the persistent kernel, and groups of equal p (order of first
     // appearance) for the launch-per-kernel path
     std::vector<int> pidx;
@@ -845,6 +946,32 @@ edaa_status run_ragged(edaa_ctx* ctx, int n, edaa_image_desc* images, const edaa
     return EDAA_OK;
 }
 
+}  // namespace
+
+namespace {
+// Outer iterations of the autotuner's trial runs: the time of one outer
+// iteration is the difference of the two, divided by their difference.
+constexpr int kTuneShortT = 2, kTuneLongT = 6;
+
+// Milliseconds of `call` (enqueued on the context stream), from HIP events.
+template <typename F>
+edaa_status time_call(edaa_ctx* ctx, F&& call, double* ms) {
+    hipEvent_t e0, e1;
+    EDAA_HIP(ctx, hipEventCreate(&e0));
+    EDAA_HIP(ctx, hipEventCreate(&e1));
+    EDAA_HIP(ctx, hipEventRecord(e0, ctx->stream));
+    edaa_status st = call();
+    if (st == EDAA_OK) {
+        EDAA_HIP(ctx, hipEventRecord(e1, ctx->stream));
+        EDAA_HIP(ctx, hipEventSynchronize(e1));
+        float f = 0.f;
+        EDAA_HIP(ctx, hipEventElapsedTime(&f, e0, e1));
+        *ms = f;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return st;
+}
 }  // namespace
 
 extern "C" {
@@ -1143,11 +1270,128 @@ edaa_status edaa_fit_ragged(edaa_ctx* ctx, int n_images, edaa_image_desc* images
         if ((st = check_shape(d.L, d.N, d.p, 1)) != EDAA_OK) return st;
         EDAA_REQUIRE(d.X && d.A && d.B, "image %d: X, A and B must not be null", k);
         EDAA_REQUIRE(params->eta1 > 0.0 || (isfinite(d.gamma) && d.gamma > 0.0), "image %d: gamma must be > 0", k);
+        EDAA_REQUIRE(d.pixel_groups >= 0, "image %d: pixel_groups must be >= 0", k);
         if (!runs_fit(d.p, 1, d.L))
             return fail(EDAA_EUNSUPPORTED, "image %d: no pass kernels fit L=%d with p=%d (LDS limit %zu bytes)", k,
                         d.L, d.p, kMaxLdsBytes);
     }
     return run_ragged(ctx, n_images, images, params);
+}
+
+
+edaa_status edaa_autotune(edaa_ctx* ctx, const void* X, int L, int N, int p, int M, const edaa_params* params,
+                          edaa_launch_plan* best, double* best_us) {
+    edaa_status st = check_ctx(ctx);
+    if (st != EDAA_OK) return st;
+    if ((st = check_params(params)) != EDAA_OK) return st;
+    if ((st = check_shape(L, N, p, M)) != EDAA_OK) return st;
+    EDAA_REQUIRE(X != nullptr, "X must not be null");
+    // candidate shapes: every compiled chunk size that fits (one run per
+    // chunk only for single runs), each with half, the default and twice
+    // the default pixel groups
+    std::vector<std::pair<int, int>> cand;
+    int rc[4] = {0, 0, 0, 0};
+    const int nr = run_choices(p, rc);
+    for (int i = 0; i < nr; ++i) {
+        const int R = rc[i];
+        if (!runs_fit(p, R, L) || (M == 1) != (R == 1)) continue;
+        const int base = make_geom(L, N, M, p, R, 0).npg;
+        for (int f : {1, 2, 4}) {
+            const int npg = std::max(1, std::min(base * f / 2, (N + kTile - 1) / kTile));
+            bool dup = false;
+            for (auto& c : cand) dup |= (c.first == R && c.second == npg);
+            if (!dup) cand.emplace_back(R, npg);
+        }
+    }
+    if (cand.empty()) return fail(EDAA_EUNSUPPORTED, "no pass kernels fit L=%d with p=%d", L, p);
+    // outputs and per-run inputs of the trial runs
+    float* buf = nullptr;
+    const size_t na = (size_t)M * p * N, ne = (size_t)M * L * p;
+    if (hipMalloc(&buf, sizeof(float) * (2 * na + ne)) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(EDAA_ENOMEM, "could not allocate the trial outputs");
+    }
+    std::vector<uint64_t> seeds(M);
+    std::vector<double> gammas(M, isfinite(params->gamma) && params->gamma > 0.0 ? params->gamma : 1.0);
+    for (int m = 0; m < M; ++m) seeds[m] = (uint64_t)m;
+    edaa_params P = *params;
+    P.flags &= ~(EDAA_FLAG_GRAPH | EDAA_FLAG_TIME_PASSES);
+    double bus = -1.0;
+    int bi = 0;
+    for (size_t i = 0; i < cand.size() && st == EDAA_OK; ++i) {
+        P.runs_per_chunk = cand[i].first;
+        P.pixel_groups = cand[i].second;
+        // the time of one outer iteration: ((T = 6) - (T = 2)) / 4, each the
+        // best of two after a warm-up
+        double t[2] = {1e30, 1e30};
+        for (int rep = 0; rep < 5 && st == EDAA_OK; ++rep) {
+            P.T = (rep == 0 || rep % 2 == 1) ? kTuneShortT : kTuneLongT;
+            double ms = 0.0;
+            st = time_call(ctx,
+                           [&]() {
+                               return run_batch(ctx, X, L, N, p, &P, M, seeds.data(), gammas.data(), nullptr,
+                                                nullptr, buf, buf + na, buf + 2 * na, nullptr, nullptr, nullptr,
+                                                nullptr);
+                           },
+                           &ms);
+            if (rep > 0) t[(rep - 1) % 2] = std::min(t[(rep - 1) % 2], ms);
+        }
+        const double us = 1e3 * (t[1] - t[0]) / (kTuneLongT - kTuneShortT);
+        if (st == EDAA_OK && (bus < 0.0 || us < bus)) {
+            bus = us;
+            bi = (int)i;
+        }
+    }
+    (void)hipFree(buf);
+    if (st != EDAA_OK) return st;
+    tune_store(ensemble_class(L, N, p, M, params->x_dtype), cand[bi].first, cand[bi].second, bus);
+    if (best) {
+        const Geom g = make_geom(L, N, M, p, cand[bi].first, cand[bi].second);
+        best->runs_per_chunk = g.R;
+        best->chunks = g.nqc;
+        best->pixel_groups = g.npg;
+        best->double_buffer = g.dbuf;
+        best->source = EDAA_PLAN_TUNED;
+    }
+    if (best_us) *best_us = bus;
+    return EDAA_OK;
+}
+
+edaa_status edaa_autotune_ragged(edaa_ctx* ctx, int n_images, edaa_image_desc* images, const edaa_params* params,
+                                 int* best_tiles_per_item, double* best_us) {
+    edaa_status st = check_ctx(ctx);
+    if (st != EDAA_OK) return st;
+    if ((st = check_params(params)) != EDAA_OK) return st;
+    EDAA_REQUIRE(n_images >= 1 && images, "n_images must be >= 1 and images non-null");
+    std::vector<edaa_image_desc> d(images, images + n_images);
+    for (auto& x : d) {
+        x.loss_trace = nullptr;
+        x.pixel_groups = 0;
+    }
+    edaa_params P = *params;
+    P.flags &= ~(EDAA_FLAG_GRAPH | EDAA_FLAG_TIME_PASSES | EDAA_FLAG_RAGGED_GROUPED);
+    double bus = -1.0;
+    int bt = kDefaultTilesPerItem;
+    for (int tpi : {1, 2, 4, 8, 16, 32}) {
+        P.tiles_per_item = tpi;
+        double t[2] = {1e30, 1e30};
+        for (int rep = 0; rep < 5; ++rep) {
+            P.T = (rep == 0 || rep % 2 == 1) ? kTuneShortT : kTuneLongT;
+            double ms = 0.0;
+            st = time_call(ctx, [&]() { return edaa_fit_ragged(ctx, n_images, d.data(), &P); }, &ms);
+            if (st != EDAA_OK) return st;
+            if (rep > 0) t[(rep - 1) % 2] = std::min(t[(rep - 1) % 2], ms);
+        }
+        const double us = 1e3 * (t[1] - t[0]) / (kTuneLongT - kTuneShortT);
+        if (bus < 0.0 || us < bus) {
+            bus = us;
+            bt = tpi;
+        }
+    }
+    tune_store(ragged_class(n_images, images, params->x_dtype), bt, 0, bus);
+    if (best_tiles_per_item) *best_tiles_per_item = bt;
+    if (best_us) *best_us = bus;
+    return EDAA_OK;
 }
 
 namespace {

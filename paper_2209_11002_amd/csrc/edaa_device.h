@@ -749,13 +749,21 @@ __device__ __forceinline__ void apass_body(const Geom& g, const State& s, int bi
     // consistent with that E).
     stage_chunk<QC, QCP>(E, g.Qp, col0, L, LP, Ec, ECS);
     __syncthreads();
-    for (int e = tid; e < R * PP * PP; e += NT) {
-        const int r = e / (PP * PP), jk = e % (PP * PP), j = jk / PP, k = jk % PP;
+    // each entry by 8 consecutive lanes (bands l = sub, sub + 8, ...),
+    // combined by a fixed butterfly
+    for (int e0 = tid / 8; e0 < R * PP * PP; e0 += NT / 8) {
+        const int sub = tid % 8;
+        const int r = e0 / (PP * PP), jk = e0 % (PP * PP), j = jk / PP, k = jk % PP;
         const float* Ek = Ec + r * PP;
         double acc = 0.0;
-        for (int l = 0; l < L; ++l) acc = fma((double)Ek[l * ECS + j], (double)Ek[l * ECS + k], acc);
-        Gd[e] = acc;
-        if (g.gf) Gf[e] = (float)acc;
+        for (int l = sub; l < L; l += 8) acc = fma((double)Ek[l * ECS + j], (double)Ek[l * ECS + k], acc);
+        acc += __shfl_xor(acc, 1);
+        acc += __shfl_xor(acc, 2);
+        acc += __shfl_xor(acc, 4);
+        if (sub == 0) {
+            Gd[e0] = acc;
+            if (g.gf) Gf[e0] = (float)acc;
+        }
     }
     __syncthreads();
     // zero the X rows beyond L and the weight padding (never written later)

@@ -76,3 +76,29 @@ def test_every_compiled_chunk_size_is_plannable_at_small_L():
     for p in range(1, 17):
         for R in _choices(p):
             assert api.plan(64, 2000, p, 2 * R, runs_per_chunk=R)["runs_per_chunk"] == R
+
+
+def test_tuned_shapes_are_read_from_the_cache_file(tmp_path):
+    """A class recorded in the file that EDAA_TUNE_CACHE names (format of
+    edaa_autotune's records: tag, class, runs per chunk, pixel groups,
+    microseconds; later lines win) sets the launch shape of that class only."""
+    import json
+    import os
+    import subprocess
+    import sys
+    cache = tmp_path / "tune.txt"
+    # Urban-shaped ensemble class: L=162, p=6, M=50, float32 X, ceil(log2(1473 tiles)) = 11
+    cache.write_text("edaa-tune-v1 ens:162:6:50:0:11 8 100 2000.0\n"
+                     "edaa-tune-v1 ens:162:6:50:0:11 4 40 1900.0\n"
+                     "edaa-tune-v1 ens:162:6:50:0:10 8 7 100.0\n")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    code = ("import json; from paper_2209_11002_amd import api; "
+            "print(json.dumps([api.plan(162, 94249, 6, 50), api.plan(162, 94249, 6, 49), api.plan(162, 40000, 6, 50),"
+            " api.plan(162, 94249, 6, 50, runs_per_chunk=8)]))")
+    out = subprocess.run([sys.executable, "-c", code], cwd=root, capture_output=True, text=True, check=True,
+                         env=dict(os.environ, EDAA_TUNE_CACHE=str(cache)))
+    tuned, other_m, other_n, requested = json.loads(out.stdout.strip().splitlines()[-1])
+    assert (tuned["source"], tuned["runs_per_chunk"], tuned["pixel_groups"]) == ("tuned", 4, 40)
+    assert other_m["source"] == "default"                      # another M is another class
+    assert (other_n["source"], other_n["runs_per_chunk"], other_n["pixel_groups"]) == ("tuned", 8, 7)
+    assert requested["source"] == "requested" and requested["runs_per_chunk"] == 8
