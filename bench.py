@@ -54,9 +54,10 @@ def kernel_source_sha256():
     return h.hexdigest()
 
 
-def stored_traffic(path):
-    """HBM bytes per B-pass launch from a committed counter summary, or None
-    when it is missing or was taken from another version of the kernels."""
+def stored_traffic(path, shape=None):
+    """HBM bytes per launch of the profiled kernel from a committed counter
+    summary, or None when it is missing, was taken from another version of
+    the kernels, or (shape given) at another launch shape."""
     try:
         fields = {}
         with open(path) as f:
@@ -66,17 +67,26 @@ def stored_traffic(path):
                     fields[k.strip()] = v.strip()
         if fields.get("kernel_source_sha256") != kernel_source_sha256():
             return None
+        if shape is not None and fields.get("launch_shape") != shape:
+            return None
         return int(float(fields["traffic_bytes_per_launch"]))
     except (OSError, KeyError, ValueError):
         return None
 
 
-def profile_run(T, workload):
+def parse_shape(text):
+    """'R,npg' -> (runs per chunk, pixel groups)."""
+    r, n = (int(v) for v in text.split(","))
+    return r, n
+
+
+def profile_run(T, workload, shape=None):
     """Workload for rocprofv3 passes: a plain device copy of known size (the
     calibration of FETCH_SIZE / WRITE_SIZE) and then T outer iterations of
-    'urban_ensemble' (the headline ensemble), 'urban_single' (one run on the
-    same scene) or 'large_single' (one run on the L=224, N=512x614, p=12
-    scene, float32 X)."""
+    'urban_ensemble' (the headline ensemble, at the launch shape `shape` if
+    given), 'urban_single' (one run on the same scene), 'large_single' (one
+    run on the L=224, N=512x614, p=12 scene, float32 X) or 'ragged' (the
+    64-image ragged batch, persistent kernel)."""
     import torch
     from paper_2209_11002_amd import api, synth
     dev = torch.device("cuda:0")
@@ -87,6 +97,14 @@ def profile_run(T, workload):
     torch.cuda.synchronize()
     del src, dst
     log(f"calibration copy: {nbytes} bytes read, {nbytes} bytes written")
+    if workload == "ragged":
+        scenes, _ = synth.ragged_images(64)
+        X = [api.normalize_pixels(torch.from_numpy(sc.X).to(dev)) for sc in scenes]
+        ps = [sc.M.shape[1] for sc in scenes]
+        api.fit_ragged(X, ps, list(range(64)), [1.0] * 64, T=T)
+        torch.cuda.synchronize()
+        log(f"profile run done ({workload}, T={T})")
+        return
     if workload == "large_single":
         scene, cfg = synth.large_smooth()
         p = 12
@@ -95,7 +113,9 @@ def profile_run(T, workload):
         p = 6
     X = api.normalize_pixels(torch.from_numpy(scene.X).to(dev))
     if workload == "urban_ensemble":
-        api.ensemble(X, p, cfg["seeds"], cfg["gammas"], T=T, K1=cfg["K1"], K2=cfg["K2"])
+        R, npg = shape if shape else (0, 0)
+        api.ensemble(X, p, cfg["seeds"], cfg["gammas"], T=T, K1=cfg["K1"], K2=cfg["K2"], runs_per_chunk=R,
+                     pixel_groups=npg)
     else:
         api.fit(X, p, T=T, K1=cfg["K1"], K2=cfg["K2"], gamma=1.0, seed=0)
     torch.cuda.synchronize()
@@ -374,10 +394,12 @@ def main():
                     help="outer iterations of the large-scene ensembles (0: skip the large scene)")
     ap.add_argument("--small-plain", type=int, default=1, help="time the Samson- and Jasper-shaped runs (0: skip)")
     ap.add_argument("--tune", type=int, default=1, help="autotune the headline launch shape first (0: default shape)")
+    ap.add_argument("--shape", default=None, metavar="R,NPG",
+                    help="pin the headline launch shape (runs per chunk, pixel groups) instead of tuning")
     ap.add_argument("--profile-run", type=int, default=0, metavar="T",
                     help="run a counter-profiling workload with T outer iterations and exit")
     ap.add_argument("--profile-workload", default="urban_ensemble",
-                    choices=("urban_ensemble", "urban_single", "large_single"))
+                    choices=("urban_ensemble", "urban_single", "large_single", "ragged"))
     ap.add_argument("--summarize", nargs="+", metavar="CSV", help="summarise rocprofv3 CSV files and exit")
     args = ap.parse_args()
     if args.summarize:
@@ -388,7 +410,7 @@ def main():
               "(run it with --gpus 1)", file=sys.stderr)
         sys.exit(2)
     if args.profile_run > 0:
-        profile_run(args.profile_run, args.profile_workload)
+        profile_run(args.profile_run, args.profile_workload, parse_shape(args.shape) if args.shape else None)
         return
 
     import numpy as np
@@ -402,10 +424,11 @@ def main():
     seeds, gammas = cfg["seeds"], cfg["gammas"]
     M = len(seeds)
     Xraw = torch.from_numpy(scene.X).to(dev)
-    if args.tune:
+    shape = parse_shape(args.shape) if args.shape else (0, 0)
+    if args.tune and not args.shape:
         best, us = api.autotune(api.normalize_pixels(Xraw), p, M, K1=K1, K2=K2)
         log(f"tuned launch shape {best}: {us:.0f} us per outer iteration")
-    plan = api.plan(L, N, p, M)
+    plan = api.plan(L, N, p, M, runs_per_chunk=shape[0], pixel_groups=shape[1])
     log(f"scene L={L} N={N} p={p} M={M} T={T}, plan {plan}")
     out = dict(A=torch.empty((M, p, N), device=dev), B=torch.empty((M, N, p), device=dev),
                E=torch.empty((M, L, p), device=dev))
@@ -413,7 +436,7 @@ def main():
     def step(graph=False, time_passes=False):
         Xn = api.normalize_pixels(Xraw)
         return api.ensemble(Xn, p, seeds, gammas, T=T, K1=K1, K2=K2, graph=graph, out=out,
-                            time_passes=time_passes)
+                            time_passes=time_passes, runs_per_chunk=shape[0], pixel_groups=shape[1])
 
     for w in range(args.warmup):
         step(time_passes=True)
@@ -464,7 +487,8 @@ def main():
     a_avg_s = a_ms / max(a_n, 1) / 1e3
     achieved = bpass_flops / b_avg_s / 1e12
     roofline = dict(bound="mfma", achieved=round(achieved, 3), peak=FP32_MFMA_TFLOPS, unit="TFLOP/s",
-                    frac=round(achieved / FP32_MFMA_TFLOPS, 4), traffic=stored_traffic(TRAFFIC_FILE),
+                    frac=round(achieved / FP32_MFMA_TFLOPS, 4),
+                    traffic=stored_traffic(TRAFFIC_FILE, f"{plan['runs_per_chunk']},{plan['pixel_groups']}"),
                     kernel="k_bpass (B-pass)", avg_launch_us=round(b_avg_s * 1e6, 2),
                     algorithmic_bytes_per_launch=bpass_bytes, flops_per_launch=bpass_flops,
                     achieved_gbs=round(bpass_bytes / b_avg_s / 1e9, 1),

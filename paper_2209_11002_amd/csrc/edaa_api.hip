@@ -1295,9 +1295,13 @@ edaa_status edaa_autotune(edaa_ctx* ctx, const void* X, int L, int N, int p, int
     for (int i = 0; i < nr; ++i) {
         const int R = rc[i];
         if (!runs_fit(p, R, L) || (M == 1) != (R == 1)) continue;
+        // (multiples of 8 keep the chunks of a pixel group on one XCD, see
+        // wg_coords, so their shared X tiles stay in that XCD's L2)
         const int base = make_geom(L, N, M, p, R, 0).npg;
         for (int f : {1, 2, 4}) {
-            const int npg = std::max(1, std::min(base * f / 2, (N + kTile - 1) / kTile));
+            int npg = base * f / 2;
+            if (npg >= 8) npg &= ~7;
+            npg = std::max(1, std::min(npg, (N + kTile - 1) / kTile));
             bool dup = false;
             for (auto& c : cand) dup |= (c.first == R && c.second == npg);
             if (!dup) cand.emplace_back(R, npg);
@@ -1363,11 +1367,7 @@ edaa_status edaa_autotune_ragged(edaa_ctx* ctx, int n_images, edaa_image_desc* i
     if (st != EDAA_OK) return st;
     if ((st = check_params(params)) != EDAA_OK) return st;
     EDAA_REQUIRE(n_images >= 1 && images, "n_images must be >= 1 and images non-null");
-    std::vector<edaa_image_desc> d(images, images + n_images);
-    for (auto& x : d) {
-        x.loss_trace = nullptr;
-        x.pixel_groups = 0;
-    }
+    std::vector<edaa_image_desc> d(n_images);
     edaa_params P = *params;
     P.flags &= ~(EDAA_FLAG_GRAPH | EDAA_FLAG_TIME_PASSES | EDAA_FLAG_RAGGED_GROUPED);
     double bus = -1.0;
@@ -1376,6 +1376,13 @@ edaa_status edaa_autotune_ragged(edaa_ctx* ctx, int n_images, edaa_image_desc* i
         P.tiles_per_item = tpi;
         double t[2] = {1e30, 1e30};
         for (int rep = 0; rep < 5; ++rep) {
+            // a fit writes the item counts it used into the descriptors:
+            // start every trial from unpinned copies
+            for (int k = 0; k < n_images; ++k) {
+                d[k] = images[k];
+                d[k].loss_trace = nullptr;
+                d[k].pixel_groups = 0;
+            }
             P.T = (rep == 0 || rep % 2 == 1) ? kTuneShortT : kTuneLongT;
             double ms = 0.0;
             st = time_call(ctx, [&]() { return edaa_fit_ragged(ctx, n_images, d.data(), &P); }, &ms);
