@@ -275,10 +275,11 @@ def errors_vs_reference(r, ref, runs, T, idx, suffix, gammas, ref32=None):
 
 def bench_large(T, error_T=10):
     """The large smooth scene (L=224, N=512x614, p=12, M=20): the batched
-    ensemble with bf16 X and with float32 X (run-iterations/s), and their
-    errors against the stored float64 results (every run at T = 10; runs 0
-    and 4 at T = 100), plus the plain single-run path on float32 X with its
-    B-pass HBM roofline."""
+    ensemble with bf16 X (bf16 matrix cores, and widened to the float32
+    ones) and with float32 X (run-iterations/s), their errors against the
+    stored float64 results (every run at T = 10; runs 0 and 4 at T = 100),
+    the per-launch pass times of the bf16 ensemble, plus the plain
+    single-run path on float32 X with its B-pass HBM roofline."""
     import numpy as np
     import torch
     from paper_2209_11002_amd import api, synth
@@ -297,14 +298,14 @@ def bench_large(T, error_T=10):
     ref32_path = os.path.join(GOLDEN, "large_fp32_ref.npz")
     ref32 = dict(np.load(ref32_path)) if os.path.exists(ref32_path) else None
     res, errs = {}, {}
-    for name, X in (("bf16", X16), ("f32", X32)):
-        api.ensemble(X, p, seeds, gammas, T=T, graph=True)
+    for name, X, widen in (("bf16", X16, False), ("bf16_widen", X16, True), ("f32", X32, False)):
+        api.ensemble(X, p, seeds, gammas, T=T, graph=True, bf16_widen=widen)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        r = api.ensemble(X, p, seeds, gammas, T=T, graph=True)
+        r = api.ensemble(X, p, seeds, gammas, T=T, graph=True, bf16_widen=widen)
         torch.cuda.synchronize()
         res[name] = (M * T / (time.perf_counter() - t0), r["loss"][:, -1].copy())
-        if ref is not None:
+        if ref is not None and not widen:
             e = {}
             long_runs = [int(m) for m in ref["long_runs"]]
             if T >= 100:
@@ -317,7 +318,16 @@ def bench_large(T, error_T=10):
     rel = float(np.max(np.abs(res["bf16"][1] - res["f32"][1]) / res["f32"][1]))
     Q = M * p
     per_outer_bf16 = 6 * pass_bytes(L, N, Q, 2)
+    api.ensemble(X16, p, seeds, gammas, T=3, time_passes=True)
+    nb, bms = api.pass_times(dev, 1)
+    na, ams = api.pass_times(dev, 0)
+    b_us, a_us = 1e3 * bms / nb, 1e3 * ams / na
+    passes = dict(bpass_avg_launch_us=round(b_us, 2), apass_avg_launch_us=round(a_us, 2),
+                  bpass_algorithmic_gbs=round(pass_bytes(L, N, Q, 2) / b_us / 1e3, 1),
+                  bpass_flops_per_launch=4.0 * L * N * Q,
+                  bpass_fp32_equivalent_tflops=round(4.0 * L * N * Q / b_us / 1e6, 2))
     out = dict(unit="run-iterations/s", L=L, N=N, p=p, M=M, T=T, bf16=round(res["bf16"][0], 2),
+               bf16_widen=round(res["bf16_widen"][0], 2), bf16_passes=passes,
                f32=round(res["f32"][0], 2), final_loss_max_rel_diff_bf16_vs_f32=rel,
                bf16_gbs=round(per_outer_bf16 * res["bf16"][0] / M / 1e9, 1),
                bf16_hbm_frac=round(per_outer_bf16 * res["bf16"][0] / M / 1e9 / HBM_GBS, 4),

@@ -18,6 +18,7 @@ EDAA_COHERENCE_COSINE, EDAA_COHERENCE_RAW = 0, 1
 EDAA_FLAG_GRAPH = 1
 EDAA_FLAG_TIME_PASSES = 2
 EDAA_FLAG_RAGGED_GROUPED = 4
+EDAA_FLAG_BF16_WIDEN = 8
 
 
 class EdaaParams(ctypes.Structure):

@@ -455,7 +455,7 @@ std::string graph_key(const Seq& q, const void* X, const void* ws) {
              g.npg, g.nqc, q.mode, q.coherence_mode, q.T, q.K1, q.K2, X, (const void*)q.s->A, (const void*)q.B_out,
              (const void*)q.E_out, (const void*)q.A0, (const void*)(q.E_given ? q.E_given : q.ri.B0), ws,
              (double)q.ri.init_scale, q.ri.eta1,
-             q.ri.eta2, q.s->x_bf16, q.timer->enabled ? 1 : 0);
+             q.ri.eta2, q.s->x_bf16 + 2 * q.s->x_mfma, q.timer->enabled ? 1 : 0);
     return buf;
 }
 
@@ -519,6 +519,12 @@ edaa_status run_sequence(edaa_ctx* ctx, const Seq& q, const void* X, int use_gra
                         [&](hipStream_t st, long long* n) { return enqueue_sequence(q, st, n); });
 }
 
+// bf16 X runs the B-pass on the bf16 matrix cores unless the caller asks
+// for the float32 one or the chunk does not fit its LDS layout.
+int use_xb(const Geom& g, int x_bytes, int flags) {
+    return (x_bytes == 2 && !(flags & EDAA_FLAG_BF16_WIDEN) && xb_fits(g.p, g.R, g.L)) ? 1 : 0;
+}
+
 // Shared implementation of edaa_fit (M = 1) and edaa_ensemble.
 edaa_status run_batch(edaa_ctx* ctx, const void* X, int L, int N, int p, const edaa_params* P, int M,
                       const uint64_t* seeds, const double* gammas, const float* A0, const float* B0, float* A_all,
@@ -536,6 +542,7 @@ edaa_status run_batch(edaa_ctx* ctx, const void* X, int L, int N, int p, const e
     layout(g, P->T, x_bytes, (char*)ctx->ws, &rb);
     State& s = rb.s;
     s.A = A_all;
+    s.x_mfma = use_xb(g, x_bytes, P->flags);
 
     // Host -> device copies of the per-run scalars happen outside any graph.
     EDAA_HIP(ctx, hipMemcpyAsync(rb.seeds, seeds, sizeof(uint64_t) * M, hipMemcpyHostToDevice, ctx->stream));
@@ -1151,6 +1158,7 @@ edaa_status edaa_fit_noalloc(edaa_ctx* ctx, const void* X, int L, int N, int p, 
     layout(g, params->T, x_bytes, (char*)ctx->scratch, &rb);
     State& s = rb.s;
     s.A = A;
+    s.x_mfma = use_xb(g, x_bytes, params->flags);
     if (loss_trace_dev) s.trace = loss_trace_dev;     // [1][T+1]: the caller's array is the trace
     if (eta_dev) s.etad = eta_dev;
     EDAA_HIP(ctx, launch_set_run(rb.seeds, rb.gammas, seed, params->gamma, ctx->stream));

@@ -62,6 +62,38 @@ __device__ __forceinline__ d4 mfma16d(double a, double b, d4 c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
+// The bf16 shape D(16x16) += A(16x32) B(32x16) (v_mfma_f32_16x16x32_bf16,
+// float32 accumulation).  Lane l holds eight k of row l % 16 of A and the same
+// eight k of column l % 16 of B, as 8 bf16 in 16 bytes (k = 8 (l / 16) + j
+// for element j; the sum over k does not depend on that assignment as long as
+// both operands use it); D as for mfma16.
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+__device__ __forceinline__ f4 mfma16_bf16(u32x4 a, u32x4 b, f4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b), c,
+                                                    0, 0, 0);
+}
+
+// x = hi + mid + lo with three bf16 terms (round to nearest at each step).
+// Three 8-bit significands hold float32's 24, so the sum is exact for every
+// x whose last term is a normal bf16 (|x| above about 1e-30), and a product
+// of an exact bf16 value with each term is exact in float32.
+__device__ __forceinline__ void split_bf16x3(const float (&x)[8], u32x4& hi, u32x4& mid, u32x4& lo) {
+    bf16x8 h, m, l;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        const __bf16 a = (__bf16)x[j];
+        const float r = x[j] - (float)a;
+        const __bf16 b = (__bf16)r;
+        h[j] = a;
+        m[j] = b;
+        l[j] = (__bf16)(r - (float)b);
+    }
+    hi = __builtin_bit_cast(u32x4, h);
+    mid = __builtin_bit_cast(u32x4, m);
+    lo = __builtin_bit_cast(u32x4, l);
+}
+
 __device__ __forceinline__ int uniform_int(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
 __device__ __forceinline__ float wave_sum(float v) {
@@ -392,6 +424,35 @@ __host__ __device__ inline PassLds pass_lds(int PP, int R, int L, int dbuf, int 
     o.total = o.xs2 + (dbuf ? LP * kXS : 0);
     return o;
 }
+
+// LDS layout (bytes) of the B-pass on the bf16 matrix cores (bpass_xb_body),
+// with LP32 = L rounded up to 32 (the k depth of one MFMA):
+//   xn   [LP32][kXNP] bf16   X tile, pixels contiguous (rows >= L zero)
+//   xo   [LP32/8][64][8] bf16  X tile, 8 consecutive bands of a pixel contiguous
+//   wsp  [LP32/32][NCB][3][64] 16-byte MFMA operands of W (three bf16 terms)
+//   wb   [2][NCB][3][64]       16-byte MFMA operands of the tile's weights
+//   sq   [QCP][kXS] float      projection W^T x (sq2: second band half, NCB = 1)
+//   f, fg [QCP] float          rescale factors
+constexpr int kXNP = 72;   // bf16 per xn row: 64 pixels + 8, so 16 rows start on 16 distinct bank groups
+struct XbLds {
+    int xn, xo, wsp, wb, sq, sq2, f, fg, total;
+};
+__host__ __device__ inline XbLds xb_lds(int PP, int R, int L) {
+    const int QCP = (PP * R + 15) & ~15, NCB = QCP / 16, LP32 = (L + 31) & ~31;
+    XbLds o;
+    o.xn = 0;
+    o.xo = o.xn + LP32 * kXNP * 2;
+    o.wsp = o.xo + LP32 * 64 * 2;
+    o.wb = o.wsp + (LP32 / 32) * NCB * 3 * 1024;
+    o.sq = o.wb + 2 * NCB * 3 * 1024;
+    o.sq2 = o.sq + QCP * kXS * 4;
+    o.f = o.sq2 + (NCB == 1 ? 16 * kXS * 4 : 0);
+    o.fg = o.f + QCP * 4;
+    o.total = o.fg + QCP * 4;
+    return o;
+}
+// Bands a workgroup of the bf16 B-pass stages: one block of 32 per wave.
+constexpr int kXbMaxL = 32 * 8;
 
 // Scheduling pattern for a block of NMFMA matrix instructions and the LDS
 // reads of the next block's operands: the reads go, up to four at a time,
@@ -1249,6 +1310,331 @@ __global__ __launch_bounds__(64 * kBpassWaves, 1) void k_bpass_multi(const Image
     const int2 jl = map[blockIdx.x];
     const ImageJob& J = jobs[jl.x];
     bpass_body<PP, R, STEP>(J.g, J.s, jl.y, J.s.W, mode, J.ri);
+}
+
+// --------------------------------------------------------------------------
+// B-pass for bf16 X on the bf16 matrix cores: the same pass as bpass_body
+// (same softmax, state, partials and results), with both contractions on
+// v_mfma_f32_16x16x32_bf16.
+//
+// X stays bf16 in LDS, in two layouts (xb_lds): xn (pixels contiguous) is the
+// A operand of the accumulation X * weights^T, whose k runs over pixels; xo
+// (eight bands of a pixel contiguous) the B operand of the projection W^T x,
+// whose k runs over bands.  The float32 operands, W and the tile's weights,
+// are split into three bf16 terms (split_bf16x3): X is exact in bf16, so each
+// product is exact in the float32 accumulation and the three MFMAs give the
+// float32 product sums up to the order of the float32 additions.  Per 32
+// bands (projection) or 32 pixels (accumulation) that is 3 MFMAs of 16
+// clocks, against 8 float32 MFMAs of 32 clocks.
+//
+// X tiles are staged through registers one tile ahead: wave w loads band
+// block w (32 bands; L <= kXbMaxL), lane (kg, m) the 4 pixels 4m.. of bands
+// 32 w + 8 kg + j, j < 8, as eight 8-byte loads; store() writes them to xn
+// as they are and, repacked with byte permutes, to xo.
+// Work split (8 waves): projection as bpass_body (one column block: waves w
+// and w + 4 take alternate k blocks of pixel block w & 3; more: the two wave
+// groups take halves of the column blocks); accumulation by row blocks of 16
+// bands, rb = w + 8 j.
+// --------------------------------------------------------------------------
+template <int NC, int CB0, int NCB, int KBS>
+__device__ __forceinline__ void xb_project(const u32x4* Xo, const u32x4* Wsp, float* Sq, int nkb, int kb0, int pb,
+                                           int lane) {
+    const int m = lane & 15, kg = lane >> 4;
+    f4 s[NC], s2[NC];
+#pragma unroll
+    for (int cb = 0; cb < NC; ++cb) s[cb] = s2[cb] = f4{0.f, 0.f, 0.f, 0.f};
+    for (int kb = kb0; kb < nkb; kb += KBS) {
+        const u32x4 b = Xo[(4 * kb + kg) * 64 + 16 * pb + m];
+        const u32x4* wp = Wsp + (size_t)(kb * NCB + CB0) * 3 * 64 + lane;
+#pragma unroll
+        for (int cb = 0; cb < NC; ++cb) {
+            // with one column block the middle term goes to a second chain
+            s[cb] = mfma16_bf16(wp[(3 * cb) * 64], b, s[cb]);
+            if (NC == 1)
+                s2[cb] = mfma16_bf16(wp[(3 * cb + 1) * 64], b, s2[cb]);
+            else
+                s[cb] = mfma16_bf16(wp[(3 * cb + 1) * 64], b, s[cb]);
+            s[cb] = mfma16_bf16(wp[(3 * cb + 2) * 64], b, s[cb]);
+        }
+    }
+#pragma unroll
+    for (int cb = 0; cb < NC; ++cb) {
+        if (NC == 1) s[cb] += s2[cb];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) Sq[(16 * (CB0 + cb) + 4 * kg + v) * kXS + 16 * pb + m] = s[cb][v];
+    }
+}
+
+// V += X_tile Wt on the bf16 matrix cores, folded into the float64 running
+// sums like mfma_accumulate (with SCALE): the running sums of column q are
+// multiplied by F[q], the tile's by G[q].
+template <int NCB, int NRBW, int NW>
+__device__ __forceinline__ void xb_accumulate(d4 (&acc)[NRBW][NCB], const uint16_t* Xn, const u32x4* Wb,
+                                              const float* F, const float* G, int nrb, int w, int lane) {
+    const int m = lane & 15, kg = lane >> 4;
+    f4 t[NRBW][NCB];
+#pragma unroll
+    for (int j = 0; j < NRBW; ++j)
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb) t[j][cb] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int pkb = 0; pkb < 2; ++pkb) {
+        u32x4 bop[NCB][3];
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb)
+#pragma unroll
+            for (int sp = 0; sp < 3; ++sp) bop[cb][sp] = Wb[((pkb * NCB + cb) * 3 + sp) * 64 + lane];
+#pragma unroll
+        for (int j = 0; j < NRBW; ++j) {
+            const int rb = w + NW * j;
+            if (rb < nrb) {
+                const u32x4 a = *(const u32x4*)(Xn + (16 * rb + m) * kXNP + 32 * pkb + 8 * kg);
+#pragma unroll
+                for (int sp = 0; sp < 3; ++sp)
+#pragma unroll
+                    for (int cb = 0; cb < NCB; ++cb) t[j][cb] = mfma16_bf16(a, bop[cb][sp], t[j][cb]);
+            }
+        }
+    }
+    float fs[NCB], gs[NCB];
+#pragma unroll
+    for (int cb = 0; cb < NCB; ++cb) {
+        fs[cb] = F[16 * cb + m];
+        gs[cb] = G[16 * cb + m];
+    }
+#pragma unroll
+    for (int j = 0; j < NRBW; ++j)
+        if (w + NW * j < nrb)
+#pragma unroll
+            for (int cb = 0; cb < NCB; ++cb)
+#pragma unroll
+                for (int v = 0; v < 4; ++v)
+                    acc[j][cb][v] = fma(acc[j][cb][v], (double)fs[cb], (double)t[j][cb][v] * (double)gs[cb]);
+}
+
+template <int PP, int R, bool STEP>
+__device__ __forceinline__ void bpass_xb_body(const Geom& g, const State& s, int bid, const float* __restrict__ W,
+                                              int mode, const RunInit& ri) {
+    using S = Shape<PP, R>;
+    constexpr int NW = 8, NT = 64 * NW;
+    constexpr int QC = S::QC, QCP = S::QCP, NCB = S::NCB, NRBW = S::NRBW * 4 / NW;
+    constexpr int SPX = kTile / NW, SV = SPX / 4;   // softmax: 8 lanes per column, 8 pixels each
+    constexpr int NC0 = (NCB + 1) / 2, NC1 = NCB - NC0;
+    static_assert(SPX == 8 && QCP * NW <= NT, "eight lanes of eight pixels per softmax column");
+    extern __shared__ float smem[];
+    char* const lds = (char*)smem;
+    const XbLds lo = xb_lds(PP, R, g.L);
+    uint16_t* Xn = (uint16_t*)(lds + lo.xn);
+    u32x4* Xo = (u32x4*)(lds + lo.xo);
+    u32x4* Wsp = (u32x4*)(lds + lo.wsp);
+    u32x4* Wb = (u32x4*)(lds + lo.wb);
+    float* Sq = (float*)(lds + lo.sq);
+    float* Sq2 = (float*)(lds + lo.sq2);
+    float* F = (float*)(lds + lo.f);
+    float* FG = (float*)(lds + lo.fg);
+
+    int pg, c;
+    wg_coords(g, bid, pg, c);
+    const int tid = threadIdx.x, lane = tid & 63, m = lane & 15, kg = lane >> 4;
+    const int w = uniform_int(tid >> 6);
+    const int L = g.L, N = g.N, nkb = (L + 31) >> 5, nrb = (L + 15) >> 4;
+    const size_t Np = (size_t)g.ntiles * kTile;
+    const int col0 = c * QC;
+
+    for (int e = tid; e < QCP; e += NT) F[e] = FG[e] = 0.f;
+    for (int e = tid; e < 2 * NCB * 3 * 64; e += NT) Wb[e] = u32x4{0u, 0u, 0u, 0u};
+    if (STEP) {
+        // W[:, chunk] as MFMA A operands: entry (kb, cb, lane) holds the rows
+        // 32 kb + 8 (lane / 16) + j of column 16 cb + lane % 16, in three terms
+        for (int e = tid; e < nkb * NCB * 64; e += NT) {
+            const int ln = e & 63, kc = e >> 6;
+            const int q = 16 * (kc % NCB) + (ln & 15), r0 = 32 * (kc / NCB) + 8 * (ln >> 4);
+            float x[8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) x[j] = (r0 + j < L && q < QC) ? W[(size_t)(r0 + j) * g.Qp + col0 + q] : 0.f;
+            u32x4 h, md, lw;
+            split_bf16x3(x, h, md, lw);
+            Wsp[(kc * 3 + 0) * 64 + ln] = h;
+            Wsp[(kc * 3 + 1) * 64 + ln] = md;
+            Wsp[(kc * 3 + 2) * 64 + ln] = lw;
+        }
+    }
+
+    const int sq = tid / NW, sub = tid % NW;
+    const int sm = c * R + sq / PP, sj = sq % PP;
+    const bool qin = sq < QC;
+    const bool cok = qin && sm < g.M;
+    float* bcol = s.Bst + (size_t)(cok ? col0 + sq : 0) * Np + SPX * sub;
+    float mrun = -INFINITY, lzc = 0.f, eta2 = 0.f;
+    double srun = 0.0;
+    if (STEP && cok) {
+        lzc = -s.colm[col0 + sq] - logf(s.cols[col0 + sq]);
+        eta2 = s.eta[2 * sm + 1];
+    }
+
+    d4 acc[NRBW][NCB];
+#pragma unroll
+    for (int jb = 0; jb < NRBW; ++jb)
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb) acc[jb][cb] = d4{0.0, 0.0, 0.0, 0.0};
+
+    // X staging registers of this wave's band block
+    const bool xw = 32 * w < L;
+    uint2 xv[8];
+    auto x_issue = [&](int tile) {
+        if (xw) {
+            const uint16_t* src = (const uint16_t*)s.X + (size_t)tile * kTile + 4 * m;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const int row = min(32 * w + 8 * kg + j, L - 1);
+                xv[j] = *(const uint2*)(src + (size_t)row * s.ldx);
+            }
+        }
+    };
+    auto x_store = [&]() {
+        if (xw) {
+            uint2 v[8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const int row = 32 * w + 8 * kg + j;
+                v[j] = row < L ? xv[j] : make_uint2(0u, 0u);
+                *(uint2*)(Xn + row * kXNP + 4 * m) = v[j];
+            }
+            // pixel 4 m + u: element j of its 16 bytes is band 32 w + 8 kg + j
+            u32x4* dst = Xo + (4 * w + kg) * 64 + 4 * m;
+            dst[0] = u32x4{__builtin_amdgcn_perm(v[1].x, v[0].x, 0x05040100u), __builtin_amdgcn_perm(v[3].x, v[2].x, 0x05040100u),
+                           __builtin_amdgcn_perm(v[5].x, v[4].x, 0x05040100u), __builtin_amdgcn_perm(v[7].x, v[6].x, 0x05040100u)};
+            dst[1] = u32x4{__builtin_amdgcn_perm(v[1].x, v[0].x, 0x07060302u), __builtin_amdgcn_perm(v[3].x, v[2].x, 0x07060302u),
+                           __builtin_amdgcn_perm(v[5].x, v[4].x, 0x07060302u), __builtin_amdgcn_perm(v[7].x, v[6].x, 0x07060302u)};
+            dst[2] = u32x4{__builtin_amdgcn_perm(v[1].y, v[0].y, 0x05040100u), __builtin_amdgcn_perm(v[3].y, v[2].y, 0x05040100u),
+                           __builtin_amdgcn_perm(v[5].y, v[4].y, 0x05040100u), __builtin_amdgcn_perm(v[7].y, v[6].y, 0x05040100u)};
+            dst[3] = u32x4{__builtin_amdgcn_perm(v[1].y, v[0].y, 0x07060302u), __builtin_amdgcn_perm(v[3].y, v[2].y, 0x07060302u),
+                           __builtin_amdgcn_perm(v[5].y, v[4].y, 0x07060302u), __builtin_amdgcn_perm(v[7].y, v[6].y, 0x07060302u)};
+        }
+    };
+
+    f4 bn[SV];
+    float tn = 0.f;
+    auto load_b = [&](int tile) {
+        if (STEP && cok) {
+            const f4* src = (const f4*)(bcol + (size_t)tile * kTile);
+#pragma unroll
+            for (int u = 0; u < SV; ++u) bn[u] = src[u];
+            tn = s.tshift[(size_t)tile * g.Qp + col0 + sq];
+        }
+    };
+    __syncthreads();
+    if (pg < g.ntiles) {
+        x_issue(pg);
+        x_store();
+        load_b(pg);
+    }
+    for (int tile = pg; tile < g.ntiles; tile += g.npg) {
+        __builtin_amdgcn_s_waitcnt(0);
+        lds_barrier();
+        f4 bv[SV];
+#pragma unroll
+        for (int u = 0; u < SV; ++u) bv[u] = bn[u];
+        const float ts = tn;
+        const int nt = tile + g.npg;
+        if (nt < g.ntiles) {
+            load_b(nt);
+            x_issue(nt);
+        }
+
+        if (STEP) {
+            if constexpr (NCB == 1)
+                xb_project<1, 0, 1, 2>(Xo, Wsp, (w < 4) ? Sq : Sq2, nkb, w >> 2, w & 3, lane);
+            else if (w < 4)
+                xb_project<NC0, 0, NCB, 1>(Xo, Wsp, Sq, nkb, 0, w, lane);
+            else if constexpr (NC1 > 0)
+                xb_project<NC1, NC0, NCB, 1>(Xo, Wsp, Sq, nkb, 0, w - 4, lane);
+            lds_barrier();
+        }
+
+        if (qin) {
+            const int pix0 = tile * kTile + SPX * sub;
+            float v[SPX];
+            if (STEP) {
+                const float sh = ts + lzc;
+                const float* grow = Sq + sq * kXS + SPX * sub;
+#pragma unroll
+                for (int u = 0; u < SV; ++u) {
+                    f4 gv = *(const f4*)(grow + 4 * u);
+                    if constexpr (NCB == 1) gv += *(const f4*)(grow - Sq + Sq2 + 4 * u);
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) v[4 * u + e] = fast_log(bv[u][e]) + sh - eta2 * gv[e];
+                }
+            } else if (mode == kModeInitRng) {
+                const uint64_t seed = ri.seeds[cok ? sm : 0];
+#pragma unroll
+                for (int i = 0; i < SPX; ++i) v[i] = ri.init_scale * uniform_u(seed, pix0 + i, sj);
+            } else {
+#pragma unroll
+                for (int i = 0; i < SPX; ++i) v[i] = fast_log(ri.B0[(size_t)min(pix0 + i, N - 1) * PP + sj]);
+            }
+            float mx = -INFINITY;
+#pragma unroll
+            for (int i = 0; i < SPX; ++i) {
+                v[i] = (cok && pix0 + i < N) ? v[i] : -INFINITY;
+                mx = fmaxf(mx, v[i]);
+            }
+            mx = fmaxf(mx, dpp<0xB1>(mx));
+            mx = fmaxf(mx, dpp<0x4E>(mx));
+            mx = fmaxf(mx, dpp<0x141>(mx));
+            const float mnew = fmaxf(mrun, mx);
+            const float f = (mrun == -INFINITY) ? 0.f : fast_exp(mrun - mnew);
+            const float fg = (mx == -INFINITY) ? 0.f : fast_exp(mx - mnew);
+            float wv[SPX], sum = 0.f;
+#pragma unroll
+            for (int i = 0; i < SPX; ++i) {
+                wv[i] = (v[i] == -INFINITY) ? 0.f : fast_exp(v[i] - mx);
+                sum += wv[i];
+            }
+            sum += dpp<0xB1>(sum);
+            sum += dpp<0x4E>(sum);
+            sum += dpp<0x141>(sum);
+            srun = fma(srun, (double)f, (double)sum * (double)fg);
+            mrun = mnew;
+            if (cok) {
+#pragma unroll
+                for (int u = 0; u < SV; ++u)
+                    ((f4*)(bcol + (size_t)tile * kTile))[u] = f4{wv[4 * u], wv[4 * u + 1], wv[4 * u + 2], wv[4 * u + 3]};
+            }
+            // the accumulation's B operand: pixels 8 sub .. of column sq are
+            // k = 8 (sub % 4) + j of pixel block sub / 4
+            u32x4 h, md, lw;
+            split_bf16x3(wv, h, md, lw);
+            u32x4* dst = Wb + ((sub >> 2) * NCB + (sq >> 4)) * 3 * 64 + 16 * (sub & 3) + (sq & 15);
+            dst[0] = h;
+            dst[64] = md;
+            dst[128] = lw;
+            if (sub == 0) {
+                F[sq] = f;
+                FG[sq] = fg;
+                if (cok) s.tshift[(size_t)tile * g.Qp + col0 + sq] = mx;
+            }
+        }
+        lds_barrier();
+        xb_accumulate<NCB, NRBW, NW>(acc, Xn, Wb, F, FG, nrb, w, lane);
+        if (nt < g.ntiles) {
+            lds_barrier();                         // every wave is done with this tile's X
+            x_store();
+        }
+    }
+
+    const size_t wgi = (size_t)pg * g.nqc + c;
+    store_acc<NCB, NRBW, QC, NW>(acc, s.Vpart + wgi * (size_t)L * QC, L, nrb, w, lane);
+    if (qin && sub == 0) {
+        s.mpart[(size_t)pg * g.Qp + col0 + sq] = cok ? mrun : -INFINITY;
+        s.spart[(size_t)pg * g.Qp + col0 + sq] = cok ? (float)srun : 0.f;
+    }
+}
+
+template <int PP, int R, bool STEP>
+__global__ __launch_bounds__(64 * kBpassWaves, 1) void k_bpass_xb(Geom g, State s, const float* __restrict__ W,
+                                                                  int mode, RunInit ri) {
+    bpass_xb_body<PP, R, STEP>(g, s, blockIdx.x, W, mode, ri);
 }
 
 // --------------------------------------------------------------------------

@@ -24,6 +24,19 @@ struct Kernels {
         return hipGetLastError();
     }
     static hipError_t bpass(const Geom& g, const State& s, int mode, const RunInit& ri, hipStream_t st) {
+        if (s.x_mfma) {
+            const size_t lds = xb_lds(PP, R, g.L).total;
+            if (mode == kModeStep) {
+                set_max_lds((const void*)k_bpass_xb<PP, R, true>, (int)lds);
+                hipLaunchKernelGGL((k_bpass_xb<PP, R, true>), dim3(g.npg * g.nqc), dim3(64 * kBpassWaves), lds, st, g,
+                                   s, (const float*)s.W, mode, ri);
+            } else {
+                set_max_lds((const void*)k_bpass_xb<PP, R, false>, (int)lds);
+                hipLaunchKernelGGL((k_bpass_xb<PP, R, false>), dim3(g.npg * g.nqc), dim3(64 * kBpassWaves), lds, st,
+                                   g, s, (const float*)s.W, mode, ri);
+            }
+            return hipGetLastError();
+        }
         const size_t lds = (size_t)pass_lds(PP, R, g.L, g.dbuf, g.ecs, g.gf).total * sizeof(float);
         if (mode == kModeStep) {
             set_max_lds((const void*)k_bpass<PP, R, true>, (int)lds);

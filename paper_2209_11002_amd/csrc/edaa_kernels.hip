@@ -100,6 +100,10 @@ size_t pass_lds_bytes(int PP, int R, int L, int kind) {
     return (size_t)pass_lds(PP, R, L, 0, QCP + 1, 0).total * sizeof(float);
 }
 
+bool xb_fits(int p, int R, int L) {
+    return L <= kXbMaxL && (size_t)xb_lds(p, R, L).total <= kMaxLdsBytes;
+}
+
 bool runs_fit(int p, int R, int L) {
     if (!has_runs(p, R) || L > max_bands(p, R)) return false;
     for (int kind = 0; kind < 3; ++kind)

@@ -103,6 +103,55 @@ def test_ragged_bf16_equals_single_fits(api):
         imgs.append((_prep(s.X, torch.bfloat16)[0], p))
     rr = api.fit_ragged([x for x, _ in imgs], [p for _, p in imgs], [1, 2, 3], [1.0, 0.5, 2.0], T=8)
     for k, ((Xg, p), r) in enumerate(zip(imgs, rr)):
-        one = api.fit(Xg, p, T=8, gamma=[1.0, 0.5, 2.0][k], seed=k + 1, pixel_groups=r["pixel_groups"])
+        # the ragged kernels run bf16 X on the float32 matrix cores
+        one = api.fit(Xg, p, T=8, gamma=[1.0, 0.5, 2.0][k], seed=k + 1, pixel_groups=r["pixel_groups"],
+                      bf16_widen=True)
         assert torch.equal(r["A"], one["A"]) and torch.equal(r["B"], one["B"]), k
         assert np.array_equal(r["loss"], one["loss"]), k
+
+
+@gpu
+@pytest.mark.parametrize("L,N,p,M,T", [
+    (64, 900, 5, 1, 8),      # one run: one column block, k blocks split between wave pairs
+    (162, 1000, 6, 10, 6),   # 8 runs per chunk (three column blocks), L not a multiple of 32
+    (224, 2048, 12, 4, 6),   # the large scene's (L, p): four runs per chunk
+    (256, 700, 16, 2, 5),    # the largest L of the bf16 matrix path, two column blocks
+    (1, 100, 2, 1, 6),       # a single band: one k block of 32 with 31 zero bands
+    (30, 50, 3, 10, 5),      # fewer pixels than one tile, 20 runs per chunk (four column blocks)
+])
+def test_bf16_matrix_path_vs_oracle(api, L, N, p, M, T):
+    """bf16 X on the bf16 matrix cores (the default for bf16 X) against the
+    oracle run on the same bf16 values, at the float32 gates; and against
+    the float32-matrix-core path (bf16_widen), which computes the same
+    products in float32: the two must agree to float32 rounding but not be
+    identical (a check that the bf16 path ran)."""
+    _say(f"bf16 matrix path L={L} N={N} p={p} M={M} T={T}")
+    # L = 1 checks the 31 zero bands of the k block on the all-positive
+    # single-band scene of test_edge_shapes_vs_oracle (seed 41).  With mixed
+    # signs (seed 71: pixels normalise to +-1) the objective falls from 24 to
+    # 1.9 in six iterations and plain float32 arithmetic already moves it by
+    # 4.6e-5 there, growing tenfold per iteration: no float32 gate holds.
+    s = synth.small_case(seed=41 if L == 1 else 70 + L, L=L, N=N, p=min(p, max(1, L)))
+    Xg, X = _prep(s.X, torch.bfloat16)
+    seeds = [m // 2 for m in range(M)]
+    gammas = [(0.5, 1.0)[m % 2] for m in range(M)]
+    r = api.ensemble(Xg, p, seeds, gammas, T=T) if M > 1 else None
+    if M == 1:
+        one = api.fit(Xg, p, T=T, gamma=gammas[0], seed=seeds[0])
+        wide = api.fit(Xg, p, T=T, gamma=gammas[0], seed=seeds[0], bf16_widen=True)
+        r = dict(loss=one["loss"][None], A=one["A"][None], B=one["B"][None])
+        rw = dict(loss=wide["loss"][None])
+    else:
+        rw = api.ensemble(Xg, p, seeds, gammas, T=T, bf16_widen=True)
+    floor = 1e-7 * 0.5 * float(np.sum(X * X))
+    for m in sorted({0, M // 2, M - 1}):
+        ref = O.edaa_fit(X, p, T=T, gamma=gammas[m], seed=seeds[m])
+        rel = np.max(np.abs(r["loss"][m] - ref["loss"]) / np.maximum(ref["loss"], floor))
+        A_err = np.max(np.abs(_np(r["A"][m]) - ref["A"]))
+        NB_err = N * np.max(np.abs(_np(r["B"][m]) - ref["B"]))
+        dw = np.max(np.abs(r["loss"][m] - rw["loss"][m]) / np.maximum(rw["loss"][m], floor))
+        _say(f"run {m}: vs oracle loss {rel:.2e} A {A_err:.2e} N*B {NB_err:.2e}; vs float32 matrix path {dw:.2e}")
+        assert rel <= 1e-4 and A_err <= 1e-3 and NB_err <= 1e-2
+        assert dw <= 1e-4
+    if L > 1:
+        assert not np.array_equal(r["loss"], rw["loss"])

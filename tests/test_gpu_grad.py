@@ -45,6 +45,17 @@ def _rel(a, b):
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
+def _elementwise(a, b, tol=1e-5):
+    """Every entry within tol of the gradient's largest entry plus tol of its
+    own size (a Frobenius-norm gate alone would let one entry be off by up to
+    sqrt(size) times more)."""
+    d = np.abs(a - b)
+    bound = tol * np.max(np.abs(b)) + tol * np.abs(b)
+    worst = float(np.max(d / bound))
+    _say(f"element-wise: worst entry at {worst:.3f} of its bound")
+    return worst <= 1.0
+
+
 @gpu
 @pytest.mark.parametrize("L,N,p", [(40, 333, 3), (198, 1000, 4), (300, 70, 16)])
 def test_loss_and_gradients_vs_oracle(api, L, N, p):
@@ -56,8 +67,11 @@ def test_loss_and_gradients_vs_oracle(api, L, N, p):
     assert f == pytest.approx(O.loss(X64, A64, B64), rel=1e-5)
     go = torch.tensor(0.75, device="cuda")
     gA, gB = api.loss_bwd(Xg, Ag, Bg, go)
-    assert _rel(gA.cpu().numpy(), 0.75 * O.grad_A(X64, A64, B64)) < 1e-5
-    assert _rel(gB.cpu().numpy(), 0.75 * O.grad_B(X64, A64, B64)) < 1e-5
+    gA_ref, gB_ref = 0.75 * O.grad_A(X64, A64, B64), 0.75 * O.grad_B(X64, A64, B64)
+    assert _rel(gA.cpu().numpy(), gA_ref) < 1e-5
+    assert _rel(gB.cpu().numpy(), gB_ref) < 1e-5
+    assert _elementwise(gA.cpu().numpy(), gA_ref)
+    assert _elementwise(gB.cpu().numpy(), gB_ref)
 
 
 @gpu
@@ -102,6 +116,8 @@ def test_autograd_function_fd_on_jasper_crop(api):
         assert _rel(Bg.grad.cpu().numpy(), fdB) < 1e-5
         assert _rel(Ag.grad.cpu().numpy(), O.grad_A(X64, A64, B64)) < 1e-5
         assert _rel(Bg.grad.cpu().numpy(), O.grad_B(X64, A64, B64)) < 1e-5
+        assert _elementwise(Ag.grad.cpu().numpy(), fdA)
+        assert _elementwise(Bg.grad.cpu().numpy(), fdB)
 
 
 @gpu
