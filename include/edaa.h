@@ -58,11 +58,13 @@ enum {
     EDAA_FLAG_RAGGED_GROUPED = 4, /* edaa_fit_ragged: run every image with one
                                 launch per kernel and group of equal p instead
                                 of the persistent kernel */
-    EDAA_FLAG_BF16_WIDEN = 8 /* bf16 X (edaa_fit, edaa_ensemble, edaa_fit_noalloc):
-                                widen X tiles to float32 and run the B-pass on
-                                the float32 matrix cores, instead of the default
-                                bf16 matrix-core B-pass (X stays bf16; the
-                                float32 operand in three bf16 terms) */
+    EDAA_FLAG_BF16_WIDEN = 8 /* bf16 X (edaa_fit, edaa_ensemble, edaa_abundances,
+                                edaa_fit_noalloc): widen X tiles to float32 and
+                                run the A- and B-passes on the float32 (and, for
+                                the projection of the A-pass, float64) matrix
+                                cores, instead of the default bf16 matrix-core
+                                passes (X stays bf16; the float32 operand in
+                                three bf16 terms) */
 };
 
 /* Parameters of Algorithm 1 / Algorithm 2.  edaa_default_params fills the

@@ -519,10 +519,12 @@ edaa_status run_sequence(edaa_ctx* ctx, const Seq& q, const void* X, int use_gra
                         [&](hipStream_t st, long long* n) { return enqueue_sequence(q, st, n); });
 }
 
-// bf16 X runs the B-pass on the bf16 matrix cores unless the caller asks
-// for the float32 one or the chunk does not fit its LDS layout.
+// bf16 X runs the B-pass (bit 0) and the A-pass (bit 1) on the bf16 matrix
+// cores unless the caller asks for the float32 ones or the chunk does not
+// fit the pass's LDS layout.
 int use_xb(const Geom& g, int x_bytes, int flags) {
-    return (x_bytes == 2 && !(flags & EDAA_FLAG_BF16_WIDEN) && xb_fits(g.p, g.R, g.L)) ? 1 : 0;
+    if (x_bytes != 2 || (flags & EDAA_FLAG_BF16_WIDEN)) return 0;
+    return (xb_fits(g.p, g.R, g.L) ? 1 : 0) | (xa_fits(g.p, g.R, g.L) ? 2 : 0);
 }
 
 // Shared implementation of edaa_fit (M = 1) and edaa_ensemble.

@@ -45,6 +45,10 @@ constexpr int kBpassWaves = 8;
 // per-pixel A-steps (p x p products on p-vectors in registers) need more
 // than the 256 registers a wave has at two waves per SIMD.
 constexpr int apass_waves(int p) { return p <= 9 ? 8 : 4; }
+// The A-pass on the bf16 matrix cores (bf16 X) takes the same wave counts
+// (eight waves at p = 10..12 measured slower: the A-steps still occupy one
+// wave per SIMD, and the Gram rows no longer fit the registers).
+constexpr int xa_waves(int p) { return apass_waves(p); }
 constexpr int kXS = 68;   // LDS pitch (floats) of an X tile row of 64 pixels
 
 typedef float f4 __attribute__((ext_vector_type(4)));
@@ -451,8 +455,35 @@ __host__ __device__ inline XbLds xb_lds(int PP, int R, int L) {
     o.total = o.fg + QCP * 4;
     return o;
 }
-// Bands a workgroup of the bf16 B-pass stages: one block of 32 per wave.
+// Bands the bf16 matrix-core passes stage: eight blocks of 32.
 constexpr int kXbMaxL = 32 * 8;
+
+// LDS layout (bytes) of the A-pass on the bf16 matrix cores (apass_xb_body):
+//   xn, xo  the X tile as for the B-pass
+//   esp  [LP32/32][NCB][3][64] 16-byte MFMA operands of E (three bf16 terms)
+//   wt   [64][WTS] float      projection P (high part), then the new abundances
+//   plo  [64][WTS] float      low part of P; once the A-steps have read it, the
+//                             [2][NCB][3][64] MFMA operands of the abundances
+//   gs   [R][PP][PP] double   Gram matrices (gf: [R][PP][PP] float copy)
+//   xx   [64] double          squared pixel norms
+struct XaLds {
+    int xn, xo, esp, wt, plo, gs, gf, xx, total;
+};
+__host__ __device__ inline XaLds xa_lds(int PP, int R, int L, int gf) {
+    const int QCP = (PP * R + 15) & ~15, NCB = QCP / 16, WTS = QCP + 1, LP32 = (L + 31) & ~31;
+    const int wt_bytes = kTile * WTS * 4, op_bytes = 2 * NCB * 3 * 1024;
+    XaLds o;
+    o.xn = 0;
+    o.xo = o.xn + LP32 * kXNP * 2;
+    o.esp = o.xo + LP32 * 64 * 2;
+    o.wt = o.esp + (LP32 / 32) * NCB * 3 * 1024;
+    o.plo = o.wt + wt_bytes;
+    o.gs = o.plo + (wt_bytes > op_bytes ? wt_bytes : op_bytes);
+    o.gf = o.gs + R * PP * PP * 8;
+    o.xx = (o.gf + (gf ? R * PP * PP * 4 : 0) + 7) & ~7;
+    o.total = o.xx + kTile * 8;
+    return o;
+}
 
 // Scheduling pattern for a block of NMFMA matrix instructions and the LDS
 // reads of the next block's operands: the reads go, up to four at a time,
@@ -1327,15 +1358,82 @@ __global__ __launch_bounds__(64 * kBpassWaves, 1) void k_bpass_multi(const Image
 // bands (projection) or 32 pixels (accumulation) that is 3 MFMAs of 16
 // clocks, against 8 float32 MFMAs of 32 clocks.
 //
-// X tiles are staged through registers one tile ahead: wave w loads band
-// block w (32 bands; L <= kXbMaxL), lane (kg, m) the 4 pixels 4m.. of bands
-// 32 w + 8 kg + j, j < 8, as eight 8-byte loads; store() writes them to xn
-// as they are and, repacked with byte permutes, to xo.
+// X tiles are staged through registers one tile ahead (XbStage).
 // Work split (8 waves): projection as bpass_body (one column block: waves w
 // and w + 4 take alternate k blocks of pixel block w & 3; more: the two wave
 // groups take halves of the column blocks); accumulation by row blocks of 16
 // bands, rb = w + 8 j.
 // --------------------------------------------------------------------------
+// Register staging of a bf16 X tile into both LDS layouts of the bf16
+// matrix-core passes: wave w stages the 32-band blocks w, w + NW, ... (L <=
+// kXbMaxL); lane (kg, m) loads the 4 pixels 4 m.. of the bands 32 bi + 8 kg +
+// j, j < 8, as eight 8-byte loads (issued one tile ahead), and store()
+// writes them to xn as they are and, repacked with byte permutes, to xo.
+template <int NW>
+struct XbStage {
+    static constexpr int NBW = kXbMaxL / 32 / NW;   // band blocks per wave
+    uint2 v[NBW][8];
+
+    __device__ __forceinline__ void issue(const void* X, size_t ldx, int L, int tile) {
+        const int lane = threadIdx.x & 63, w = uniform_int(threadIdx.x >> 6), m = lane & 15, kg = lane >> 4;
+        const uint16_t* src = (const uint16_t*)X + (size_t)tile * kTile + 4 * m;
+#pragma unroll
+        for (int i = 0; i < NBW; ++i) {
+            const int bi = w + NW * i;
+            if (32 * bi < L) {                         // uniform per wave
+#pragma unroll
+                for (int j = 0; j < 8; ++j) {
+                    const int row = min(32 * bi + 8 * kg + j, L - 1);
+                    v[i][j] = *(const uint2*)(src + (size_t)row * ldx);
+                }
+            }
+        }
+    }
+    __device__ __forceinline__ void store(uint16_t* Xn, u32x4* Xo, int L) const {
+        const int lane = threadIdx.x & 63, w = uniform_int(threadIdx.x >> 6), m = lane & 15, kg = lane >> 4;
+#pragma unroll
+        for (int i = 0; i < NBW; ++i) {
+            const int bi = w + NW * i;
+            if (32 * bi < L) {
+                uint2 u[8];
+#pragma unroll
+                for (int j = 0; j < 8; ++j) {
+                    const int row = 32 * bi + 8 * kg + j;
+                    u[j] = row < L ? v[i][j] : make_uint2(0u, 0u);
+                    *(uint2*)(Xn + row * kXNP + 4 * m) = u[j];
+                }
+                // pixel 4 m + e: element j of its 16 bytes is band 32 bi + 8 kg + j
+                u32x4* dst = Xo + (4 * bi + kg) * 64 + 4 * m;
+                constexpr unsigned LO = 0x05040100u, HI = 0x07060302u;
+                dst[0] = u32x4{__builtin_amdgcn_perm(u[1].x, u[0].x, LO), __builtin_amdgcn_perm(u[3].x, u[2].x, LO),
+                               __builtin_amdgcn_perm(u[5].x, u[4].x, LO), __builtin_amdgcn_perm(u[7].x, u[6].x, LO)};
+                dst[1] = u32x4{__builtin_amdgcn_perm(u[1].x, u[0].x, HI), __builtin_amdgcn_perm(u[3].x, u[2].x, HI),
+                               __builtin_amdgcn_perm(u[5].x, u[4].x, HI), __builtin_amdgcn_perm(u[7].x, u[6].x, HI)};
+                dst[2] = u32x4{__builtin_amdgcn_perm(u[1].y, u[0].y, LO), __builtin_amdgcn_perm(u[3].y, u[2].y, LO),
+                               __builtin_amdgcn_perm(u[5].y, u[4].y, LO), __builtin_amdgcn_perm(u[7].y, u[6].y, LO)};
+                dst[3] = u32x4{__builtin_amdgcn_perm(u[1].y, u[0].y, HI), __builtin_amdgcn_perm(u[3].y, u[2].y, HI),
+                               __builtin_amdgcn_perm(u[5].y, u[4].y, HI), __builtin_amdgcn_perm(u[7].y, u[6].y, HI)};
+            }
+        }
+    }
+};
+
+// Operands of one k block of a bf16 projection: the X operand and the three
+// terms of NC column blocks of the float32 operand.
+template <int NC>
+struct XbOps {
+    u32x4 b, e[NC][3];
+    template <int CB0, int NCB>
+    __device__ __forceinline__ void load(const u32x4* Xo, const u32x4* Esp, int kb, int pb, int lane) {
+        b = Xo[(4 * kb + (lane >> 4)) * 64 + 16 * pb + (lane & 15)];
+        const u32x4* ep = Esp + (size_t)(kb * NCB + CB0) * 3 * 64 + lane;
+#pragma unroll
+        for (int cb = 0; cb < NC; ++cb)
+#pragma unroll
+            for (int sp = 0; sp < 3; ++sp) e[cb][sp] = ep[(3 * cb + sp) * 64];
+    }
+};
+
 template <int NC, int CB0, int NCB, int KBS>
 __device__ __forceinline__ void xb_project(const u32x4* Xo, const u32x4* Wsp, float* Sq, int nkb, int kb0, int pb,
                                            int lane) {
@@ -1343,19 +1441,32 @@ __device__ __forceinline__ void xb_project(const u32x4* Xo, const u32x4* Wsp, fl
     f4 s[NC], s2[NC];
 #pragma unroll
     for (int cb = 0; cb < NC; ++cb) s[cb] = s2[cb] = f4{0.f, 0.f, 0.f, 0.f};
-    for (int kb = kb0; kb < nkb; kb += KBS) {
-        const u32x4 b = Xo[(4 * kb + kg) * 64 + 16 * pb + m];
-        const u32x4* wp = Wsp + (size_t)(kb * NCB + CB0) * 3 * 64 + lane;
+    auto mma = [&](const XbOps<NC>& o) {
 #pragma unroll
         for (int cb = 0; cb < NC; ++cb) {
             // with one column block the middle term goes to a second chain
-            s[cb] = mfma16_bf16(wp[(3 * cb) * 64], b, s[cb]);
+            s[cb] = mfma16_bf16(o.e[cb][0], o.b, s[cb]);
             if (NC == 1)
-                s2[cb] = mfma16_bf16(wp[(3 * cb + 1) * 64], b, s2[cb]);
+                s2[cb] = mfma16_bf16(o.e[cb][1], o.b, s2[cb]);
             else
-                s[cb] = mfma16_bf16(wp[(3 * cb + 1) * 64], b, s[cb]);
-            s[cb] = mfma16_bf16(wp[(3 * cb + 2) * 64], b, s[cb]);
+                s[cb] = mfma16_bf16(o.e[cb][1], o.b, s[cb]);
+            s[cb] = mfma16_bf16(o.e[cb][2], o.b, s[cb]);
         }
+    };
+    // software pipeline over k blocks with two operand sets (the next
+    // block's LDS reads are in flight while the current block's MFMAs run);
+    // no branch in the loop body
+    if (kb0 < nkb) {
+        XbOps<NC> o0, o1;
+        o0.template load<CB0, NCB>(Xo, Wsp, kb0, pb, lane);
+        int kb = kb0;
+        for (; kb + KBS < nkb; kb += 2 * KBS) {
+            o1.template load<CB0, NCB>(Xo, Wsp, kb + KBS, pb, lane);
+            mma(o0);
+            o0.template load<CB0, NCB>(Xo, Wsp, (kb + 2 * KBS < nkb) ? kb + 2 * KBS : kb, pb, lane);
+            mma(o1);
+        }
+        if (kb < nkb) mma(o0);
     }
 #pragma unroll
     for (int cb = 0; cb < NC; ++cb) {
@@ -1366,9 +1477,9 @@ __device__ __forceinline__ void xb_project(const u32x4* Xo, const u32x4* Wsp, fl
 }
 
 // V += X_tile Wt on the bf16 matrix cores, folded into the float64 running
-// sums like mfma_accumulate (with SCALE): the running sums of column q are
+// sums like mfma_accumulate; with SCALE the running sums of column q are
 // multiplied by F[q], the tile's by G[q].
-template <int NCB, int NRBW, int NW>
+template <int NCB, int NRBW, int NW, bool SCALE = true>
 __device__ __forceinline__ void xb_accumulate(d4 (&acc)[NRBW][NCB], const uint16_t* Xn, const u32x4* Wb,
                                               const float* F, const float* G, int nrb, int w, int lane) {
     const int m = lane & 15, kg = lane >> 4;
@@ -1377,30 +1488,45 @@ __device__ __forceinline__ void xb_accumulate(d4 (&acc)[NRBW][NCB], const uint16
     for (int j = 0; j < NRBW; ++j)
 #pragma unroll
         for (int cb = 0; cb < NCB; ++cb) t[j][cb] = f4{0.f, 0.f, 0.f, 0.f};
+    // the operand reads of PK pixel blocks are issued before their first
+    // MFMA (both blocks at once up to three column blocks: one LDS latency
+    // per tile); rows past the last block re-read the last one
+    constexpr int PK = NCB <= 3 ? 2 : 1;
 #pragma unroll
-    for (int pkb = 0; pkb < 2; ++pkb) {
-        u32x4 bop[NCB][3];
+    for (int p0 = 0; p0 < 2; p0 += PK) {
+        u32x4 bop[PK][NCB][3], xa[NRBW][PK];
 #pragma unroll
-        for (int cb = 0; cb < NCB; ++cb)
+        for (int pk = 0; pk < PK; ++pk)
 #pragma unroll
-            for (int sp = 0; sp < 3; ++sp) bop[cb][sp] = Wb[((pkb * NCB + cb) * 3 + sp) * 64 + lane];
+            for (int cb = 0; cb < NCB; ++cb)
+#pragma unroll
+                for (int sp = 0; sp < 3; ++sp) bop[pk][cb][sp] = Wb[(((p0 + pk) * NCB + cb) * 3 + sp) * 64 + lane];
+#pragma unroll
+        for (int j = 0; j < NRBW; ++j)
+#pragma unroll
+            for (int pk = 0; pk < PK; ++pk)
+                xa[j][pk] =
+                    *(const u32x4*)(Xn + (16 * min(w + NW * j, nrb - 1) + m) * kXNP + 32 * (p0 + pk) + 8 * kg);
 #pragma unroll
         for (int j = 0; j < NRBW; ++j) {
-            const int rb = w + NW * j;
-            if (rb < nrb) {
-                const u32x4 a = *(const u32x4*)(Xn + (16 * rb + m) * kXNP + 32 * pkb + 8 * kg);
+            if (w + NW * j < nrb) {
 #pragma unroll
-                for (int sp = 0; sp < 3; ++sp)
+                for (int pk = 0; pk < PK; ++pk)
 #pragma unroll
-                    for (int cb = 0; cb < NCB; ++cb) t[j][cb] = mfma16_bf16(a, bop[cb][sp], t[j][cb]);
+                    for (int sp = 0; sp < 3; ++sp)
+#pragma unroll
+                        for (int cb = 0; cb < NCB; ++cb)
+                            t[j][cb] = mfma16_bf16(xa[j][pk], bop[pk][cb][sp], t[j][cb]);
             }
         }
     }
     float fs[NCB], gs[NCB];
+    if (SCALE) {
 #pragma unroll
-    for (int cb = 0; cb < NCB; ++cb) {
-        fs[cb] = F[16 * cb + m];
-        gs[cb] = G[16 * cb + m];
+        for (int cb = 0; cb < NCB; ++cb) {
+            fs[cb] = F[16 * cb + m];
+            gs[cb] = G[16 * cb + m];
+        }
     }
 #pragma unroll
     for (int j = 0; j < NRBW; ++j)
@@ -1409,7 +1535,8 @@ __device__ __forceinline__ void xb_accumulate(d4 (&acc)[NRBW][NCB], const uint16
             for (int cb = 0; cb < NCB; ++cb)
 #pragma unroll
                 for (int v = 0; v < 4; ++v)
-                    acc[j][cb][v] = fma(acc[j][cb][v], (double)fs[cb], (double)t[j][cb][v] * (double)gs[cb]);
+                    acc[j][cb][v] = SCALE ? fma(acc[j][cb][v], (double)fs[cb], (double)t[j][cb][v] * (double)gs[cb])
+                                          : acc[j][cb][v] + (double)t[j][cb][v];
 }
 
 template <int PP, int R, bool STEP>
@@ -1478,41 +1605,7 @@ __device__ __forceinline__ void bpass_xb_body(const Geom& g, const State& s, int
 #pragma unroll
         for (int cb = 0; cb < NCB; ++cb) acc[jb][cb] = d4{0.0, 0.0, 0.0, 0.0};
 
-    // X staging registers of this wave's band block
-    const bool xw = 32 * w < L;
-    uint2 xv[8];
-    auto x_issue = [&](int tile) {
-        if (xw) {
-            const uint16_t* src = (const uint16_t*)s.X + (size_t)tile * kTile + 4 * m;
-#pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                const int row = min(32 * w + 8 * kg + j, L - 1);
-                xv[j] = *(const uint2*)(src + (size_t)row * s.ldx);
-            }
-        }
-    };
-    auto x_store = [&]() {
-        if (xw) {
-            uint2 v[8];
-#pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                const int row = 32 * w + 8 * kg + j;
-                v[j] = row < L ? xv[j] : make_uint2(0u, 0u);
-                *(uint2*)(Xn + row * kXNP + 4 * m) = v[j];
-            }
-            // pixel 4 m + u: element j of its 16 bytes is band 32 w + 8 kg + j
-            u32x4* dst = Xo + (4 * w + kg) * 64 + 4 * m;
-            dst[0] = u32x4{__builtin_amdgcn_perm(v[1].x, v[0].x, 0x05040100u), __builtin_amdgcn_perm(v[3].x, v[2].x, 0x05040100u),
-                           __builtin_amdgcn_perm(v[5].x, v[4].x, 0x05040100u), __builtin_amdgcn_perm(v[7].x, v[6].x, 0x05040100u)};
-            dst[1] = u32x4{__builtin_amdgcn_perm(v[1].x, v[0].x, 0x07060302u), __builtin_amdgcn_perm(v[3].x, v[2].x, 0x07060302u),
-                           __builtin_amdgcn_perm(v[5].x, v[4].x, 0x07060302u), __builtin_amdgcn_perm(v[7].x, v[6].x, 0x07060302u)};
-            dst[2] = u32x4{__builtin_amdgcn_perm(v[1].y, v[0].y, 0x05040100u), __builtin_amdgcn_perm(v[3].y, v[2].y, 0x05040100u),
-                           __builtin_amdgcn_perm(v[5].y, v[4].y, 0x05040100u), __builtin_amdgcn_perm(v[7].y, v[6].y, 0x05040100u)};
-            dst[3] = u32x4{__builtin_amdgcn_perm(v[1].y, v[0].y, 0x07060302u), __builtin_amdgcn_perm(v[3].y, v[2].y, 0x07060302u),
-                           __builtin_amdgcn_perm(v[5].y, v[4].y, 0x07060302u), __builtin_amdgcn_perm(v[7].y, v[6].y, 0x07060302u)};
-        }
-    };
-
+    XbStage<NW> xs;
     f4 bn[SV];
     float tn = 0.f;
     auto load_b = [&](int tile) {
@@ -1525,8 +1618,8 @@ __device__ __forceinline__ void bpass_xb_body(const Geom& g, const State& s, int
     };
     __syncthreads();
     if (pg < g.ntiles) {
-        x_issue(pg);
-        x_store();
+        xs.issue(s.X, s.ldx, L, pg);
+        xs.store(Xn, Xo, L);
         load_b(pg);
     }
     for (int tile = pg; tile < g.ntiles; tile += g.npg) {
@@ -1539,7 +1632,7 @@ __device__ __forceinline__ void bpass_xb_body(const Geom& g, const State& s, int
         const int nt = tile + g.npg;
         if (nt < g.ntiles) {
             load_b(nt);
-            x_issue(nt);
+            xs.issue(s.X, s.ldx, L, nt);
         }
 
         if (STEP) {
@@ -1619,7 +1712,7 @@ __device__ __forceinline__ void bpass_xb_body(const Geom& g, const State& s, int
         xb_accumulate<NCB, NRBW, NW>(acc, Xn, Wb, F, FG, nrb, w, lane);
         if (nt < g.ntiles) {
             lds_barrier();                         // every wave is done with this tile's X
-            x_store();
+            xs.store(Xn, Xo, L);
         }
     }
 
@@ -1635,6 +1728,399 @@ template <int PP, int R, bool STEP>
 __global__ __launch_bounds__(64 * kBpassWaves, 1) void k_bpass_xb(Geom g, State s, const float* __restrict__ W,
                                                                   int mode, RunInit ri) {
     bpass_xb_body<PP, R, STEP>(g, s, blockIdx.x, W, mode, ri);
+}
+
+// --------------------------------------------------------------------------
+// A-pass for bf16 X on the bf16 matrix cores: the same pass as apass_body
+// (objective at the incoming state, K1 A-steps per pixel and run, X A^T and
+// A A^T partials), with the X tile kept in bf16 (XbStage) and
+//   * the projection P = E^T x on v_mfma_f32_16x16x32_bf16, E in three bf16
+//     terms (exact, so each product is exact): each block of 32 bands is
+//     summed in float32 by the matrix core and folded into float64, and P is
+//     kept as a float pair (high, low) as in mfma_project_f64; the float32
+//     rounding inside a block is unbiased and independent from pixel to pixel,
+//     so it averages out of the objective's sum over pixels;
+//   * X A^T on the bf16 matrix cores with the abundances in three bf16 terms
+//     (xb_accumulate);
+//   * A A^T on the float32 matrix cores from the float32 abundances, as in
+//     apass_body (mfma_gram).
+// --------------------------------------------------------------------------
+template <int NC, int CB0, int NCB, int WTS>
+__device__ __forceinline__ double xa_project(const u32x4* Xo, const u32x4* Esp, float* Phi, float* Plo, int nkb,
+                                             int pb, int lane) {
+    const int m = lane & 15, kg = lane >> 4;
+    d4 s[NC];
+    f4 tp[NC];
+#pragma unroll
+    for (int cb = 0; cb < NC; ++cb) {
+        s[cb] = d4{0.0, 0.0, 0.0, 0.0};
+        tp[cb] = f4{0.f, 0.f, 0.f, 0.f};
+    }
+    double xx = 0.0;
+    auto step = [&](const XbOps<NC>& o) {
+        f4 t[NC];
+#pragma unroll
+        for (int cb = 0; cb < NC; ++cb) {
+            t[cb] = mfma16_bf16(o.e[cb][0], o.b, f4{0.f, 0.f, 0.f, 0.f});
+            t[cb] = mfma16_bf16(o.e[cb][1], o.b, t[cb]);
+            t[cb] = mfma16_bf16(o.e[cb][2], o.b, t[cb]);
+        }
+        // while those run: this lane's 8 bands of ||x||^2 and the fold of
+        // the previous block
+        const bf16x8 bv = __builtin_bit_cast(bf16x8, o.b);
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const double x = (double)(float)bv[j];
+            xx = fma(x, x, xx);
+        }
+#pragma unroll
+        for (int cb = 0; cb < NC; ++cb) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) s[cb][v] += (double)tp[cb][v];
+            tp[cb] = t[cb];
+        }
+    };
+    // software pipeline as in xb_project
+    XbOps<NC> o0, o1;
+    o0.template load<CB0, NCB>(Xo, Esp, 0, pb, lane);
+    int kb = 0;
+    for (; kb + 1 < nkb; kb += 2) {
+        o1.template load<CB0, NCB>(Xo, Esp, kb + 1, pb, lane);
+        step(o0);
+        o0.template load<CB0, NCB>(Xo, Esp, (kb + 2 < nkb) ? kb + 2 : kb, pb, lane);
+        step(o1);
+    }
+    if (kb < nkb) step(o0);
+#pragma unroll
+    for (int cb = 0; cb < NC; ++cb)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const double P = s[cb][v] + (double)tp[cb][v];
+            const float hi = (float)P;
+            const int idx = (16 * pb + m) * WTS + 16 * (CB0 + cb) + 4 * kg + v;
+            Phi[idx] = hi;
+            Plo[idx] = (float)(P - (double)hi);
+        }
+    return xx;
+}
+
+// A A^T blocks (qb, qb) and (qb, qb + 1) of the tile on the float32 matrix
+// cores, from the abundances Wt [64][WTS], folded into float64 (the Gram part
+// of mfma_accumulate).
+template <int NCB, int NGBW, int WTS, int NW>
+__device__ __forceinline__ void mfma_gram(d4 (&gram)[NGBW], const float* Wt, int w, int lane) {
+    const int m = lane & 15, kk = lane >> 4;
+#pragma unroll
+    for (int gi = 0; gi < NGBW; ++gi) {
+        const int gb = w + NW * gi;
+        if (gb < 2 * NCB - 1) {
+            const int q1 = gb >> 1, q2 = q1 + (gb & 1);
+            f4 tg = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int k = 0; k < 16; ++k)
+                tg = mfma16(Wt[(4 * k + kk) * WTS + 16 * q1 + m], Wt[(4 * k + kk) * WTS + 16 * q2 + m], tg);
+#pragma unroll
+            for (int v = 0; v < 4; ++v) gram[gi][v] += (double)tg[v];
+        }
+    }
+}
+
+template <int PP, int R>
+__device__ __forceinline__ void apass_xb_body(const Geom& g, const State& s, int bid, const float* __restrict__ E,
+                                              int K1) {
+    using S = Shape<PP, R>;
+    constexpr int NW = xa_waves(PP), NT = 64 * NW;
+    constexpr int QC = S::QC, QCP = S::QCP, NCB = S::NCB, WTS = S::WTS;
+    constexpr int RW = (R + NW - 1) / NW;
+    // A-step layout as in apass_body; without the float64 projection the
+    // eight-wave kernels up to p = 4 also have the registers to spread 2 or 4
+    // runs over lane pairs or quads
+    constexpr int SPL = (R < NW && (R == 1 || NW == 4 || PP <= 4)) ? (NW / R < 4 ? NW / R : 4) : 1;
+    constexpr bool SPLIT = SPL > 1;
+    constexpr int JW = (PP + SPL - 1) / SPL;
+    static_assert(!SPLIT || NW % R == 0, "runs per chunk must divide the waves");
+    constexpr int NRBW = S::NRBW * 4 / NW;
+    constexpr int NGBW = (S::NGB + NW - 1) / NW;
+    constexpr int NC0 = (NW == 8) ? (NCB + 1) / 2 : NCB, NC1 = NCB - NC0;
+    extern __shared__ float smem[];
+    char* const lds = (char*)smem;
+    const int L = g.L, N = g.N, nkb = (L + 31) >> 5, nrb = (L + 15) >> 4;
+    const bool gfx = (size_t)xa_lds(PP, R, L, 1).total <= kMaxLdsBytes;   // room for the float Gram copy
+    const XaLds lo = xa_lds(PP, R, L, gfx ? 1 : 0);
+    uint16_t* Xn = (uint16_t*)(lds + lo.xn);
+    u32x4* Xo = (u32x4*)(lds + lo.xo);
+    u32x4* Esp = (u32x4*)(lds + lo.esp);
+    float* Wt = (float*)(lds + lo.wt);
+    float* Plo = (float*)(lds + lo.plo);
+    u32x4* Wb = (u32x4*)(lds + lo.plo);
+    double* Gd = (double*)(lds + lo.gs);
+    float* Gf = (float*)(lds + lo.gf);
+    double* XX = (double*)(lds + lo.xx);
+
+    int pg, c;
+    wg_coords(g, bid, pg, c);
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int w = uniform_int(tid >> 6);
+    const int col0 = c * QC;
+    float* __restrict__ A = s.A;
+
+    // E[:, chunk] as MFMA A operands (three bf16 terms), and the Gram
+    // matrices in float64 from the float32 E
+    for (int e = tid; e < nkb * NCB * 64; e += NT) {
+        const int ln = e & 63, kc = e >> 6;
+        const int q = 16 * (kc % NCB) + (ln & 15), r0 = 32 * (kc / NCB) + 8 * (ln >> 4);
+        float x[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) x[j] = (r0 + j < L && q < QC) ? E[(size_t)(r0 + j) * g.Qp + col0 + q] : 0.f;
+        u32x4 h, md, lw;
+        split_bf16x3(x, h, md, lw);
+        Esp[(kc * 3 + 0) * 64 + ln] = h;
+        Esp[(kc * 3 + 1) * 64 + ln] = md;
+        Esp[(kc * 3 + 2) * 64 + ln] = lw;
+    }
+    for (int e0 = tid / 8; e0 < R * PP * PP; e0 += NT / 8) {
+        const int sub = tid % 8;
+        const int r = e0 / (PP * PP), jk = e0 % (PP * PP), j = jk / PP, k = jk % PP;
+        const float* Ek = E + col0 + r * PP;
+        double acc = 0.0;
+        for (int l = sub; l < L; l += 8) acc = fma((double)Ek[(size_t)l * g.Qp + j], (double)Ek[(size_t)l * g.Qp + k], acc);
+        acc += __shfl_xor(acc, 1);
+        acc += __shfl_xor(acc, 2);
+        acc += __shfl_xor(acc, 4);
+        if (sub == 0) {
+            Gd[e0] = acc;
+            if (gfx) Gf[e0] = (float)acc;
+        }
+    }
+    // the weight padding columns (never written later)
+    for (int e = tid; e < kTile * WTS; e += NT) Wt[e] = 0.f;
+    __syncthreads();
+
+    d4 acc[NRBW][NCB], gram[NGBW];
+#pragma unroll
+    for (int j = 0; j < NRBW; ++j)
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb) acc[j][cb] = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int j = 0; j < NGBW; ++j) gram[j] = d4{0.0, 0.0, 0.0, 0.0};
+    double lacc[RW];
+#pragma unroll
+    for (int r = 0; r < RW; ++r) lacc[r] = 0.0;
+    const int sr = SPLIT ? tid / (64 * SPL) : 0, si = SPLIT ? (tid / SPL) % 64 : lane, ss = SPLIT ? tid % SPL : 0;
+    const bool sact = !SPLIT || sr < R;
+    float Gfr[JW][PP];
+    if constexpr (SPLIT) {
+#pragma unroll
+        for (int jj = 0; jj < JW; ++jj)
+#pragma unroll
+            for (int kk = 0; kk < PP; ++kk) {
+                const int j = ss + SPL * jj;
+                Gfr[jj][kk] = (sact && j < PP) ? (float)Gd[min(sr, R - 1) * PP * PP + j * PP + kk] : 0.f;
+            }
+    }
+
+    XbStage<NW> xs;
+    float an[RW][PP];
+    float ano[JW];
+    auto load_a = [&](int tile) {
+        if constexpr (SPLIT) {
+            const size_t pixc = (size_t)min(tile * kTile + si, N - 1);
+            const int m = min(c * R + min(sr, R - 1), g.M - 1);
+#pragma unroll
+            for (int j = 0; j < PP; ++j) an[0][j] = A[(size_t)(m * PP + j) * N + pixc];
+#pragma unroll
+            for (int jj = 0; jj < JW; ++jj) ano[jj] = A[(size_t)(m * PP + min(ss + SPL * jj, PP - 1)) * N + pixc];
+        } else {
+            const size_t pixc = (size_t)min(tile * kTile + lane, N - 1);
+#pragma unroll
+            for (int k = 0; k < RW; ++k) {
+                const int m = c * R + min(w + NW * k, R - 1);
+#pragma unroll
+                for (int j = 0; j < PP; ++j) an[k][j] = A[(size_t)(min(m, g.M - 1) * PP + j) * N + pixc];
+            }
+        }
+    };
+    if (pg < g.ntiles) {
+        xs.issue(s.X, s.ldx, L, pg);
+        xs.store(Xn, Xo, L);
+        load_a(pg);
+    }
+    for (int tile = pg; tile < g.ntiles; tile += g.npg) {
+        __builtin_amdgcn_s_waitcnt(0);
+        lds_barrier();
+        const int pix = tile * kTile + si;
+        const bool pok = pix < N;
+        float a[RW][PP];
+        float ao[JW];
+        if constexpr (SPLIT) {
+            const bool ok = sact && c * R + sr < g.M && pok;
+#pragma unroll
+            for (int j = 0; j < PP; ++j) a[0][j] = ok ? an[0][j] : 0.f;
+#pragma unroll
+            for (int jj = 0; jj < JW; ++jj) ao[jj] = (ok && ss + SPL * jj < PP) ? ano[jj] : 0.f;
+        } else {
+#pragma unroll
+            for (int k = 0; k < RW; ++k) {
+                const int m = c * R + w + NW * k;
+                const bool mok = m < g.M && w + NW * k < R;
+#pragma unroll
+                for (int j = 0; j < PP; ++j) a[k][j] = (mok && pok) ? an[k][j] : 0.f;
+            }
+        }
+        const int nt = tile + g.npg;
+        if (nt < g.ntiles) {
+            load_a(nt);
+            xs.issue(s.X, s.ldx, L, nt);
+        }
+        // projection: P for pixels 16w..16w+15 (16 (w - 4).. with eight
+        // waves, w >= 4, which take the last NC1 column blocks)
+        if (w < 4) {
+            double xx = xa_project<NC0, 0, NCB, WTS>(Xo, Esp, Wt, Plo, nkb, w, lane);
+            xx += __shfl_xor(xx, 16);
+            xx += __shfl_xor(xx, 32);
+            if (lane < 16) XX[16 * w + lane] = xx;
+        } else if constexpr (NC1 > 0) {
+            (void)xa_project<NC1, NC0, NCB, WTS>(Xo, Esp, Wt, Plo, nkb, w - 4, lane);
+        }
+        lds_barrier();
+        if constexpr (SPLIT) {
+            const int m = c * R + sr;
+            const bool ok = sact && m < g.M && pok;
+            if (sact) {
+                float Po[JW];
+                double q = 0.0;
+#pragma unroll
+                for (int jj = 0; jj < JW; ++jj) {
+                    const int j = ss + SPL * jj;
+                    const int jc = min(j, PP - 1);
+                    Po[jj] = j < PP ? Wt[si * WTS + sr * PP + jc] : 0.f;
+                    const double* Gj = Gd + sr * PP * PP + jc * PP;
+                    double ga = 0.0;
+#pragma unroll
+                    for (int kk = 0; kk < PP; ++kk) ga = fma(Gj[kk], (double)a[0][kk], ga);
+                    const double pj = (double)Po[jj] + (double)(j < PP ? Plo[si * WTS + sr * PP + jc] : 0.f);
+                    q = fma((double)ao[jj], ga - 2.0 * pj, q);
+                }
+                q = group_sum<SPL>(q);
+                if (ok && ss == 0) lacc[0] += XX[si] + q;
+                if (m < g.M) a_steps_split<PP, SPL>(a[0], ao, Po, Gfr, s.eta[2 * m], K1, ss);
+#pragma unroll
+                for (int jj = 0; jj < JW; ++jj) {
+                    const int j = ss + SPL * jj;
+                    if (j < PP) {
+                        if (ok) A[(size_t)(m * PP + j) * N + pix] = ao[jj];
+                        Wt[si * WTS + sr * PP + j] = ok ? ao[jj] : 0.f;
+                    }
+                }
+            }
+        } else {
+            const double xnorm = XX[lane];
+#pragma unroll
+            for (int k = 0; k < RW; ++k) {
+                const int r = w + NW * k, m = c * R + r;
+                if (r >= R) continue;
+                const bool mok = m < g.M;
+                float P[PP];
+#pragma unroll
+                for (int j = 0; j < PP; ++j) P[j] = Wt[lane * WTS + r * PP + j];
+                const double* Gr = Gd + r * PP * PP;
+                if (mok && pok) {
+                    double q = xnorm;
+#pragma unroll
+                    for (int j = 0; j < PP; ++j) {
+                        double ga = 0.0;
+#pragma unroll
+                        for (int kk = 0; kk < PP; ++kk) ga = fma(Gr[j * PP + kk], (double)a[k][kk], ga);
+                        const double pj = (double)P[j] + (double)Plo[lane * WTS + r * PP + j];
+                        q = fma((double)a[k][j], ga - 2.0 * pj, q);
+                    }
+                    lacc[k] += q;
+                }
+                if (mok) {
+                    if (gfx)
+                        a_steps<PP>(a[k], P, Gf + r * PP * PP, s.eta[2 * m], K1);
+                    else
+                        a_steps<PP>(a[k], P, Gr, s.eta[2 * m], K1);
+                }
+#pragma unroll
+                for (int j = 0; j < PP; ++j) {
+                    if (mok && pok) A[(size_t)(m * PP + j) * N + pix] = a[k][j];
+                    Wt[lane * WTS + r * PP + j] = (mok && pok) ? a[k][j] : 0.f;
+                }
+            }
+        }
+        lds_barrier();
+        // the new abundances as MFMA B operands (over the low parts of P,
+        // which the A-steps have consumed): entry (pkb, cb, lane) holds
+        // pixels 32 pkb + 8 (lane / 16) + j of column 16 cb + lane % 16
+        for (int e = tid; e < 2 * NCB * 64; e += NT) {
+            const int ln = e & 63, pc = e >> 6;
+            const int q = 16 * (pc % NCB) + (ln & 15), p0 = 32 * (pc / NCB) + 8 * (ln >> 4);
+            float x[8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) x[j] = Wt[(p0 + j) * WTS + q];
+            u32x4 h, md, lw;
+            split_bf16x3(x, h, md, lw);
+            Wb[(pc * 3 + 0) * 64 + ln] = h;
+            Wb[(pc * 3 + 1) * 64 + ln] = md;
+            Wb[(pc * 3 + 2) * 64 + ln] = lw;
+        }
+        lds_barrier();
+        xb_accumulate<NCB, NRBW, NW, false>(acc, Xn, Wb, nullptr, nullptr, nrb, w, lane);
+        mfma_gram<NCB, NGBW, WTS, NW>(gram, Wt, w, lane);
+        if (nt < g.ntiles) {
+            lds_barrier();                         // every wave is done with this tile's X and weights
+            xs.store(Xn, Xo, L);
+        }
+    }
+
+    const size_t wgi = (size_t)pg * g.nqc + c;
+    store_acc<NCB, NRBW, QC, NW>(acc, s.Vpart + wgi * (size_t)L * QC, L, nrb, w, lane);
+    {
+        const int m16 = lane & 15, kk = lane >> 4;
+        float* AAp = s.AApart + wgi * (size_t)(R * PP * PP);
+#pragma unroll
+        for (int gi = 0; gi < NGBW; ++gi) {
+            const int gb = w + NW * gi;
+            if (gb < 2 * NCB - 1) {
+                const int qb1 = gb >> 1, qb2 = qb1 + (gb & 1);
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int q1 = 16 * qb1 + 4 * kk + v, q2 = 16 * qb2 + m16;
+                    if (q1 < QC && q2 < QC && q1 / PP == q2 / PP) {
+                        const int r = q1 / PP, j = q1 % PP, k = q2 % PP;
+                        AAp[r * PP * PP + j * PP + k] = (float)gram[gi][v];
+                        if (qb1 != qb2) AAp[r * PP * PP + k * PP + j] = (float)gram[gi][v];
+                    }
+                }
+            }
+        }
+    }
+    if constexpr (SPLIT) {
+        const double tot = wave_sum(lacc[0]);
+        __syncthreads();
+        if (lane == 0) XX[w] = tot;
+        __syncthreads();
+        if (tid < R) {
+            double t = 0.0;
+            for (int w2 = tid * SPL; w2 < (tid + 1) * SPL; ++w2) t += XX[w2];
+            if (c * R + tid < g.M) s.lpart[(size_t)pg * g.M + c * R + tid] = t;
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < RW; ++k) {
+            const int r = w + NW * k, m = c * R + r;
+            if (r >= R) continue;
+            const double tot = wave_sum(lacc[k]);
+            if (lane == 0 && m < g.M) s.lpart[(size_t)pg * g.M + m] = tot;
+        }
+    }
+}
+
+template <int PP, int R>
+__global__ __launch_bounds__(64 * xa_waves(PP), 1) void k_apass_xb(Geom g, State s, const float* __restrict__ E,
+                                                                      int K1) {
+    apass_xb_body<PP, R>(g, s, blockIdx.x, E, K1);
 }
 
 // --------------------------------------------------------------------------

@@ -17,6 +17,16 @@ static_assert(PP >= 1 && PP <= kMaxP, "EDAA_INST_P out of range");
 template <int R>
 struct Kernels {
     static hipError_t apass(const Geom& g, const State& s, int K1, hipStream_t st) {
+        if constexpr (PP <= 12) {          // xa_fits: the bf16 A-pass up to p = 12
+            if (s.x_mfma & 2) {
+                const bool gf = (size_t)xa_lds(PP, R, g.L, 1).total <= kMaxLdsBytes;
+                const size_t lds = xa_lds(PP, R, g.L, gf ? 1 : 0).total;
+                set_max_lds((const void*)k_apass_xb<PP, R>, (int)lds);
+                hipLaunchKernelGGL((k_apass_xb<PP, R>), dim3(g.npg * g.nqc), dim3(64 * xa_waves(PP)), lds, st, g,
+                                   s, (const float*)s.E, K1);
+                return hipGetLastError();
+            }
+        }
         const size_t lds = (size_t)pass_lds(PP, R, g.L, g.dbuf, g.ecs, g.gf).total * sizeof(float);
         set_max_lds((const void*)k_apass<PP, R>, (int)lds);
         hipLaunchKernelGGL((k_apass<PP, R>), dim3(g.npg * g.nqc), dim3(64 * apass_waves(PP)), lds, st, g, s,
@@ -24,7 +34,7 @@ struct Kernels {
         return hipGetLastError();
     }
     static hipError_t bpass(const Geom& g, const State& s, int mode, const RunInit& ri, hipStream_t st) {
-        if (s.x_mfma) {
+        if (s.x_mfma & 1) {
             const size_t lds = xb_lds(PP, R, g.L).total;
             if (mode == kModeStep) {
                 set_max_lds((const void*)k_bpass_xb<PP, R, true>, (int)lds);

@@ -82,7 +82,7 @@ struct State {
     const void* X;      // [L][ldx] padded copy of the caller's X (float32 or bf16 bits), pixels >= N zero
     size_t ldx;         // ntiles * 64
     int x_bf16;
-    int x_mfma;         // bf16 X: the B-pass contractions run on the bf16 matrix cores
+    int x_mfma;         // bf16 X on the bf16 matrix cores: bit 0 the B-pass, bit 1 the A-pass
     float* A;           // [Q][N] abundances (the caller's A_all)
     float* Bst;         // [Q][ntiles * 64] unnormalised pixel weights (pixels >= N: zero)
     float* tshift;      // [ntiles][Qp] shift used when a tile of Bst was written
@@ -272,9 +272,11 @@ constexpr size_t kMaxLdsBytes = 160 * 1024;
 // Whether chunks of R runs have compiled kernels that fit L bands (LDS of all
 // three pass kernels and the accumulators' band capacity).
 bool runs_fit(int p, int R, int L);
-// Whether the B-pass of a chunk of R runs can keep bf16 X tiles in bf16 and
-// run on the bf16 matrix cores (L and LDS limits).
+// Whether the B-pass (xb_fits) or the A-pass (xa_fits) of a chunk of R runs
+// can keep bf16 X tiles in bf16 and run on the bf16 matrix cores (L and LDS
+// limits).
 bool xb_fits(int p, int R, int L);
+bool xa_fits(int p, int R, int L);
 // Default runs per chunk for M runs (1 when M = 1 or when nothing else fits).
 int runs_per_chunk(int p, int M, int L);
 // Geometry with R runs per chunk and npg pixel groups (0: defaults).

@@ -104,6 +104,12 @@ bool xb_fits(int p, int R, int L) {
     return L <= kXbMaxL && (size_t)xb_lds(p, R, L).total <= kMaxLdsBytes;
 }
 
+// (above p = 12 the bf16 A-pass kernels spill registers to scratch: the
+// float64 A-pass serves those)
+bool xa_fits(int p, int R, int L) {
+    return p <= 12 && L <= kXbMaxL && (size_t)xa_lds(p, R, L, 0).total <= kMaxLdsBytes;
+}
+
 bool runs_fit(int p, int R, int L) {
     if (!has_runs(p, R) || L > max_bands(p, R)) return false;
     for (int kind = 0; kind < 3; ++kind)

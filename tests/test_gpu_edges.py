@@ -118,13 +118,17 @@ def test_ragged_bf16_equals_single_fits(api):
     (256, 700, 16, 2, 5),    # the largest L of the bf16 matrix path, two column blocks
     (1, 100, 2, 1, 6),       # a single band: one k block of 32 with 31 zero bands
     (30, 50, 3, 10, 5),      # fewer pixels than one tile, 20 runs per chunk (four column blocks)
+    (120, 800, 4, 4, 5),     # four runs per chunk, A-steps of a run spread over lane pairs
+    (96, 500, 9, 4, 5),      # four runs per chunk at p = 9
+    (224, 3000, 12, 1, 5),   # one run at the large scene's (L, p): A-steps over lane quads
 ])
 def test_bf16_matrix_path_vs_oracle(api, L, N, p, M, T):
-    """bf16 X on the bf16 matrix cores (the default for bf16 X) against the
-    oracle run on the same bf16 values, at the float32 gates; and against
-    the float32-matrix-core path (bf16_widen), which computes the same
-    products in float32: the two must agree to float32 rounding but not be
-    identical (a check that the bf16 path ran)."""
+    """bf16 X on the bf16 matrix cores (the default for bf16 X: both passes
+    up to p = 12 and L = 256, the B-pass above p = 12) against the oracle run
+    on the same bf16 values, at the float32 gates; and against the
+    float32-matrix-core path (bf16_widen), which computes the same products
+    in float32: the two must agree to float32 rounding but not be identical
+    (a check that the bf16 path ran)."""
     _say(f"bf16 matrix path L={L} N={N} p={p} M={M} T={T}")
     # L = 1 checks the 31 zero bands of the k block on the all-positive
     # single-band scene of test_edge_shapes_vs_oracle (seed 41).  With mixed
