@@ -85,8 +85,9 @@ def profile_run(T, workload, shape=None):
     calibration of FETCH_SIZE / WRITE_SIZE) and then T outer iterations of
     'urban_ensemble' (the headline ensemble, at the launch shape `shape` if
     given), 'urban_single' (one run on the same scene), 'large_single' (one
-    run on the L=224, N=512x614, p=12 scene, float32 X) or 'ragged' (the
-    64-image ragged batch, persistent kernel)."""
+    run on the L=224, N=512x614, p=12 scene, float32 X), 'large_bf16' (the
+    M=20 ensemble on that scene with bf16 X, bf16 matrix-core passes) or
+    'ragged' (the 64-image ragged batch, persistent kernel)."""
     import torch
     from paper_2209_11002_amd import api, synth
     dev = torch.device("cuda:0")
@@ -105,14 +106,17 @@ def profile_run(T, workload, shape=None):
         torch.cuda.synchronize()
         log(f"profile run done ({workload}, T={T})")
         return
-    if workload == "large_single":
+    if workload in ("large_single", "large_bf16"):
         scene, cfg = synth.large_smooth()
         p = 12
     else:
         scene, cfg = synth.urban_ensemble()
         p = 6
-    X = api.normalize_pixels(torch.from_numpy(scene.X).to(dev))
-    if workload == "urban_ensemble":
+    X = api.normalize_pixels(torch.from_numpy(scene.X).to(dev),
+                             out_dtype=torch.bfloat16 if workload == "large_bf16" else torch.float32)
+    if workload == "large_bf16":
+        api.ensemble(X, p, cfg["seeds"], cfg["gammas"], T=T, K1=cfg["K1"], K2=cfg["K2"])
+    elif workload == "urban_ensemble":
         R, npg = shape if shape else (0, 0)
         api.ensemble(X, p, cfg["seeds"], cfg["gammas"], T=T, K1=cfg["K1"], K2=cfg["K2"], runs_per_chunk=R,
                      pixel_groups=npg)
@@ -409,7 +413,7 @@ def main():
     ap.add_argument("--profile-run", type=int, default=0, metavar="T",
                     help="run a counter-profiling workload with T outer iterations and exit")
     ap.add_argument("--profile-workload", default="urban_ensemble",
-                    choices=("urban_ensemble", "urban_single", "large_single", "ragged"))
+                    choices=("urban_ensemble", "urban_single", "large_single", "large_bf16", "ragged"))
     ap.add_argument("--summarize", nargs="+", metavar="CSV", help="summarise rocprofv3 CSV files and exit")
     args = ap.parse_args()
     if args.summarize:

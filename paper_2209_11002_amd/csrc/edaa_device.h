@@ -45,9 +45,10 @@ constexpr int kBpassWaves = 8;
 // per-pixel A-steps (p x p products on p-vectors in registers) need more
 // than the 256 registers a wave has at two waves per SIMD.
 constexpr int apass_waves(int p) { return p <= 9 ? 8 : 4; }
-// The A-pass on the bf16 matrix cores (bf16 X) takes the same wave counts
-// (eight waves at p = 10..12 measured slower: the A-steps still occupy one
-// wave per SIMD, and the Gram rows no longer fit the registers).
+// The A-pass on the bf16 matrix cores (bf16 X) takes the same wave counts.
+// (Eight waves at p = 10..12, with the A-steps of a (run, pixel) over 2 or 4
+// lanes reading their Gram rows from LDS, measured no faster: the A-steps
+// there are bound by vector-ALU throughput, not latency.)
 constexpr int xa_waves(int p) { return apass_waves(p); }
 constexpr int kXS = 68;   // LDS pitch (floats) of an X tile row of 64 pixels
 
@@ -388,6 +389,7 @@ __device__ __forceinline__ void a_steps_split(float (&a)[PP], float (&ao)[(PP + 
     }
 }
 
+
 template <int PP, int R>
 struct Shape {
     static constexpr int QC = PP * R;                   // columns per chunk
@@ -457,6 +459,17 @@ __host__ __device__ inline XbLds xb_lds(int PP, int R, int L) {
 }
 // Bands the bf16 matrix-core passes stage: eight blocks of 32.
 constexpr int kXbMaxL = 32 * 8;
+
+// Bank swizzles of the bf16 passes' 16-byte LDS operands (64 banks of 4
+// bytes: 16 slots of 16 bytes per bank cycle).  xo: pixel i of an 8-band row
+// sits in slot i with its two low bits XORed with bits 4-5, so the writes of
+// 16 lanes (pixels 4m + e, m = 0..15) hit 16 distinct slots while the
+// projection's reads (16 consecutive pixels) stay a permutation of 16 slots.
+// Weight operands: lane l = 16 kg + m of pixel block pb sits in slot 16 kg +
+// ((m + 2 kg + 8 pb) & 15), so the softmax's writes (8 lanes of a column: kg
+// and pb vary, m fixed) spread over 16 slots.
+__device__ __forceinline__ int xo_slot(int px) { return (px & ~3) | ((px ^ (px >> 4)) & 3); }
+__device__ __forceinline__ int wb_slot(int kg, int m, int pb) { return 16 * kg + ((m + 2 * kg + 8 * pb) & 15); }
 
 // LDS layout (bytes) of the A-pass on the bf16 matrix cores (apass_xb_body):
 //   xn, xo  the X tile as for the B-pass
@@ -1403,15 +1416,15 @@ struct XbStage {
                     *(uint2*)(Xn + row * kXNP + 4 * m) = u[j];
                 }
                 // pixel 4 m + e: element j of its 16 bytes is band 32 bi + 8 kg + j
-                u32x4* dst = Xo + (4 * bi + kg) * 64 + 4 * m;
+                u32x4* dst = Xo + (4 * bi + kg) * 64;
                 constexpr unsigned LO = 0x05040100u, HI = 0x07060302u;
-                dst[0] = u32x4{__builtin_amdgcn_perm(u[1].x, u[0].x, LO), __builtin_amdgcn_perm(u[3].x, u[2].x, LO),
+                dst[xo_slot(4 * m)] = u32x4{__builtin_amdgcn_perm(u[1].x, u[0].x, LO), __builtin_amdgcn_perm(u[3].x, u[2].x, LO),
                                __builtin_amdgcn_perm(u[5].x, u[4].x, LO), __builtin_amdgcn_perm(u[7].x, u[6].x, LO)};
-                dst[1] = u32x4{__builtin_amdgcn_perm(u[1].x, u[0].x, HI), __builtin_amdgcn_perm(u[3].x, u[2].x, HI),
+                dst[xo_slot(4 * m + 1)] = u32x4{__builtin_amdgcn_perm(u[1].x, u[0].x, HI), __builtin_amdgcn_perm(u[3].x, u[2].x, HI),
                                __builtin_amdgcn_perm(u[5].x, u[4].x, HI), __builtin_amdgcn_perm(u[7].x, u[6].x, HI)};
-                dst[2] = u32x4{__builtin_amdgcn_perm(u[1].y, u[0].y, LO), __builtin_amdgcn_perm(u[3].y, u[2].y, LO),
+                dst[xo_slot(4 * m + 2)] = u32x4{__builtin_amdgcn_perm(u[1].y, u[0].y, LO), __builtin_amdgcn_perm(u[3].y, u[2].y, LO),
                                __builtin_amdgcn_perm(u[5].y, u[4].y, LO), __builtin_amdgcn_perm(u[7].y, u[6].y, LO)};
-                dst[3] = u32x4{__builtin_amdgcn_perm(u[1].y, u[0].y, HI), __builtin_amdgcn_perm(u[3].y, u[2].y, HI),
+                dst[xo_slot(4 * m + 3)] = u32x4{__builtin_amdgcn_perm(u[1].y, u[0].y, HI), __builtin_amdgcn_perm(u[3].y, u[2].y, HI),
                                __builtin_amdgcn_perm(u[5].y, u[4].y, HI), __builtin_amdgcn_perm(u[7].y, u[6].y, HI)};
             }
         }
@@ -1425,7 +1438,7 @@ struct XbOps {
     u32x4 b, e[NC][3];
     template <int CB0, int NCB>
     __device__ __forceinline__ void load(const u32x4* Xo, const u32x4* Esp, int kb, int pb, int lane) {
-        b = Xo[(4 * kb + (lane >> 4)) * 64 + 16 * pb + (lane & 15)];
+        b = Xo[(4 * kb + (lane >> 4)) * 64 + xo_slot(16 * pb + (lane & 15))];
         const u32x4* ep = Esp + (size_t)(kb * NCB + CB0) * 3 * 64 + lane;
 #pragma unroll
         for (int cb = 0; cb < NC; ++cb)
@@ -1500,7 +1513,8 @@ __device__ __forceinline__ void xb_accumulate(d4 (&acc)[NRBW][NCB], const uint16
 #pragma unroll
             for (int cb = 0; cb < NCB; ++cb)
 #pragma unroll
-                for (int sp = 0; sp < 3; ++sp) bop[pk][cb][sp] = Wb[(((p0 + pk) * NCB + cb) * 3 + sp) * 64 + lane];
+                for (int sp = 0; sp < 3; ++sp)
+                    bop[pk][cb][sp] = Wb[(((p0 + pk) * NCB + cb) * 3 + sp) * 64 + wb_slot(kg, m, p0 + pk)];
 #pragma unroll
         for (int j = 0; j < NRBW; ++j)
 #pragma unroll
@@ -1698,7 +1712,7 @@ __device__ __forceinline__ void bpass_xb_body(const Geom& g, const State& s, int
             // k = 8 (sub % 4) + j of pixel block sub / 4
             u32x4 h, md, lw;
             split_bf16x3(wv, h, md, lw);
-            u32x4* dst = Wb + ((sub >> 2) * NCB + (sq >> 4)) * 3 * 64 + 16 * (sub & 3) + (sq & 15);
+            u32x4* dst = Wb + ((sub >> 2) * NCB + (sq >> 4)) * 3 * 64 + wb_slot(sub & 3, sq & 15, sub >> 2);
             dst[0] = h;
             dst[64] = md;
             dst[128] = lw;
@@ -2061,9 +2075,10 @@ __device__ __forceinline__ void apass_xb_body(const Geom& g, const State& s, int
             for (int j = 0; j < 8; ++j) x[j] = Wt[(p0 + j) * WTS + q];
             u32x4 h, md, lw;
             split_bf16x3(x, h, md, lw);
-            Wb[(pc * 3 + 0) * 64 + ln] = h;
-            Wb[(pc * 3 + 1) * 64 + ln] = md;
-            Wb[(pc * 3 + 2) * 64 + ln] = lw;
+            const int sl = wb_slot(ln >> 4, ln & 15, pc / NCB);
+            Wb[(pc * 3 + 0) * 64 + sl] = h;
+            Wb[(pc * 3 + 1) * 64 + sl] = md;
+            Wb[(pc * 3 + 2) * 64 + sl] = lw;
         }
         lds_barrier();
         xb_accumulate<NCB, NRBW, NW, false>(acc, Xn, Wb, nullptr, nullptr, nrb, w, lane);
