@@ -1033,17 +1033,20 @@ __device__ __forceinline__ void apass_body(const Geom& g, const State& s, int bi
                 for (int j = 0; j < PP; ++j) P[j] = Wt[lane * WTS + r * PP + j];
                 const double* Gr = Gd + r * PP * PP;
                 if (mok && pok) {
-                    // ||x - E a||^2 = ||x||^2 - 2 a.P + a.G a, in float64
-                    double q = xnorm;
+                    // ||x - E a||^2 = ||x||^2 - 2 a.P + a.G a, in float64, with
+                    // a.G a = 2 sum_j a_j (G_jj a_j / 2 + sum_{k > j} G_jk a_k)
+                    // (G symmetric: half the products)
+                    double quad = 0.0, lin = 0.0;
 #pragma unroll
                     for (int j = 0; j < PP; ++j) {
-                        double ga = 0.0;
+                        const double aj = (double)a[k][j];
+                        double sj = 0.5 * Gr[j * PP + j] * aj;
 #pragma unroll
-                        for (int kk = 0; kk < PP; ++kk) ga = fma(Gr[j * PP + kk], (double)a[k][kk], ga);
-                        const double pj = (double)P[j] + (double)Plo[lane * WTS + r * PP + j];
-                        q = fma((double)a[k][j], ga - 2.0 * pj, q);
+                        for (int kk = j + 1; kk < PP; ++kk) sj = fma(Gr[j * PP + kk], (double)a[k][kk], sj);
+                        quad = fma(aj, sj, quad);
+                        lin = fma(aj, (double)P[j] + (double)Plo[lane * WTS + r * PP + j], lin);
                     }
-                    lacc[k] += q;
+                    lacc[k] += xnorm + 2.0 * (quad - lin);
                 }
                 if (mok) {
                     if (g.gf)
@@ -2039,16 +2042,19 @@ __device__ __forceinline__ void apass_xb_body(const Geom& g, const State& s, int
                 for (int j = 0; j < PP; ++j) P[j] = Wt[lane * WTS + r * PP + j];
                 const double* Gr = Gd + r * PP * PP;
                 if (mok && pok) {
-                    double q = xnorm;
+                    // ||x||^2 - 2 a.P + a.G a with a.G a = 2 sum_j a_j (G_jj a_j / 2
+                    // + sum_{k > j} G_jk a_k) (G symmetric: half the products)
+                    double quad = 0.0, lin = 0.0;
 #pragma unroll
                     for (int j = 0; j < PP; ++j) {
-                        double ga = 0.0;
+                        const double aj = (double)a[k][j];
+                        double sj = 0.5 * Gr[j * PP + j] * aj;
 #pragma unroll
-                        for (int kk = 0; kk < PP; ++kk) ga = fma(Gr[j * PP + kk], (double)a[k][kk], ga);
-                        const double pj = (double)P[j] + (double)Plo[lane * WTS + r * PP + j];
-                        q = fma((double)a[k][j], ga - 2.0 * pj, q);
+                        for (int kk = j + 1; kk < PP; ++kk) sj = fma(Gr[j * PP + kk], (double)a[k][kk], sj);
+                        quad = fma(aj, sj, quad);
+                        lin = fma(aj, (double)P[j] + (double)Plo[lane * WTS + r * PP + j], lin);
                     }
-                    lacc[k] += q;
+                    lacc[k] += xnorm + 2.0 * (quad - lin);
                 }
                 if (mok) {
                     if (gfx)
