@@ -301,7 +301,10 @@ def bench_large(T, error_T=10):
     ref = dict(np.load(ref_path)) if os.path.exists(ref_path) else None
     ref32_path = os.path.join(GOLDEN, "large_fp32_ref.npz")
     ref32 = dict(np.load(ref32_path)) if os.path.exists(ref32_path) else None
-    res, errs = {}, {}
+    res, errs, plans = {}, {}, {}
+    for name, X in (("bf16", X16), ("f32", X32)):                  # launch shapes for both classes
+        plans[name], tuned_us = api.autotune(X, p, M, K1=cfg["K1"], K2=cfg["K2"])
+        log(f"large scene {name}: tuned launch shape {plans[name]} ({tuned_us:.0f} us per outer iteration)")
     for name, X, widen in (("bf16", X16, False), ("bf16_widen", X16, True), ("f32", X32, False)):
         api.ensemble(X, p, seeds, gammas, T=T, graph=True, bf16_widen=widen)
         torch.cuda.synchronize()
@@ -331,7 +334,7 @@ def bench_large(T, error_T=10):
                   bpass_flops_per_launch=4.0 * L * N * Q,
                   bpass_fp32_equivalent_tflops=round(4.0 * L * N * Q / b_us / 1e6, 2))
     out = dict(unit="run-iterations/s", L=L, N=N, p=p, M=M, T=T, bf16=round(res["bf16"][0], 2),
-               bf16_widen=round(res["bf16_widen"][0], 2), bf16_passes=passes,
+               bf16_widen=round(res["bf16_widen"][0], 2), bf16_passes=passes, launch_shapes=plans,
                f32=round(res["f32"][0], 2), final_loss_max_rel_diff_bf16_vs_f32=rel,
                bf16_gbs=round(per_outer_bf16 * res["bf16"][0] / M / 1e9, 1),
                bf16_hbm_frac=round(per_outer_bf16 * res["bf16"][0] / M / 1e9 / HBM_GBS, 4),

@@ -78,13 +78,28 @@ def sad(M_ref, E):
     return float(np.mean(np.diag(spectral_angles(M_ref, E))))
 
 
+def normalised_abundances(M_ref, A_ref):
+    """The reference abundances restated for l2-normalised pixels: a noise-free
+    pixel x = M a normalises to x / ||x|| = sum_j c_j m_j / ||m_j|| with c_j =
+    a_j ||m_j|| / ||M a||, a point on the ray of the simplex combination
+    a^_j = a_j ||m_j|| / sum_k a_k ||m_k|| of the normalised endmembers.
+    Abundances on the simplex fitted to normalised data estimate a^, not a
+    (they coincide when the endmembers have equal norms)."""
+    M_ref = torch.as_tensor(M_ref, dtype=torch.float64)
+    A_ref = torch.as_tensor(A_ref, dtype=torch.float64).to(M_ref.device)
+    W = A_ref * torch.linalg.norm(M_ref, dim=0)[:, None]
+    return W / W.sum(dim=0, keepdim=True)
+
+
 def score(M_ref, A_ref, E, A):
     """RMSE and SAD of an estimate (E [L][p], A [p][N]) after pairing its
-    endmembers with the reference ones."""
+    endmembers with the reference ones; rmse_normalised scores the same
+    abundances against normalised_abundances."""
     perm = match_endmembers(M_ref, E)
     E = torch.as_tensor(E)[:, perm]
     A = torch.as_tensor(A)[perm, :]
-    return dict(rmse=rmse(A_ref, A), sad=sad(M_ref, E), perm=perm)
+    return dict(rmse=rmse(A_ref, A), rmse_normalised=rmse(normalised_abundances(M_ref, A_ref), A),
+                sad=sad(M_ref, E), perm=perm)
 
 
 def draw_runs(M, gamma_seed=0):
@@ -141,7 +156,8 @@ def main(argv=None):
         X = api.normalize_pixels(torch.from_numpy(sc.X).cuda())
         # as in the paper's experiments, EDAA sees the l2-normalised pixels
         # and is scored against the scene's own ground truth (SAD does not
-        # depend on the scale of the endmembers)
+        # depend on the scale of the endmembers); rmse_normalised scores
+        # against that ground truth restated for normalised pixels
         for row in sweeps(X, sc, p):
             print(json.dumps(dict(scene=name, **row)), flush=True)
 

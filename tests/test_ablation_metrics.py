@@ -102,3 +102,40 @@ def test_run_draws_follow_the_step_set():
     assert ablation.GAMMA_SET == O.GAMMA_SET
     # the K sweep keeps the budget of 1000 updates: T (K1 + K2) = 1000
     assert all((500 // K) * 2 * K == 1000 for K in ablation.K_BUDGET)
+
+
+def test_normalised_abundances_pins():
+    """normalised_abundances (the reference restated for l2-normalised pixels):
+    columns on the simplex; pure pixels stay pure; equal endmember norms leave
+    the abundances unchanged; and a noise-free normalised pixel x / ||x|| lies
+    on the ray of M_hat a^ (M_hat: endmembers scaled to unit norm), checked by
+    a cosine of 1 and by least squares."""
+    rng = np.random.default_rng(7)
+    L, p, N = 30, 4, 200
+    M = rng.uniform(0.1, 1.0, size=(L, p)) * rng.uniform(0.5, 3.0, size=p)[None, :]
+    A = rng.dirichlet(np.ones(p), size=N).T
+    A[:, :p] = np.eye(p)                                     # the first p pixels are pure
+    Ah = ablation.normalised_abundances(M, A).numpy()
+    assert np.all(Ah >= 0) and np.allclose(Ah.sum(axis=0), 1.0, atol=1e-14)
+    assert np.allclose(Ah[:, :p], np.eye(p), atol=1e-15)
+    Mu = M / np.linalg.norm(M, axis=0)
+    assert np.allclose(ablation.normalised_abundances(Mu, A).numpy(), A, atol=1e-14)
+    X = M @ A
+    Xn = X / np.linalg.norm(X, axis=0)
+    Y = Mu @ Ah
+    cos = np.sum(Xn * Y, axis=0) / np.linalg.norm(Y, axis=0)
+    assert np.allclose(cos, 1.0, atol=1e-12)
+    # the direction determines a^: least squares of Xn on Mu, renormalised to sum 1
+    C, *_ = np.linalg.lstsq(Mu, Xn, rcond=None)
+    assert np.allclose(C / C.sum(axis=0), Ah, atol=1e-10)
+
+
+def test_score_reports_both_references():
+    rng = np.random.default_rng(8)
+    L, p, N = 20, 3, 50
+    M = rng.uniform(0.1, 1.0, size=(L, p))
+    A = rng.dirichlet(np.ones(p), size=N).T
+    r = ablation.score(M, A, M, ablation.normalised_abundances(M, A))
+    assert r["rmse_normalised"] < 1e-12 and r["sad"] < 1e-5
+    r = ablation.score(M, A, M, A)
+    assert r["rmse"] < 1e-12
