@@ -80,14 +80,15 @@ def parse_shape(text):
     return r, n
 
 
-def profile_run(T, workload, shape=None):
+def profile_run(T, workload, shape=None, tiles_per_item=0):
     """Workload for rocprofv3 passes: a plain device copy of known size (the
     calibration of FETCH_SIZE / WRITE_SIZE) and then T outer iterations of
     'urban_ensemble' (the headline ensemble, at the launch shape `shape` if
     given), 'urban_single' (one run on the same scene), 'large_single' (one
     run on the L=224, N=512x614, p=12 scene, float32 X), 'large_bf16' (the
     M=20 ensemble on that scene with bf16 X, bf16 matrix-core passes) or
-    'ragged' (the 64-image ragged batch, persistent kernel)."""
+    'ragged' (the 64-image ragged batch, persistent kernel, work items of
+    `tiles_per_item` tiles, 0 for the default)."""
     import torch
     from paper_2209_11002_amd import api, synth
     dev = torch.device("cuda:0")
@@ -102,7 +103,7 @@ def profile_run(T, workload, shape=None):
         scenes, _ = synth.ragged_images(64)
         X = [api.normalize_pixels(torch.from_numpy(sc.X).to(dev)) for sc in scenes]
         ps = [sc.M.shape[1] for sc in scenes]
-        api.fit_ragged(X, ps, list(range(64)), [1.0] * 64, T=T)
+        api.fit_ragged(X, ps, list(range(64)), [1.0] * 64, T=T, tiles_per_item=tiles_per_item)
         torch.cuda.synchronize()
         log(f"profile run done ({workload}, T={T})")
         return
@@ -417,6 +418,8 @@ def main():
                     help="run a counter-profiling workload with T outer iterations and exit")
     ap.add_argument("--profile-workload", default="urban_ensemble",
                     choices=("urban_ensemble", "urban_single", "large_single", "large_bf16", "ragged"))
+    ap.add_argument("--tiles-per-item", type=int, default=0,
+                    help="--profile-workload ragged: work-item size of the persistent kernel (0: default)")
     ap.add_argument("--summarize", nargs="+", metavar="CSV", help="summarise rocprofv3 CSV files and exit")
     args = ap.parse_args()
     if args.summarize:
@@ -427,7 +430,8 @@ def main():
               "(run it with --gpus 1)", file=sys.stderr)
         sys.exit(2)
     if args.profile_run > 0:
-        profile_run(args.profile_run, args.profile_workload, parse_shape(args.shape) if args.shape else None)
+        profile_run(args.profile_run, args.profile_workload, parse_shape(args.shape) if args.shape else None,
+                    args.tiles_per_item)
         return
 
     import numpy as np

@@ -49,6 +49,27 @@ def test_autotune_ensemble_shape_is_used(api):
 
 
 @gpu
+def test_autotune_bf16_class_is_its_own(api):
+    """bf16 X is its own tuning class (its passes are the bf16 matrix-core
+    kernels): tuning it leaves the float32 class of the same shape at its
+    default, and the tuned bf16 ensemble still matches the oracle run on the
+    bf16 values."""
+    L, N, p, M = 52, 2500, 5, 5
+    Xg, _ = _prep(83, L, N, p)
+    X16 = Xg.to(torch.bfloat16)
+    X64 = X16.double().cpu().numpy()
+    best, us = api.autotune(X16, p, M)
+    _say(f"bf16 tuned {best}, {us:.1f} us per outer iteration")
+    assert api.plan(L, N, p, M, x_dtype=torch.bfloat16)["source"] == "tuned"
+    assert api.plan(L, N, p, M)["source"] == "default"
+    seeds, gammas = list(range(M)), [0.5, 1.0, 2.0, 0.5, 1.0]
+    r = api.ensemble(X16, p, seeds, gammas, T=5)
+    ref = O.ensemble(X64, p, seeds, gammas, T=5)
+    for m, rr in enumerate(ref["runs"]):
+        assert np.max(np.abs(r["loss"][m] - rr["loss"]) / rr["loss"]) < 1e-4, m
+
+
+@gpu
 def test_autotune_ragged_item_size_is_used(api):
     shapes = [(40, 3000, 3), (57, 5000, 6), (31, 700, 4), (80, 9000, 8)]
     imgs = [_prep(90 + k, L, N, p)[0] for k, (L, N, p) in enumerate(shapes)]

@@ -58,6 +58,23 @@ def test_noalloc_matches_fit_twice_then_smaller(api):
 
 
 @gpu
+def test_noalloc_matches_fit_bf16(api):
+    """The same with bf16 X (the bf16 matrix-core passes)."""
+    dev = torch.device("cuda:0")
+    L, N, p, T, seed = 50, 700, 5, 6, 73
+    _say(f"noalloc vs fit, bf16 X, L={L} N={N} p={p} T={T}")
+    X = _prep(seed, L, N, p).to(torch.bfloat16)
+    ref = api.fit(X, p, T=T, gamma=1.0, seed=seed)
+    out = dict(A=torch.full((p, N), np.nan, device=dev), B=torch.full((N, p), np.nan, device=dev),
+               E=torch.full((L, p), np.nan, device=dev),
+               loss=torch.full((T + 1,), np.nan, dtype=torch.float64, device=dev))
+    api.fit_noalloc(X, p, out, T=T, gamma=1.0, seed=seed)
+    torch.cuda.synchronize()
+    assert torch.equal(out["A"], ref["A"]) and torch.equal(out["B"], ref["B"]) and torch.equal(out["E"], ref["E"])
+    assert np.array_equal(out["loss"].cpu().numpy(), ref["loss"])
+
+
+@gpu
 def test_noalloc_refuses_what_it_cannot_hold(api):
     dev = torch.device("cuda:0")
     X = torch.zeros((448, 8), device=dev)
