@@ -64,7 +64,15 @@ enum {
                                 the projection of the A-pass, float64) matrix
                                 cores, instead of the default bf16 matrix-core
                                 passes (X stays bf16; the float32 operand in
-                                three bf16 terms) */
+                                three bf16 terms) */,
+    EDAA_FLAG_F32_MFMA = 16 /* float32 X (edaa_fit, edaa_ensemble,
+                                edaa_fit_noalloc): run the B-pass contractions
+                                on the float32 matrix cores instead of the
+                                default bf16 ones, where both float32 operands
+                                are split exactly into three bf16 terms and the
+                                six products above float32 rounding are summed
+                                (the two agree to float32 rounding, not bit for
+                                bit) */
 };
 
 /* Parameters of Algorithm 1 / Algorithm 2.  edaa_default_params fills the

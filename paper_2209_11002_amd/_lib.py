@@ -19,6 +19,7 @@ EDAA_FLAG_GRAPH = 1
 EDAA_FLAG_TIME_PASSES = 2
 EDAA_FLAG_RAGGED_GROUPED = 4
 EDAA_FLAG_BF16_WIDEN = 8
+EDAA_FLAG_F32_MFMA = 16
 
 
 class EdaaParams(ctypes.Structure):

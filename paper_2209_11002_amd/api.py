@@ -89,7 +89,7 @@ def _check_dense_operands(X, A, B):
 
 
 def _params(T, K1, K2, gamma, eta, init_scale, threshold, x_dtype, coherence, graph, time_passes=False,
-            runs_per_chunk=0, pixel_groups=0, bf16_widen=False):
+            runs_per_chunk=0, pixel_groups=0, bf16_widen=False, f32_mfma=False):
     P = L_.default_params()
     P.runs_per_chunk, P.pixel_groups = int(runs_per_chunk), int(pixel_groups)
     P.T, P.K1, P.K2 = int(T), int(K1), int(K2)
@@ -103,6 +103,8 @@ def _params(T, K1, K2, gamma, eta, init_scale, threshold, x_dtype, coherence, gr
     P.flags = (L_.EDAA_FLAG_GRAPH if graph else 0) | (L_.EDAA_FLAG_TIME_PASSES if time_passes else 0)
     if bf16_widen:
         P.flags |= L_.EDAA_FLAG_BF16_WIDEN
+    if f32_mfma:
+        P.flags |= L_.EDAA_FLAG_F32_MFMA
     return P
 
 
@@ -122,13 +124,16 @@ def normalize_pixels(X, out_dtype=torch.float32, count_zero=False):
 
 
 def fit(X, p, T=100, K1=5, K2=5, gamma=1.0, seed=0, A0=None, B0=None, eta=None,
-        init_scale=0.1, graph=False, time_passes=False, pixel_groups=0, out=None, bf16_widen=False):
+        init_scale=0.1, graph=False, time_passes=False, pixel_groups=0, out=None, bf16_widen=False,
+        f32_mfma=False):
     """One run of Algorithm 1 on l2-normalised X [L, N] (float32 or bfloat16,
     on the GPU).  Returns a dict: A [p, N], B [N, p], E [L, p] (tensors),
     loss (numpy, T+1), eta1, eta2.  out: optional dict of preallocated
     A [p, N], B [N, p], E [L, p] float32 tensors to write into.
-    bf16_widen: bf16 X runs the B-pass on the float32 matrix cores
-    (EDAA_FLAG_BF16_WIDEN) instead of the bf16 ones."""
+    bf16_widen: bf16 X runs the passes on the float32 matrix cores
+    (EDAA_FLAG_BF16_WIDEN) instead of the bf16 ones.  f32_mfma: float32 X
+    runs the B-pass on the float32 matrix cores (EDAA_FLAG_F32_MFMA) instead
+    of the bf16 ones with three-term operands."""
     Lb, N = _check_x(X)
     dev = X.device
     if out is None:
@@ -147,7 +152,7 @@ def fit(X, p, T=100, K1=5, K2=5, gamma=1.0, seed=0, A0=None, B0=None, eta=None,
     trace = (c_double * (T + 1))()
     eta_out = (c_double * 2)()
     P = _params(T, K1, K2, gamma, eta, init_scale, 1.05, _x_dtype(X), "cosine", graph, time_passes,
-                pixel_groups=pixel_groups, bf16_widen=bf16_widen)
+                pixel_groups=pixel_groups, bf16_widen=bf16_widen, f32_mfma=f32_mfma)
     lib = L_.load()
     st = lib.edaa_fit(_ctx(dev), _ptr(X), Lb, N, p, byref(P), c_uint64(seed), _ptr(A0), _ptr(B0),
                       _ptr(A), _ptr(B), _ptr(E), trace, eta_out)
@@ -208,12 +213,12 @@ def abundances(X, E, T=100, K1=5, gamma=1.0, A0=None, eta1=None, graph=False):
 
 def ensemble(X, p, seeds, gammas, T=100, K1=5, K2=5, coherence="cosine", threshold=1.05,
              init_scale=0.1, graph=False, out=None, time_passes=False, runs_per_chunk=0, pixel_groups=0,
-             bf16_widen=False):
+             bf16_widen=False, f32_mfma=False):
     """M runs of Algorithm 1 advanced together plus Algorithm 2.  Returns a
     dict with A [M, p, N], B [M, N, p], E [M, L, p] (tensors), loss [M, T+1],
     fit [M], mu [M], status [M] (numpy) and the selected run index.
     runs_per_chunk / pixel_groups pin the launch shape (0: tuned or
-    default; see plan()); bf16_widen as for fit()."""
+    default; see plan()); bf16_widen, f32_mfma as for fit()."""
     Lb, N = _check_x(X)
     M = len(seeds)
     if len(gammas) != M:
@@ -236,7 +241,7 @@ def ensemble(X, p, seeds, gammas, T=100, K1=5, K2=5, coherence="cosine", thresho
     status = np.zeros(M, dtype=np.int32)
     sel = c_int(-1)
     P = _params(T, K1, K2, 1.0, None, init_scale, threshold, _x_dtype(X), coherence, graph, time_passes,
-                runs_per_chunk, pixel_groups, bf16_widen)
+                runs_per_chunk, pixel_groups, bf16_widen, f32_mfma)
     lib = L_.load()
     dp = lambda a: a.ctypes.data_as(ctypes.POINTER(c_double))  # noqa: E731
     st = lib.edaa_ensemble(_ctx(dev), _ptr(X), Lb, N, p, byref(P), M, sd, gm,

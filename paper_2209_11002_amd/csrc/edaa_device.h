@@ -498,6 +498,72 @@ __host__ __device__ inline XaLds xa_lds(int PP, int R, int L, int gf) {
     return o;
 }
 
+// LDS layout (bytes) of the B-pass for float32 X on the bf16 matrix cores
+// (bpass_xs_body), LP32 = L rounded up to 32:
+//   xf   [LP32][kXS] float       X tile, pixels contiguous (rows >= L zero)
+//   wsp  [LP32/32][NCB][3][64]   16-byte MFMA operands of W (three bf16 terms),
+//                                bands in the order of xs_band
+//   wb   [2][NCB][3][64]         16-byte MFMA operands of the tile's weights
+//   sq   [QCP][kXS] float        projection W^T x (the k blocks of waves 0-3)
+//   sq2  [QCP][kXS] float        the k blocks of waves 4-7 (ksplit only)
+//   f, fg [QCP] float            rescale factors
+// ksplit: the two wave groups take alternate k blocks of every column block
+// (each X operand is split once); without it (more than three column blocks,
+// or no room for sq2) they take halves of the column blocks.
+struct XsLds {
+    int xf, wsp, wb, sq, sq2, f, fg, total, ksplit;
+};
+__host__ __device__ inline XsLds xs_lds(int PP, int R, int L) {
+    const int QCP = (PP * R + 15) & ~15, NCB = QCP / 16, LP32 = (L + 31) & ~31;
+    XsLds o;
+    o.xf = 0;
+    o.wsp = o.xf + LP32 * kXS * 4;
+    o.wb = o.wsp + (LP32 / 32) * NCB * 3 * 1024;
+    o.sq = o.wb + 2 * NCB * 3 * 1024;
+    o.sq2 = o.sq + QCP * kXS * 4;
+    o.ksplit = NCB <= 3 && o.sq2 + QCP * kXS * 4 + 2 * QCP * 4 <= 160 * 1024;
+    if (NCB == 1) o.ksplit = 1;       // one column block: the second group has no other share
+    o.f = o.sq2 + (o.ksplit ? QCP * kXS * 4 : 0);
+    o.fg = o.f + QCP * 4;
+    o.total = o.fg + QCP * 4;
+    return o;
+}
+
+// Band of element j of the 8 a lane of k group kg holds in the float32-X
+// projection (within a block of 32): 4 kg + (j & 3) + 16 (j >> 2), so that
+// the eight single-float reads of the 64 lanes (rows 4 kg + c at pitch kXS,
+// 16 consecutive pixels) fall on 64 distinct banks.  W's operands use the
+// same order.
+__device__ __forceinline__ int xs_band(int kg, int j) { return 4 * kg + (j & 3) + 16 * (j >> 2); }
+
+// Two float32 values as three packed bf16 terms each (element 0 in the low
+// half): hi = rn(x), mid = rn(x - hi), lo = rn(x - hi - mid), with exact
+// differences, so hi + mid + lo == x for |x| above about 1e-30.
+__device__ __forceinline__ unsigned pack_bf16(float a, float b) {
+    typedef float f2 __attribute__((ext_vector_type(2)));
+    typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+    return __builtin_bit_cast(unsigned, __builtin_convertvector(f2{a, b}, bf16x2));
+}
+__device__ __forceinline__ void split2_bf16x3(float x0, float x1, unsigned& h, unsigned& m, unsigned& l) {
+    h = pack_bf16(x0, x1);
+    const float r0 = x0 - __builtin_bit_cast(float, h << 16);
+    const float r1 = x1 - __builtin_bit_cast(float, h & 0xffff0000u);
+    m = pack_bf16(r0, r1);
+    const float s0 = r0 - __builtin_bit_cast(float, m << 16);
+    const float s1 = r1 - __builtin_bit_cast(float, m & 0xffff0000u);
+    l = pack_bf16(s0, s1);
+}
+__device__ __forceinline__ void split8_bf16x3(const float (&x)[8], u32x4 (&t)[3]) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        unsigned h, m, l;
+        split2_bf16x3(x[2 * i], x[2 * i + 1], h, m, l);
+        t[0][i] = h;
+        t[1][i] = m;
+        t[2][i] = l;
+    }
+}
+
 // Scheduling pattern for a block of NMFMA matrix instructions and the LDS
 // reads of the next block's operands: the reads go, up to four at a time,
 // between the first four MFMAs, so they complete while the later MFMAs of
@@ -1745,6 +1811,392 @@ template <int PP, int R, bool STEP>
 __global__ __launch_bounds__(64 * kBpassWaves, 1) void k_bpass_xb(Geom g, State s, const float* __restrict__ W,
                                                                   int mode, RunInit ri) {
     bpass_xb_body<PP, R, STEP>(g, s, blockIdx.x, W, mode, ri);
+}
+
+// --------------------------------------------------------------------------
+// B-pass for float32 X on the bf16 matrix cores: the same pass as bpass_body
+// (same softmax, state, partials and results).  Both float32 operands of each
+// contraction are split exactly into three bf16 terms, x = xh + xm + xl and
+// w = wh + wm + wl (split2_bf16x3), and the six products whose size is above
+// about 2^-24 of x w (xh wh, xh wm, xm wh, xh wl, xl wh, xm wm) are summed on
+// v_mfma_f32_16x16x32_bf16 with float32 accumulation; the three dropped ones
+// are below 2^-23 of the product and unbiased, the size of a float32
+// rounding (the "bf16x6" scheme of Henry, Tang and Heinecke, "Leveraging the
+// bfloat16 artificial intelligence datatype for higher-precision
+// computations", ARITH 2019).  Per 32 bands or pixels that is 6 MFMAs of 16
+// clocks, against 8 float32 MFMAs of 32.
+//
+// The X tile is kept once in LDS as float32 (xf, pixels contiguous, staged
+// through registers one tile ahead: XfStage); both contractions read their
+// eight values per lane from it and split them in registers: the
+// accumulation's A operand (eight consecutive pixels of a band) as two 16-byte
+// reads, the projection's B operand (eight bands of a pixel, in the order of
+// xs_band) as eight single reads.
+// Work split (8 waves): projection: waves w and w + 4 take pixel block w & 3,
+// with alternate k blocks of every column block (ksplit; sums in sq and sq2)
+// or halves of the column blocks; accumulation by row blocks of 16 bands, rb
+// = w + 8 j.
+// --------------------------------------------------------------------------
+// Register staging of a float32 X tile: round i, lane (r, q) of wave w loads
+// pixels 4 q .. 4 q + 3 of band 4 (w + NW i) + r (16-byte loads, issued one
+// tile ahead); store() writes them to xf.
+template <int NW>
+struct XfStage {
+    static constexpr int NI = kXbMaxL / (4 * NW);   // rounds of 4 NW bands
+    f4 v[NI];
+
+    __device__ __forceinline__ void issue(const float* X, size_t ldx, int L, int tile) {
+        const int lane = threadIdx.x & 63, w = uniform_int(threadIdx.x >> 6);
+        const float* src = X + (size_t)tile * kTile + 4 * (lane & 15);
+#pragma unroll
+        for (int i = 0; i < NI; ++i) {
+            const int row = 4 * (w + NW * i) + (lane >> 4);
+            if (4 * (w + NW * i) < L) v[i] = *(const f4*)(src + (size_t)min(row, L - 1) * ldx);
+        }
+    }
+    __device__ __forceinline__ void store(float* Xf, int L) const {
+        const int lane = threadIdx.x & 63, w = uniform_int(threadIdx.x >> 6);
+#pragma unroll
+        for (int i = 0; i < NI; ++i) {
+            const int row = 4 * (w + NW * i) + (lane >> 4);
+            if (row < L) *(f4*)(Xf + row * kXS + 4 * (lane & 15)) = v[i];
+        }
+    }
+};
+
+// Operands of one k block of the float32-X projection: the eight float32 X
+// values of the lane (split when used) and the three terms of NC column
+// blocks of W.
+template <int NC>
+struct XsOps {
+    float x[8];
+    u32x4 e[NC][3];
+    template <int CB0, int NCB>
+    __device__ __forceinline__ void load(const float* Xf, const u32x4* Wsp, int kb, int pb, int lane) {
+        const float* xb = Xf + (32 * kb + 4 * (lane >> 4)) * kXS + 16 * pb + (lane & 15);
+#pragma unroll
+        for (int j = 0; j < 8; ++j) x[j] = xb[((j & 3) + 16 * (j >> 2)) * kXS];
+        const u32x4* ep = Wsp + (size_t)(kb * NCB + CB0) * 3 * 64 + lane;
+#pragma unroll
+        for (int cb = 0; cb < NC; ++cb)
+#pragma unroll
+            for (int sp = 0; sp < 3; ++sp) e[cb][sp] = ep[(3 * cb + sp) * 64];
+    }
+};
+
+// The six products of a split pair, smallest first: product u takes term
+// x6a(u) of X and term x6b(u) of the other operand (0 hi, 1 mid, 2 lo).
+constexpr int x6a(int u) { return u == 0 || u == 3 ? 1 : u == 1 ? 2 : 0; }
+constexpr int x6b(int u) { return u == 0 || u == 4 ? 1 : u == 2 ? 2 : 0; }
+
+template <int NC, int CB0, int NCB, int KBS>
+__device__ __forceinline__ void xs_project(const float* Xf, const u32x4* Wsp, float* Sq, int nkb, int kb0, int pb,
+                                           int lane) {
+    const int m = lane & 15, kg = lane >> 4;
+    f4 s[NC], s2[NC];
+#pragma unroll
+    for (int cb = 0; cb < NC; ++cb) s[cb] = s2[cb] = f4{0.f, 0.f, 0.f, 0.f};
+    auto mma = [&](const XsOps<NC>& o) {
+        u32x4 xt[3];
+        split8_bf16x3(o.x, xt);
+#pragma unroll
+        for (int u = 0; u < 6; ++u)
+#pragma unroll
+            for (int cb = 0; cb < NC; ++cb) {
+                // with one column block alternate products go to a second chain
+                if (NC == 1 && (u & 1))
+                    s2[cb] = mfma16_bf16(o.e[cb][x6b(u)], xt[x6a(u)], s2[cb]);
+                else
+                    s[cb] = mfma16_bf16(o.e[cb][x6b(u)], xt[x6a(u)], s[cb]);
+            }
+    };
+    if (kb0 < nkb) {
+        XsOps<NC> o0, o1;
+        o0.template load<CB0, NCB>(Xf, Wsp, kb0, pb, lane);
+        int kb = kb0;
+        for (; kb + KBS < nkb; kb += 2 * KBS) {
+            o1.template load<CB0, NCB>(Xf, Wsp, kb + KBS, pb, lane);
+            mma(o0);
+            o0.template load<CB0, NCB>(Xf, Wsp, (kb + 2 * KBS < nkb) ? kb + 2 * KBS : kb, pb, lane);
+            mma(o1);
+        }
+        if (kb < nkb) mma(o0);
+    }
+#pragma unroll
+    for (int cb = 0; cb < NC; ++cb) {
+        if (NC == 1) s[cb] += s2[cb];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) Sq[(16 * (CB0 + cb) + 4 * kg + v) * kXS + 16 * pb + m] = s[cb][v];
+    }
+}
+
+// V += X_tile Wt on the bf16 matrix cores from the float32 X tile (xf) and the
+// split weights, folded into the float64 running sums like xb_accumulate.
+template <int NCB, int NRBW, int NW>
+__device__ __forceinline__ void xs_accumulate(d4 (&acc)[NRBW][NCB], const float* Xf, const u32x4* Wb, const float* F,
+                                              const float* G, int nrb, int w, int lane) {
+    const int m = lane & 15, kg = lane >> 4;
+    constexpr int JG = NRBW < 2 ? NRBW : 2, CG = NCB >= 4 ? 2 : NCB;
+    static_assert(NRBW % JG == 0 && NCB % CG == 0, "row and column blocks in whole groups");
+    f4 t[NRBW][NCB];
+#pragma unroll
+    for (int j = 0; j < NRBW; ++j)
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb) t[j][cb] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int pk = 0; pk < 2; ++pk) {
+        u32x4 xa[JG][3];
+        // row blocks in groups of JG (the split X operands of a group are live
+        // together: 20 registers per row block), column blocks in groups of CG
+#pragma unroll
+        for (int j0 = 0; j0 < NRBW; j0 += JG) {
+            float xv[JG][8];
+#pragma unroll
+            for (int jj = 0; jj < JG; ++jj) {
+                const float* xp = Xf + (16 * min(w + NW * (j0 + jj), nrb - 1) + m) * kXS + 32 * pk + 8 * kg;
+                const f4 a = *(const f4*)xp, b = *(const f4*)(xp + 4);
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    xv[jj][e] = a[e];
+                    xv[jj][4 + e] = b[e];
+                }
+            }
+#pragma unroll
+            for (int jj = 0; jj < JG; ++jj) split8_bf16x3(xv[jj], xa[jj]);
+#pragma unroll
+            for (int c0 = 0; c0 < NCB; c0 += CG) {
+                u32x4 bop[CG][3];
+#pragma unroll
+                for (int cc = 0; cc < CG; ++cc)
+#pragma unroll
+                    for (int sp = 0; sp < 3; ++sp)
+                        bop[cc][sp] = Wb[((pk * NCB + c0 + cc) * 3 + sp) * 64 + wb_slot(kg, m, pk)];
+#pragma unroll
+                for (int u = 0; u < 6; ++u)
+#pragma unroll
+                    for (int jj = 0; jj < JG; ++jj) {
+                        if (w + NW * (j0 + jj) < nrb) {
+#pragma unroll
+                            for (int cc = 0; cc < CG; ++cc)
+                                t[j0 + jj][c0 + cc] =
+                                    mfma16_bf16(xa[jj][x6a(u)], bop[cc][x6b(u)], t[j0 + jj][c0 + cc]);
+                        }
+                    }
+            }
+        }
+    }
+    float fs[NCB], gs[NCB];
+#pragma unroll
+    for (int cb = 0; cb < NCB; ++cb) {
+        fs[cb] = F[16 * cb + m];
+        gs[cb] = G[16 * cb + m];
+    }
+#pragma unroll
+    for (int j = 0; j < NRBW; ++j)
+        if (w + NW * j < nrb)
+#pragma unroll
+            for (int cb = 0; cb < NCB; ++cb)
+#pragma unroll
+                for (int v = 0; v < 4; ++v)
+                    acc[j][cb][v] = fma(acc[j][cb][v], (double)fs[cb], (double)t[j][cb][v] * (double)gs[cb]);
+}
+
+template <int PP, int R, bool STEP>
+__device__ __forceinline__ void bpass_xs_body(const Geom& g, const State& s, int bid, const float* __restrict__ W,
+                                              int mode, const RunInit& ri) {
+    using S = Shape<PP, R>;
+    constexpr int NW = 8, NT = 64 * NW;
+    constexpr int QC = S::QC, QCP = S::QCP, NCB = S::NCB, NRBW = S::NRBW * 4 / NW;
+    constexpr int SPX = kTile / NW, SV = SPX / 4;   // softmax: 8 lanes per column, 8 pixels each
+    constexpr int NC0 = (NCB + 1) / 2, NC1 = NCB - NC0;
+    static_assert(SPX == 8 && QCP * NW <= NT, "eight lanes of eight pixels per softmax column");
+    extern __shared__ float smem[];
+    char* const lds = (char*)smem;
+    const XsLds lo = xs_lds(PP, R, g.L);
+    float* Xf = (float*)(lds + lo.xf);
+    u32x4* Wsp = (u32x4*)(lds + lo.wsp);
+    u32x4* Wb = (u32x4*)(lds + lo.wb);
+    float* Sq = (float*)(lds + lo.sq);
+    float* Sq2 = (float*)(lds + lo.sq2);
+    float* F = (float*)(lds + lo.f);
+    float* FG = (float*)(lds + lo.fg);
+    const bool ksplit = NCB <= 3 && lo.ksplit;
+
+    int pg, c;
+    wg_coords(g, bid, pg, c);
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int w = uniform_int(tid >> 6);
+    const int L = g.L, N = g.N, nkb = (L + 31) >> 5, nrb = (L + 15) >> 4;
+    const size_t Np = (size_t)g.ntiles * kTile;
+    const int col0 = c * QC;
+
+    for (int e = tid; e < QCP; e += NT) F[e] = FG[e] = 0.f;
+    for (int e = tid; e < 2 * NCB * 3 * 64; e += NT) Wb[e] = u32x4{0u, 0u, 0u, 0u};
+    // X rows L .. 32 nkb - 1 (read by the last k block and row block) stay zero
+    for (int e = tid; e < (32 * nkb - L) * kXS; e += NT) Xf[L * kXS + e] = 0.f;
+    if (STEP) {
+        // W[:, chunk] as MFMA A operands: entry (kb, cb, lane) holds the rows
+        // 32 kb + xs_band(lane / 16, j) of column 16 cb + lane % 16
+        for (int e = tid; e < nkb * NCB * 64; e += NT) {
+            const int ln = e & 63, kc = e >> 6;
+            const int q = 16 * (kc % NCB) + (ln & 15), r0 = 32 * (kc / NCB);
+            float x[8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const int r = r0 + xs_band(ln >> 4, j);
+                x[j] = (r < L && q < QC) ? W[(size_t)r * g.Qp + col0 + q] : 0.f;
+            }
+            u32x4 t[3];
+            split8_bf16x3(x, t);
+            Wsp[(kc * 3 + 0) * 64 + ln] = t[0];
+            Wsp[(kc * 3 + 1) * 64 + ln] = t[1];
+            Wsp[(kc * 3 + 2) * 64 + ln] = t[2];
+        }
+    }
+
+    const int sq = tid / NW, sub = tid % NW;
+    const int sm = c * R + sq / PP, sj = sq % PP;
+    const bool qin = sq < QC;
+    const bool cok = qin && sm < g.M;
+    float* bcol = s.Bst + (size_t)(cok ? col0 + sq : 0) * Np + SPX * sub;
+    float mrun = -INFINITY, lzc = 0.f, eta2 = 0.f;
+    double srun = 0.0;
+    if (STEP && cok) {
+        lzc = -s.colm[col0 + sq] - logf(s.cols[col0 + sq]);
+        eta2 = s.eta[2 * sm + 1];
+    }
+
+    d4 acc[NRBW][NCB];
+#pragma unroll
+    for (int jb = 0; jb < NRBW; ++jb)
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb) acc[jb][cb] = d4{0.0, 0.0, 0.0, 0.0};
+
+    XfStage<NW> xs;
+    f4 bn[SV];
+    float tn = 0.f;
+    auto load_b = [&](int tile) {
+        if (STEP && cok) {
+            const f4* src = (const f4*)(bcol + (size_t)tile * kTile);
+#pragma unroll
+            for (int u = 0; u < SV; ++u) bn[u] = src[u];
+            tn = s.tshift[(size_t)tile * g.Qp + col0 + sq];
+        }
+    };
+    __syncthreads();
+    if (pg < g.ntiles) {
+        xs.issue((const float*)s.X, s.ldx, L, pg);
+        xs.store(Xf, L);
+        load_b(pg);
+    }
+    for (int tile = pg; tile < g.ntiles; tile += g.npg) {
+        __builtin_amdgcn_s_waitcnt(0);
+        lds_barrier();
+        f4 bv[SV];
+#pragma unroll
+        for (int u = 0; u < SV; ++u) bv[u] = bn[u];
+        const float ts = tn;
+        const int nt = tile + g.npg;
+        if (nt < g.ntiles) {
+            load_b(nt);
+            xs.issue((const float*)s.X, s.ldx, L, nt);
+        }
+
+        if (STEP) {
+            if (ksplit) {
+                if constexpr (NCB <= 3)
+                    xs_project<NCB, 0, NCB, 2>(Xf, Wsp, (w < 4) ? Sq : Sq2, nkb, w >> 2, w & 3, lane);
+            } else if (w < 4) {
+                xs_project<NC0, 0, NCB, 1>(Xf, Wsp, Sq, nkb, 0, w, lane);
+            } else if constexpr (NC1 > 0) {
+                xs_project<NC1, NC0, NCB, 1>(Xf, Wsp, Sq, nkb, 0, w - 4, lane);
+            }
+            lds_barrier();
+        }
+
+        if (qin) {
+            const int pix0 = tile * kTile + SPX * sub;
+            float v[SPX];
+            if (STEP) {
+                const float sh = ts + lzc;
+                const float* grow = Sq + sq * kXS + SPX * sub;
+#pragma unroll
+                for (int u = 0; u < SV; ++u) {
+                    f4 gv = *(const f4*)(grow + 4 * u);
+                    if (ksplit) gv += *(const f4*)(grow - Sq + Sq2 + 4 * u);
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) v[4 * u + e] = fast_log(bv[u][e]) + sh - eta2 * gv[e];
+                }
+            } else if (mode == kModeInitRng) {
+                const uint64_t seed = ri.seeds[cok ? sm : 0];
+#pragma unroll
+                for (int i = 0; i < SPX; ++i) v[i] = ri.init_scale * uniform_u(seed, pix0 + i, sj);
+            } else {
+#pragma unroll
+                for (int i = 0; i < SPX; ++i) v[i] = fast_log(ri.B0[(size_t)min(pix0 + i, N - 1) * PP + sj]);
+            }
+            float mx = -INFINITY;
+#pragma unroll
+            for (int i = 0; i < SPX; ++i) {
+                v[i] = (cok && pix0 + i < N) ? v[i] : -INFINITY;
+                mx = fmaxf(mx, v[i]);
+            }
+            mx = fmaxf(mx, dpp<0xB1>(mx));
+            mx = fmaxf(mx, dpp<0x4E>(mx));
+            mx = fmaxf(mx, dpp<0x141>(mx));
+            const float mnew = fmaxf(mrun, mx);
+            const float f = (mrun == -INFINITY) ? 0.f : fast_exp(mrun - mnew);
+            const float fg = (mx == -INFINITY) ? 0.f : fast_exp(mx - mnew);
+            float wv[SPX], sum = 0.f;
+#pragma unroll
+            for (int i = 0; i < SPX; ++i) {
+                wv[i] = (v[i] == -INFINITY) ? 0.f : fast_exp(v[i] - mx);
+                sum += wv[i];
+            }
+            sum += dpp<0xB1>(sum);
+            sum += dpp<0x4E>(sum);
+            sum += dpp<0x141>(sum);
+            srun = fma(srun, (double)f, (double)sum * (double)fg);
+            mrun = mnew;
+            if (cok) {
+#pragma unroll
+                for (int u = 0; u < SV; ++u)
+                    ((f4*)(bcol + (size_t)tile * kTile))[u] = f4{wv[4 * u], wv[4 * u + 1], wv[4 * u + 2], wv[4 * u + 3]};
+            }
+            // the accumulation's B operand: pixels 8 sub .. of column sq are
+            // k = 8 (sub % 4) + j of pixel block sub / 4
+            u32x4 t[3];
+            split8_bf16x3(wv, t);
+            u32x4* dst = Wb + ((sub >> 2) * NCB + (sq >> 4)) * 3 * 64 + wb_slot(sub & 3, sq & 15, sub >> 2);
+            dst[0] = t[0];
+            dst[64] = t[1];
+            dst[128] = t[2];
+            if (sub == 0) {
+                F[sq] = f;
+                FG[sq] = fg;
+                if (cok) s.tshift[(size_t)tile * g.Qp + col0 + sq] = mx;
+            }
+        }
+        lds_barrier();
+        xs_accumulate<NCB, NRBW, NW>(acc, Xf, Wb, F, FG, nrb, w, lane);
+        if (nt < g.ntiles) {
+            lds_barrier();                         // every wave is done with this tile's X
+            xs.store(Xf, L);
+        }
+    }
+
+    const size_t wgi = (size_t)pg * g.nqc + c;
+    store_acc<NCB, NRBW, QC, NW>(acc, s.Vpart + wgi * (size_t)L * QC, L, nrb, w, lane);
+    if (qin && sub == 0) {
+        s.mpart[(size_t)pg * g.Qp + col0 + sq] = cok ? mrun : -INFINITY;
+        s.spart[(size_t)pg * g.Qp + col0 + sq] = cok ? (float)srun : 0.f;
+    }
+}
+
+template <int PP, int R, bool STEP>
+__global__ __launch_bounds__(64 * kBpassWaves, 1) void k_bpass_xs(Geom g, State s, const float* __restrict__ W,
+                                                                  int mode, RunInit ri) {
+    bpass_xs_body<PP, R, STEP>(g, s, blockIdx.x, W, mode, ri);
 }
 
 // --------------------------------------------------------------------------

@@ -34,6 +34,19 @@ struct Kernels {
         return hipGetLastError();
     }
     static hipError_t bpass(const Geom& g, const State& s, int mode, const RunInit& ri, hipStream_t st) {
+        if ((s.x_mfma & 1) && !s.x_bf16) {       // float32 X, three-term bf16 products
+            const size_t lds = xs_lds(PP, R, g.L).total;
+            if (mode == kModeStep) {
+                set_max_lds((const void*)k_bpass_xs<PP, R, true>, (int)lds);
+                hipLaunchKernelGGL((k_bpass_xs<PP, R, true>), dim3(g.npg * g.nqc), dim3(64 * kBpassWaves), lds, st, g,
+                                   s, (const float*)s.W, mode, ri);
+            } else {
+                set_max_lds((const void*)k_bpass_xs<PP, R, false>, (int)lds);
+                hipLaunchKernelGGL((k_bpass_xs<PP, R, false>), dim3(g.npg * g.nqc), dim3(64 * kBpassWaves), lds, st,
+                                   g, s, (const float*)s.W, mode, ri);
+            }
+            return hipGetLastError();
+        }
         if (s.x_mfma & 1) {
             const size_t lds = xb_lds(PP, R, g.L).total;
             if (mode == kModeStep) {

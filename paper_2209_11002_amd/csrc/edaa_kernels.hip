@@ -104,6 +104,10 @@ bool xb_fits(int p, int R, int L) {
     return L <= kXbMaxL && (size_t)xb_lds(p, R, L).total <= kMaxLdsBytes;
 }
 
+bool xs_fits(int p, int R, int L) {
+    return L <= kXbMaxL && (size_t)xs_lds(p, R, L).total <= kMaxLdsBytes;
+}
+
 // (above p = 12 the bf16 A-pass kernels spill registers to scratch: the
 // float64 A-pass serves those)
 bool xa_fits(int p, int R, int L) {

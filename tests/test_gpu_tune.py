@@ -82,5 +82,6 @@ def test_autotune_ragged_item_size_is_used(api):
     for k, ((L, N, p), r) in enumerate(zip(shapes, rr)):
         ntiles = (N + 63) // 64
         assert r["pixel_groups"] == (ntiles + tpi - 1) // tpi, k
-        one = api.fit(imgs[k], p, T=5, gamma=gammas[k], seed=seeds[k], pixel_groups=r["pixel_groups"])
+        one = api.fit(imgs[k], p, T=5, gamma=gammas[k], seed=seeds[k], pixel_groups=r["pixel_groups"],
+                      f32_mfma=True)
         assert torch.equal(r["A"], one["A"]) and np.array_equal(r["loss"], one["loss"]), k
