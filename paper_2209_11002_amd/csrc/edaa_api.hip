@@ -521,10 +521,14 @@ edaa_status run_sequence(edaa_ctx* ctx, const Seq& q, const void* X, int use_gra
 
 // bf16 X runs the B-pass (bit 0) and the A-pass (bit 1) on the bf16 matrix
 // cores unless the caller asks for the float32 ones or the chunk does not
-// fit the pass's LDS layout; float32 X runs its B-pass there (three-term
-// products) unless EDAA_FLAG_F32_MFMA asks for the float32 matrix cores.
+// fit the pass's LDS layout; float32 X runs its passes there (three-term
+// products; the A-pass up to p = 9) unless EDAA_FLAG_F32_MFMA asks for the
+// float32 (and float64) matrix cores.
 int use_xb(const Geom& g, int x_bytes, int flags) {
-    if (x_bytes == 4) return (!(flags & EDAA_FLAG_F32_MFMA) && xs_fits(g.p, g.R, g.L)) ? 1 : 0;
+    if (x_bytes == 4) {
+        if (flags & EDAA_FLAG_F32_MFMA) return 0;
+        return (xs_fits(g.p, g.R, g.L) ? 1 : 0) | (xas_fits(g.p, g.R, g.L) ? 2 : 0);
+    }
     if (flags & EDAA_FLAG_BF16_WIDEN) return 0;
     return (xb_fits(g.p, g.R, g.L) ? 1 : 0) | (xa_fits(g.p, g.R, g.L) ? 2 : 0);
 }

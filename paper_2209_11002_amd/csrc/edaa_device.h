@@ -30,6 +30,8 @@
 
 #include <math.h>
 
+#include <type_traits>
+
 #include "edaa_internal.h"
 namespace edaa {
 namespace {
@@ -50,6 +52,11 @@ constexpr int apass_waves(int p) { return p <= 9 ? 8 : 4; }
 // lanes reading their Gram rows from LDS, measured no faster: the A-steps
 // there are bound by vector-ALU throughput, not latency.)
 constexpr int xa_waves(int p) { return apass_waves(p); }
+// Chunks whose float32-X A-pass runs on the bf16 matrix cores (k_apass_xs):
+// up to p = 6 and three column blocks; the others need more than the 256
+// registers a wave has at eight waves per workgroup (the float32 tile staged
+// in registers takes 32) and keep the float64/float32 A-pass.
+constexpr bool xas_chunk(int p, int R) { return p <= 6 && (p * R + 15) / 16 <= 3; }
 constexpr int kXS = 68;   // LDS pitch (floats) of an X tile row of 64 pixels
 
 typedef float f4 __attribute__((ext_vector_type(4)));
@@ -1931,8 +1938,9 @@ __device__ __forceinline__ void xs_project(const float* Xf, const u32x4* Wsp, fl
 }
 
 // V += X_tile Wt on the bf16 matrix cores from the float32 X tile (xf) and the
-// split weights, folded into the float64 running sums like xb_accumulate.
-template <int NCB, int NRBW, int NW>
+// split weights, folded into the float64 running sums like xb_accumulate
+// (SCALE as there).
+template <int NCB, int NRBW, int NW, bool SCALE = true>
 __device__ __forceinline__ void xs_accumulate(d4 (&acc)[NRBW][NCB], const float* Xf, const u32x4* Wb, const float* F,
                                               const float* G, int nrb, int w, int lane) {
     const int m = lane & 15, kg = lane >> 4;
@@ -1986,10 +1994,12 @@ __device__ __forceinline__ void xs_accumulate(d4 (&acc)[NRBW][NCB], const float*
         }
     }
     float fs[NCB], gs[NCB];
+    if (SCALE) {
 #pragma unroll
-    for (int cb = 0; cb < NCB; ++cb) {
-        fs[cb] = F[16 * cb + m];
-        gs[cb] = G[16 * cb + m];
+        for (int cb = 0; cb < NCB; ++cb) {
+            fs[cb] = F[16 * cb + m];
+            gs[cb] = G[16 * cb + m];
+        }
     }
 #pragma unroll
     for (int j = 0; j < NRBW; ++j)
@@ -1998,7 +2008,8 @@ __device__ __forceinline__ void xs_accumulate(d4 (&acc)[NRBW][NCB], const float*
             for (int cb = 0; cb < NCB; ++cb)
 #pragma unroll
                 for (int v = 0; v < 4; ++v)
-                    acc[j][cb][v] = fma(acc[j][cb][v], (double)fs[cb], (double)t[j][cb][v] * (double)gs[cb]);
+                    acc[j][cb][v] = SCALE ? fma(acc[j][cb][v], (double)fs[cb], (double)t[j][cb][v] * (double)gs[cb])
+                                          : acc[j][cb][v] + (double)t[j][cb][v];
 }
 
 template <int PP, int R, bool STEP>
@@ -2273,6 +2284,71 @@ __device__ __forceinline__ double xa_project(const u32x4* Xo, const u32x4* Esp, 
     return xx;
 }
 
+// The same projection from a float32 X tile (xf, read and split as in
+// xs_project, E in the band order of xs_band): six products per block of 32
+// bands, summed in float32 by the matrix core and folded into float64.
+template <int NC, int CB0, int NCB, int WTS>
+__device__ __forceinline__ double xs_pa_project(const float* Xf, const u32x4* Esp, float* Phi, float* Plo, int nkb,
+                                                int pb, int lane) {
+    const int m = lane & 15, kg = lane >> 4;
+    d4 s[NC];
+    f4 tp[NC];
+#pragma unroll
+    for (int cb = 0; cb < NC; ++cb) {
+        s[cb] = d4{0.0, 0.0, 0.0, 0.0};
+        tp[cb] = f4{0.f, 0.f, 0.f, 0.f};
+    }
+    double xx = 0.0;
+    auto step = [&](const XsOps<NC>& o) {
+        u32x4 xt[3];
+        split8_bf16x3(o.x, xt);
+        f4 t[NC], t2[NC];
+#pragma unroll
+        for (int cb = 0; cb < NC; ++cb) t[cb] = t2[cb] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int u = 0; u < 6; ++u)
+#pragma unroll
+            for (int cb = 0; cb < NC; ++cb) {
+                // with one column block alternate products go to a second chain
+                if (NC == 1 && (u & 1))
+                    t2[cb] = mfma16_bf16(o.e[cb][x6b(u)], xt[x6a(u)], t2[cb]);
+                else
+                    t[cb] = mfma16_bf16(o.e[cb][x6b(u)], xt[x6a(u)], t[cb]);
+            }
+        // while those run: this lane's 8 bands of ||x||^2 and the fold of
+        // the previous block
+#pragma unroll
+        for (int j = 0; j < 8; ++j) xx = fma((double)o.x[j], (double)o.x[j], xx);
+#pragma unroll
+        for (int cb = 0; cb < NC; ++cb) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) s[cb][v] += (double)tp[cb][v];
+            tp[cb] = NC == 1 ? t[cb] + t2[cb] : t[cb];
+        }
+    };
+    XsOps<NC> o0, o1;
+    o0.template load<CB0, NCB>(Xf, Esp, 0, pb, lane);
+    int kb = 0;
+    for (; kb + 1 < nkb; kb += 2) {
+        o1.template load<CB0, NCB>(Xf, Esp, kb + 1, pb, lane);
+        step(o0);
+        o0.template load<CB0, NCB>(Xf, Esp, (kb + 2 < nkb) ? kb + 2 : kb, pb, lane);
+        step(o1);
+    }
+    if (kb < nkb) step(o0);
+#pragma unroll
+    for (int cb = 0; cb < NC; ++cb)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const double P = s[cb][v] + (double)tp[cb][v];
+            const float hi = (float)P;
+            const int idx = (16 * pb + m) * WTS + 16 * (CB0 + cb) + 4 * kg + v;
+            Phi[idx] = hi;
+            Plo[idx] = (float)(P - (double)hi);
+        }
+    return xx;
+}
+
 // A A^T blocks (qb, qb) and (qb, qb + 1) of the tile on the float32 matrix
 // cores, from the abundances Wt [64][WTS], folded into float64 (the Gram part
 // of mfma_accumulate).
@@ -2294,7 +2370,7 @@ __device__ __forceinline__ void mfma_gram(d4 (&gram)[NGBW], const float* Wt, int
     }
 }
 
-template <int PP, int R>
+template <int PP, int R, bool XF = false>
 __device__ __forceinline__ void apass_xb_body(const Geom& g, const State& s, int bid, const float* __restrict__ E,
                                               int K1) {
     using S = Shape<PP, R>;
@@ -2311,6 +2387,7 @@ __device__ __forceinline__ void apass_xb_body(const Geom& g, const State& s, int
     constexpr int NRBW = S::NRBW * 4 / NW;
     constexpr int NGBW = (S::NGB + NW - 1) / NW;
     constexpr int NC0 = (NW == 8) ? (NCB + 1) / 2 : NCB, NC1 = NCB - NC0;
+    static_assert(!XF || NW == 8, "float32 X tiles are staged by eight waves");
     extern __shared__ float smem[];
     char* const lds = (char*)smem;
     const int L = g.L, N = g.N, nkb = (L + 31) >> 5, nrb = (L + 15) >> 4;
@@ -2318,6 +2395,7 @@ __device__ __forceinline__ void apass_xb_body(const Geom& g, const State& s, int
     const XaLds lo = xa_lds(PP, R, L, gfx ? 1 : 0);
     uint16_t* Xn = (uint16_t*)(lds + lo.xn);
     u32x4* Xo = (u32x4*)(lds + lo.xo);
+    float* Xf = (float*)(lds + lo.xn);          // float32 X: [LP32][kXS] over xn and xo
     u32x4* Esp = (u32x4*)(lds + lo.esp);
     float* Wt = (float*)(lds + lo.wt);
     float* Plo = (float*)(lds + lo.plo);
@@ -2333,14 +2411,18 @@ __device__ __forceinline__ void apass_xb_body(const Geom& g, const State& s, int
     const int col0 = c * QC;
     float* __restrict__ A = s.A;
 
-    // E[:, chunk] as MFMA A operands (three bf16 terms), and the Gram
-    // matrices in float64 from the float32 E
+    // E[:, chunk] as MFMA A operands (three bf16 terms; float32 X: bands in
+    // the order of xs_band), and the Gram matrices in float64 from the
+    // float32 E
     for (int e = tid; e < nkb * NCB * 64; e += NT) {
         const int ln = e & 63, kc = e >> 6;
-        const int q = 16 * (kc % NCB) + (ln & 15), r0 = 32 * (kc / NCB) + 8 * (ln >> 4);
+        const int q = 16 * (kc % NCB) + (ln & 15), r0 = 32 * (kc / NCB);
         float x[8];
 #pragma unroll
-        for (int j = 0; j < 8; ++j) x[j] = (r0 + j < L && q < QC) ? E[(size_t)(r0 + j) * g.Qp + col0 + q] : 0.f;
+        for (int j = 0; j < 8; ++j) {
+            const int r = r0 + (XF ? xs_band(ln >> 4, j) : 8 * (ln >> 4) + j);
+            x[j] = (r < L && q < QC) ? E[(size_t)r * g.Qp + col0 + q] : 0.f;
+        }
         u32x4 h, md, lw;
         split_bf16x3(x, h, md, lw);
         Esp[(kc * 3 + 0) * 64 + ln] = h;
@@ -2361,8 +2443,11 @@ __device__ __forceinline__ void apass_xb_body(const Geom& g, const State& s, int
             if (gfx) Gf[e0] = (float)acc;
         }
     }
-    // the weight padding columns (never written later)
+    // the weight padding columns (never written later); float32 X: the rows
+    // L .. 32 nkb - 1 of the tile (never written later)
     for (int e = tid; e < kTile * WTS; e += NT) Wt[e] = 0.f;
+    if (XF)
+        for (int e = tid; e < (32 * nkb - L) * kXS; e += NT) Xf[L * kXS + e] = 0.f;
     __syncthreads();
 
     d4 acc[NRBW][NCB], gram[NGBW];
@@ -2388,7 +2473,13 @@ __device__ __forceinline__ void apass_xb_body(const Geom& g, const State& s, int
             }
     }
 
-    XbStage<NW> xs;
+    std::conditional_t<XF, XfStage<NW>, XbStage<NW>> xs;
+    auto stage_store = [&]() {
+        if constexpr (XF)
+            xs.store(Xf, L);
+        else
+            xs.store(Xn, Xo, L);
+    };
     float an[RW][PP];
     float ano[JW];
     auto load_a = [&](int tile) {
@@ -2410,8 +2501,8 @@ __device__ __forceinline__ void apass_xb_body(const Geom& g, const State& s, int
         }
     };
     if (pg < g.ntiles) {
-        xs.issue(s.X, s.ldx, L, pg);
-        xs.store(Xn, Xo, L);
+        xs.issue((const std::conditional_t<XF, float, void>*)s.X, s.ldx, L, pg);
+        stage_store();
         load_a(pg);
     }
     for (int tile = pg; tile < g.ntiles; tile += g.npg) {
@@ -2439,17 +2530,21 @@ __device__ __forceinline__ void apass_xb_body(const Geom& g, const State& s, int
         const int nt = tile + g.npg;
         if (nt < g.ntiles) {
             load_a(nt);
-            xs.issue(s.X, s.ldx, L, nt);
+            xs.issue((const std::conditional_t<XF, float, void>*)s.X, s.ldx, L, nt);
         }
         // projection: P for pixels 16w..16w+15 (16 (w - 4).. with eight
         // waves, w >= 4, which take the last NC1 column blocks)
         if (w < 4) {
-            double xx = xa_project<NC0, 0, NCB, WTS>(Xo, Esp, Wt, Plo, nkb, w, lane);
+            double xx = XF ? xs_pa_project<NC0, 0, NCB, WTS>(Xf, Esp, Wt, Plo, nkb, w, lane)
+                           : xa_project<NC0, 0, NCB, WTS>(Xo, Esp, Wt, Plo, nkb, w, lane);
             xx += __shfl_xor(xx, 16);
             xx += __shfl_xor(xx, 32);
             if (lane < 16) XX[16 * w + lane] = xx;
         } else if constexpr (NC1 > 0) {
-            (void)xa_project<NC1, NC0, NCB, WTS>(Xo, Esp, Wt, Plo, nkb, w - 4, lane);
+            if constexpr (XF)
+                (void)xs_pa_project<NC1, NC0, NCB, WTS>(Xf, Esp, Wt, Plo, nkb, w - 4, lane);
+            else
+                (void)xa_project<NC1, NC0, NCB, WTS>(Xo, Esp, Wt, Plo, nkb, w - 4, lane);
         }
         lds_barrier();
         if constexpr (SPLIT) {
@@ -2539,11 +2634,14 @@ __device__ __forceinline__ void apass_xb_body(const Geom& g, const State& s, int
             Wb[(pc * 3 + 2) * 64 + sl] = lw;
         }
         lds_barrier();
-        xb_accumulate<NCB, NRBW, NW, false>(acc, Xn, Wb, nullptr, nullptr, nrb, w, lane);
+        if constexpr (XF)
+            xs_accumulate<NCB, NRBW, NW, false>(acc, Xf, Wb, nullptr, nullptr, nrb, w, lane);
+        else
+            xb_accumulate<NCB, NRBW, NW, false>(acc, Xn, Wb, nullptr, nullptr, nrb, w, lane);
         mfma_gram<NCB, NGBW, WTS, NW>(gram, Wt, w, lane);
         if (nt < g.ntiles) {
             lds_barrier();                         // every wave is done with this tile's X and weights
-            xs.store(Xn, Xo, L);
+            stage_store();
         }
     }
 
@@ -2594,6 +2692,16 @@ template <int PP, int R>
 __global__ __launch_bounds__(64 * xa_waves(PP), 1) void k_apass_xb(Geom g, State s, const float* __restrict__ E,
                                                                       int K1) {
     apass_xb_body<PP, R>(g, s, blockIdx.x, E, K1);
+}
+
+// The A-pass for float32 X on the bf16 matrix cores (eight-wave kernels, p <=
+// 9): the X tile kept once in float32 (XfStage, same LDS bytes as the two bf16
+// layouts), the projection and X A^T with both operands in three bf16 terms
+// and six products (xs_pa_project, xs_accumulate).
+template <int PP, int R>
+__global__ __launch_bounds__(64 * xa_waves(PP), 1) void k_apass_xs(Geom g, State s, const float* __restrict__ E,
+                                                                      int K1) {
+    apass_xb_body<PP, R, true>(g, s, blockIdx.x, E, K1);
 }
 
 // --------------------------------------------------------------------------

@@ -17,6 +17,16 @@ static_assert(PP >= 1 && PP <= kMaxP, "EDAA_INST_P out of range");
 template <int R>
 struct Kernels {
     static hipError_t apass(const Geom& g, const State& s, int K1, hipStream_t st) {
+        if constexpr (xas_chunk(PP, R)) {   // xas_fits: the float32-X A-pass
+            if ((s.x_mfma & 2) && !s.x_bf16) {
+                const bool gf = (size_t)xa_lds(PP, R, g.L, 1).total <= kMaxLdsBytes;
+                const size_t lds = xa_lds(PP, R, g.L, gf ? 1 : 0).total;
+                set_max_lds((const void*)k_apass_xs<PP, R>, (int)lds);
+                hipLaunchKernelGGL((k_apass_xs<PP, R>), dim3(g.npg * g.nqc), dim3(64 * xa_waves(PP)), lds, st, g,
+                                   s, (const float*)s.E, K1);
+                return hipGetLastError();
+            }
+        }
         if constexpr (PP <= 12) {          // xa_fits: the bf16 A-pass up to p = 12
             if (s.x_mfma & 2) {
                 const bool gf = (size_t)xa_lds(PP, R, g.L, 1).total <= kMaxLdsBytes;

@@ -83,7 +83,7 @@ struct State {
     size_t ldx;         // ntiles * 64
     int x_bf16;
     int x_mfma;         // passes on the bf16 matrix cores: bit 0 the B-pass (k_bpass_xb for bf16 X,
-                        // k_bpass_xs for float32 X), bit 1 the A-pass (bf16 X)
+                        // k_bpass_xs for float32 X), bit 1 the A-pass (k_apass_xb, k_apass_xs)
     float* A;           // [Q][N] abundances (the caller's A_all)
     float* Bst;         // [Q][ntiles * 64] unnormalised pixel weights (pixels >= N: zero)
     float* tshift;      // [ntiles][Qp] shift used when a tile of Bst was written
@@ -278,8 +278,10 @@ bool runs_fit(int p, int R, int L);
 // limits).
 bool xb_fits(int p, int R, int L);
 bool xa_fits(int p, int R, int L);
-// Whether the float32-X B-pass on the bf16 matrix cores (k_bpass_xs) fits.
+// Whether the float32-X B-pass (k_bpass_xs) or A-pass (k_apass_xs, xas_chunk)
+// on the bf16 matrix cores fits.
 bool xs_fits(int p, int R, int L);
+bool xas_fits(int p, int R, int L);
 // Default runs per chunk for M runs (1 when M = 1 or when nothing else fits).
 int runs_per_chunk(int p, int M, int L);
 // Geometry with R runs per chunk and npg pixel groups (0: defaults).

@@ -108,6 +108,10 @@ bool xs_fits(int p, int R, int L) {
     return L <= kXbMaxL && (size_t)xs_lds(p, R, L).total <= kMaxLdsBytes;
 }
 
+bool xas_fits(int p, int R, int L) {
+    return xas_chunk(p, R) && L <= kXbMaxL && (size_t)xa_lds(p, R, L, 0).total <= kMaxLdsBytes;
+}
+
 // (above p = 12 the bf16 A-pass kernels spill registers to scratch: the
 // float64 A-pass serves those)
 bool xa_fits(int p, int R, int L) {

@@ -173,11 +173,12 @@ def test_bf16_matrix_path_vs_oracle(api, L, N, p, M, T):
     (300, 600, 4, 4, 5),     # L > 256: the float32 matrix-core B-pass serves
 ])
 def test_f32_split_path_vs_oracle(api, L, N, p, M, T):
-    """float32 X runs its B-pass on the bf16 matrix cores with both operands
-    in three bf16 terms (the default up to L = 256): against the oracle at the
-    float32 gates, and against the float32 matrix-core B-pass (f32_mfma),
-    which must agree to float32 rounding but not be identical (a check that
-    the split path ran); above L = 256 the two are the same kernels."""
+    """float32 X runs its B-pass (and, up to p = 6 and three column blocks,
+    its A-pass) on the bf16 matrix cores with both operands in three bf16
+    terms (the default up to L = 256): against the oracle at the float32
+    gates, and against the float32 matrix-core passes (f32_mfma), which must
+    agree to float32 rounding but not be identical (a check that the split
+    path ran); above L = 256 the two are the same kernels."""
     _say(f"float32 split path L={L} N={N} p={p} M={M} T={T}")
     s = synth.small_case(seed=41 if L == 1 else 90 + L, L=L, N=N, p=min(p, max(1, L)))
     Xg, X = _prep(s.X)
