@@ -121,6 +121,12 @@ typedef struct {
     int pixel_groups;        /* workgroups per chunk (each strides over tiles)   */
     int double_buffer;       /* 1: the next X tile loads while one is processed  */
     int source;              /* EDAA_PLAN_DEFAULT, _TUNED or _REQUESTED          */
+    int bf16_passes;         /* passes on the bf16 matrix cores: bit 0 the B-pass,
+                                bit 1 the A-pass (bf16 X tiles; float32 X with
+                                its operands in three bf16 terms, where a chunk
+                                has at least two column blocks of 16 runs x
+                                endmembers); 0: the float32 (and float64)
+                                matrix-core passes                            */
 } edaa_launch_plan;
 enum { EDAA_PLAN_DEFAULT = 0, EDAA_PLAN_TUNED = 1, EDAA_PLAN_REQUESTED = 2 };
 

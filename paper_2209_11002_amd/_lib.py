@@ -39,7 +39,7 @@ class EdaaImageDesc(ctypes.Structure):
 
 class EdaaLaunchPlan(ctypes.Structure):
     _fields_ = [("runs_per_chunk", c_int), ("chunks", c_int), ("pixel_groups", c_int),
-                ("double_buffer", c_int), ("source", c_int)]
+                ("double_buffer", c_int), ("source", c_int), ("bf16_passes", c_int)]
 
 
 EDAA_PLAN_DEFAULT, EDAA_PLAN_TUNED, EDAA_PLAN_REQUESTED = 0, 1, 2

@@ -320,7 +320,7 @@ def autotune(X, p, M=1, K1=5, K2=5, gamma=1.0):
     us = c_double(0.0)
     check(L_.load().edaa_autotune(_ctx(X.device), _ptr(X), Lb, N, int(p), int(M), byref(P), byref(best), byref(us)))
     return dict(runs_per_chunk=best.runs_per_chunk, chunks=best.chunks, pixel_groups=best.pixel_groups,
-                double_buffer=best.double_buffer, source="tuned"), us.value
+                double_buffer=best.double_buffer, source="tuned", bf16_passes=best.bf16_passes), us.value
 
 
 def autotune_ragged(images, ps, seeds, gammas, K1=5, K2=5):
@@ -336,16 +336,19 @@ def autotune_ragged(images, ps, seeds, gammas, K1=5, K2=5):
     return tpi.value, us.value
 
 
-def plan(L, N, p, M=1, runs_per_chunk=0, pixel_groups=0, x_dtype=torch.float32):
+def plan(L, N, p, M=1, runs_per_chunk=0, pixel_groups=0, x_dtype=torch.float32, bf16_widen=False,
+         f32_mfma=False):
     """Launch shape that fit (M = 1) or ensemble (M runs) would use: a dict
-    with runs_per_chunk, chunks, pixel_groups, double_buffer and source
-    ('default', 'tuned' or 'requested').  Host only."""
+    with runs_per_chunk, chunks, pixel_groups, double_buffer, source
+    ('default', 'tuned' or 'requested') and bf16_passes (bit 0: the B-pass,
+    bit 1: the A-pass on the bf16 matrix cores).  Host only."""
     P = _params(1, 1, 1, 1.0, None, 0.1, 1.05, L_.EDAA_X_BF16 if x_dtype == torch.bfloat16 else L_.EDAA_X_F32,
-                "cosine", False, runs_per_chunk=runs_per_chunk, pixel_groups=pixel_groups)
+                "cosine", False, runs_per_chunk=runs_per_chunk, pixel_groups=pixel_groups, bf16_widen=bf16_widen,
+                f32_mfma=f32_mfma)
     out = L_.EdaaLaunchPlan()
     check(L_.load().edaa_plan(int(L), int(N), int(p), int(M), byref(P), byref(out)))
     return dict(runs_per_chunk=out.runs_per_chunk, chunks=out.chunks, pixel_groups=out.pixel_groups,
-                double_buffer=out.double_buffer,
+                double_buffer=out.double_buffer, bf16_passes=out.bf16_passes,
                 source={L_.EDAA_PLAN_DEFAULT: "default", L_.EDAA_PLAN_TUNED: "tuned",
                         L_.EDAA_PLAN_REQUESTED: "requested"}[out.source])
 

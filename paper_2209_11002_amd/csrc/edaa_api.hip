@@ -521,12 +521,14 @@ edaa_status run_sequence(edaa_ctx* ctx, const Seq& q, const void* X, int use_gra
 
 // bf16 X runs the B-pass (bit 0) and the A-pass (bit 1) on the bf16 matrix
 // cores unless the caller asks for the float32 ones or the chunk does not
-// fit the pass's LDS layout; float32 X runs its passes there (three-term
-// products; the A-pass up to p = 9) unless EDAA_FLAG_F32_MFMA asks for the
-// float32 (and float64) matrix cores.
+// fit the pass's LDS layout.  float32 X runs its passes there (three-term
+// products; the A-pass where xas_chunk allows) when the chunk has at least
+// two column blocks, over which the split of each X value is shared (with one
+// column block the float32 matrix-core passes are faster), unless
+// EDAA_FLAG_F32_MFMA asks for the float32 (and float64) matrix cores.
 int use_xb(const Geom& g, int x_bytes, int flags) {
     if (x_bytes == 4) {
-        if (flags & EDAA_FLAG_F32_MFMA) return 0;
+        if ((flags & EDAA_FLAG_F32_MFMA) || (g.p * g.R + 15) / 16 < 2) return 0;
         return (xs_fits(g.p, g.R, g.L) ? 1 : 0) | (xas_fits(g.p, g.R, g.L) ? 2 : 0);
     }
     if (flags & EDAA_FLAG_BF16_WIDEN) return 0;
@@ -1075,6 +1077,7 @@ edaa_status edaa_plan(int L, int N, int p, int M, const edaa_params* params, eda
     out->pixel_groups = g.npg;
     out->double_buffer = g.dbuf;
     out->source = source;
+    out->bf16_passes = use_xb(g, params->x_dtype == EDAA_X_BF16 ? 2 : 4, params->flags);
     return EDAA_OK;
 }
 
@@ -1372,6 +1375,7 @@ edaa_status edaa_autotune(edaa_ctx* ctx, const void* X, int L, int N, int p, int
         best->pixel_groups = g.npg;
         best->double_buffer = g.dbuf;
         best->source = EDAA_PLAN_TUNED;
+        best->bf16_passes = use_xb(g, params->x_dtype == EDAA_X_BF16 ? 2 : 4, params->flags);
     }
     if (best_us) *best_us = bus;
     return EDAA_OK;

@@ -163,27 +163,31 @@ def test_bf16_matrix_path_vs_oracle(api, L, N, p, M, T):
 
 @gpu
 @pytest.mark.parametrize("L,N,p,M,T", [
-    (64, 900, 5, 1, 8),      # one run: one column block, k blocks split between the wave groups
+    (64, 900, 5, 1, 8),      # one run, one column block: the float32 matrix-core passes serve
     (162, 1000, 6, 10, 6),   # 8 runs per chunk: three column blocks, k blocks split, L not a multiple of 32
+    (64, 900, 5, 4, 6),      # 4 runs per chunk: two column blocks, k blocks split
     (224, 2048, 12, 4, 6),   # three column blocks without room for the second projection buffer
     (256, 700, 16, 2, 5),    # the largest L of the path, two column blocks
-    (1, 100, 2, 1, 6),       # a single band: one k block of 32 with 31 zero bands
+    (1, 100, 2, 10, 6),      # a single band: one k block of 32 with 31 zero bands
     (30, 50, 3, 10, 5),      # fewer pixels than one tile, 20 runs per chunk (four column blocks)
-    (156, 2500, 3, 1, 6),    # one run, three endmembers
-    (300, 600, 4, 4, 5),     # L > 256: the float32 matrix-core B-pass serves
+    (156, 2500, 3, 8, 6),    # two column blocks at p = 3
+    (300, 600, 4, 8, 5),     # L > 256: the float32 matrix-core passes serve
 ])
 def test_f32_split_path_vs_oracle(api, L, N, p, M, T):
-    """float32 X runs its B-pass (and, up to p = 6 and three column blocks,
-    its A-pass) on the bf16 matrix cores with both operands in three bf16
-    terms (the default up to L = 256): against the oracle at the float32
-    gates, and against the float32 matrix-core passes (f32_mfma), which must
-    agree to float32 rounding but not be identical (a check that the split
-    path ran); above L = 256 the two are the same kernels."""
+    """float32 X runs its B-pass (and, up to p = 6, its A-pass) on the bf16
+    matrix cores with both operands in three bf16 terms when a chunk has at
+    least two column blocks and L <= 256 (plan()'s bf16_passes says which):
+    against the oracle at the float32 gates, and against the float32
+    matrix-core passes (f32_mfma), which must agree to float32 rounding and
+    differ exactly when the plan names a bf16 pass (a check of which
+    kernels ran)."""
     _say(f"float32 split path L={L} N={N} p={p} M={M} T={T}")
     s = synth.small_case(seed=41 if L == 1 else 90 + L, L=L, N=N, p=min(p, max(1, L)))
     Xg, X = _prep(s.X)
     seeds = [m // 2 for m in range(M)]
     gammas = [(0.5, 1.0)[m % 2] for m in range(M)]
+    passes = api.plan(L, N, p, M)["bf16_passes"]
+    assert api.plan(L, N, p, M, f32_mfma=True)["bf16_passes"] == 0
     if M == 1:
         one = api.fit(Xg, p, T=T, gamma=gammas[0], seed=seeds[0])
         ref32 = api.fit(Xg, p, T=T, gamma=gammas[0], seed=seeds[0], f32_mfma=True)
@@ -199,10 +203,9 @@ def test_f32_split_path_vs_oracle(api, L, N, p, M, T):
         A_err = np.max(np.abs(_np(r["A"][m]) - ref["A"]))
         NB_err = N * np.max(np.abs(_np(r["B"][m]) - ref["B"]))
         dw = np.max(np.abs(r["loss"][m] - rw["loss"][m]) / np.maximum(rw["loss"][m], floor))
-        _say(f"run {m}: vs oracle loss {rel:.2e} A {A_err:.2e} N*B {NB_err:.2e}; vs float32 matrix path {dw:.2e}")
+        _say(f"run {m} (bf16 passes {passes}): vs oracle loss {rel:.2e} A {A_err:.2e} N*B {NB_err:.2e}; "
+             f"vs float32 matrix path {dw:.2e}")
         assert rel <= 1e-4 and A_err <= 1e-3 and NB_err <= 1e-2
         assert dw <= 1e-4
-    if 1 < L <= 256:
-        assert not np.array_equal(r["loss"], rw["loss"])
-    elif L > 256:
-        assert np.array_equal(r["loss"], rw["loss"]) and torch.equal(r["A"], rw["A"])
+    same = np.array_equal(r["loss"], rw["loss"]) and torch.equal(r["A"], rw["A"])
+    assert same == (passes == 0)

@@ -102,3 +102,24 @@ def test_tuned_shapes_are_read_from_the_cache_file(tmp_path):
     assert other_m["source"] == "default"                      # another M is another class
     assert (other_n["source"], other_n["runs_per_chunk"], other_n["pixel_groups"]) == ("tuned", 8, 7)
     assert requested["source"] == "requested" and requested["runs_per_chunk"] == 8
+
+
+def test_bf16_matrix_passes_policy():
+    """Which passes run on the bf16 matrix cores.  float32 X: the B-pass
+    (operands in three bf16 terms) when a chunk has at least two 16-column
+    blocks and L <= 256, the A-pass too up to p = 6 and three column blocks;
+    single runs (one column block) keep the float32 matrix-core passes, as
+    does EDAA_FLAG_F32_MFMA.  bf16 X: both passes up to p = 12 and L = 256
+    (the B-pass above p = 12), none with EDAA_FLAG_BF16_WIDEN."""
+    import torch
+    bf = torch.bfloat16
+    for L, N, p, M, want in [(162, 94249, 6, 50, 3), (162, 94249, 6, 1, 0), (224, 314368, 12, 20, 1),
+                             (224, 314368, 12, 1, 0), (64, 900, 5, 4, 3), (30, 50, 3, 10, 1), (256, 700, 16, 2, 1),
+                             (257, 700, 4, 8, 0), (300, 600, 4, 8, 0)]:
+        pl = api.plan(L, N, p, M)
+        assert pl["bf16_passes"] == want, (L, N, p, M, pl)
+        assert api.plan(L, N, p, M, f32_mfma=True)["bf16_passes"] == 0
+    for L, N, p, M, want in [(162, 94249, 6, 1, 3), (224, 314368, 12, 20, 3), (256, 700, 16, 2, 1),
+                             (257, 700, 4, 8, 0)]:
+        assert api.plan(L, N, p, M, x_dtype=bf)["bf16_passes"] == want, (L, N, p, M)
+        assert api.plan(L, N, p, M, x_dtype=bf, bf16_widen=True)["bf16_passes"] == 0
