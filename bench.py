@@ -30,6 +30,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 FP32_MFMA_TFLOPS = 157.3          # MI355X dense FP32 matrix peak (v_mfma_f32_16x16x4f32: 32 cycles/SIMD)
+BF16_MFMA_TFLOPS = 2500.0         # MI355X dense bf16 matrix peak (v_mfma_f32_16x16x32_bf16: 16 cycles/SIMD)
 HBM_GBS = 8000.0
 PROFILES = os.path.join(ROOT, "profiles")
 TRAFFIC_FILE = os.path.join(PROFILES, "k_bpass_urban_ensemble_traffic.txt")
@@ -511,13 +512,23 @@ def main():
     b_avg_s = b_ms / max(b_n, 1) / 1e3
     a_avg_s = a_ms / max(a_n, 1) / 1e3
     achieved = bpass_flops / b_avg_s / 1e12
+    R = plan["runs_per_chunk"]
+    split_b, split_a = bool(plan["bf16_passes"] & 1), bool(plan["bf16_passes"] & 2)
     roofline = dict(bound="mfma", achieved=round(achieved, 3), peak=FP32_MFMA_TFLOPS, unit="TFLOP/s",
                     frac=round(achieved / FP32_MFMA_TFLOPS, 4),
                     traffic=stored_traffic(TRAFFIC_FILE, f"{plan['runs_per_chunk']},{plan['pixel_groups']}"),
-                    kernel="k_bpass (B-pass)", avg_launch_us=round(b_avg_s * 1e6, 2),
+                    kernel=(f"k_bpass_xs<{p}, {R}, true> (B-pass; float32 products as six bf16 matrix-core products)"
+                            if split_b else f"k_bpass<{p}, {R}, true> (B-pass on the float32 matrix cores)"),
+                    avg_launch_us=round(b_avg_s * 1e6, 2),
                     algorithmic_bytes_per_launch=bpass_bytes, flops_per_launch=bpass_flops,
                     achieved_gbs=round(bpass_bytes / b_avg_s / 1e9, 1),
+                    apass_kernel=f"k_apass_xs<{p}, {R}>" if split_a else f"k_apass<{p}, {R}>",
                     apass_avg_launch_us=round(a_avg_s * 1e6, 2))
+    if split_b:
+        # the same float32 work priced at the kernel's own matrix-core
+        # ceiling: six bf16 products per float32 product
+        roofline["bf16x6_peak_tflops"] = round(BF16_MFMA_TFLOPS / 6, 1)
+        roofline["frac_of_bf16x6_peak"] = round(achieved / (BF16_MFMA_TFLOPS / 6), 4)
     final_loss_batched = r["loss"][:, -1].copy()
     log(f"batched: {value:.1f} run-it/s, {ms_per_step:.1f} ms/step, B-pass {b_avg_s * 1e6:.1f} us")
 

@@ -2070,11 +2070,15 @@ __device__ __forceinline__ void bpass_xs_body(const Geom& g, const State& s, int
     const bool qin = sq < QC;
     const bool cok = qin && sm < g.M;
     float* bcol = s.Bst + (size_t)(cok ? col0 + sq : 0) * Np + SPX * sub;
+    // the softmax works with log weights in base 2 (v / ln 2), so that log and
+    // exp are the hardware's log2 and exp2 with one multiply per column and
+    // tile; mrun and the shifts written out are converted back
+    constexpr float kLog2e = 1.4426950408889634f, kLn2 = 0.6931471805599453f;
     float mrun = -INFINITY, lzc = 0.f, eta2 = 0.f;
     double srun = 0.0;
     if (STEP && cok) {
         lzc = -s.colm[col0 + sq] - logf(s.cols[col0 + sq]);
-        eta2 = s.eta[2 * sm + 1];
+        eta2 = s.eta[2 * sm + 1] * kLog2e;
     }
 
     d4 acc[NRBW][NCB];
@@ -2129,39 +2133,47 @@ __device__ __forceinline__ void bpass_xs_body(const Geom& g, const State& s, int
             const int pix0 = tile * kTile + SPX * sub;
             float v[SPX];
             if (STEP) {
-                const float sh = ts + lzc;
+                const float sh = (ts + lzc) * kLog2e;
                 const float* grow = Sq + sq * kXS + SPX * sub;
 #pragma unroll
                 for (int u = 0; u < SV; ++u) {
                     f4 gv = *(const f4*)(grow + 4 * u);
                     if (ksplit) gv += *(const f4*)(grow - Sq + Sq2 + 4 * u);
 #pragma unroll
-                    for (int e = 0; e < 4; ++e) v[4 * u + e] = fast_log(bv[u][e]) + sh - eta2 * gv[e];
+                    for (int e = 0; e < 4; ++e) v[4 * u + e] = __builtin_amdgcn_logf(bv[u][e]) + fmaf(-eta2, gv[e], sh);
                 }
             } else if (mode == kModeInitRng) {
                 const uint64_t seed = ri.seeds[cok ? sm : 0];
+                const float sc = ri.init_scale * kLog2e;
 #pragma unroll
-                for (int i = 0; i < SPX; ++i) v[i] = ri.init_scale * uniform_u(seed, pix0 + i, sj);
+                for (int i = 0; i < SPX; ++i) v[i] = sc * uniform_u(seed, pix0 + i, sj);
             } else {
 #pragma unroll
-                for (int i = 0; i < SPX; ++i) v[i] = fast_log(ri.B0[(size_t)min(pix0 + i, N - 1) * PP + sj]);
+                for (int i = 0; i < SPX; ++i) v[i] = __builtin_amdgcn_logf(ri.B0[(size_t)min(pix0 + i, N - 1) * PP + sj]);
             }
-            float mx = -INFINITY;
+            // padding runs, and pixels past N in the last tile, take no weight
+            if (!cok) {
 #pragma unroll
-            for (int i = 0; i < SPX; ++i) {
-                v[i] = (cok && pix0 + i < N) ? v[i] : -INFINITY;
-                mx = fmaxf(mx, v[i]);
+                for (int i = 0; i < SPX; ++i) v[i] = -INFINITY;
+            } else if (pix0 + SPX > N) {
+#pragma unroll
+                for (int i = 0; i < SPX; ++i)
+                    if (pix0 + i >= N) v[i] = -INFINITY;
             }
+            float mx = v[0];
+#pragma unroll
+            for (int i = 1; i < SPX; ++i) mx = fmaxf(mx, v[i]);
             mx = fmaxf(mx, dpp<0xB1>(mx));
             mx = fmaxf(mx, dpp<0x4E>(mx));
             mx = fmaxf(mx, dpp<0x141>(mx));
             const float mnew = fmaxf(mrun, mx);
-            const float f = (mrun == -INFINITY) ? 0.f : fast_exp(mrun - mnew);
-            const float fg = (mx == -INFINITY) ? 0.f : fast_exp(mx - mnew);
+            const float f = (mrun == -INFINITY) ? 0.f : __builtin_amdgcn_exp2f(mrun - mnew);
+            const float fg = (mx == -INFINITY) ? 0.f : __builtin_amdgcn_exp2f(mx - mnew);
+            const float mxs = (mx == -INFINITY) ? 0.f : mx;     // exp2(-inf - mxs) = 0
             float wv[SPX], sum = 0.f;
 #pragma unroll
             for (int i = 0; i < SPX; ++i) {
-                wv[i] = (v[i] == -INFINITY) ? 0.f : fast_exp(v[i] - mx);
+                wv[i] = __builtin_amdgcn_exp2f(v[i] - mxs);
                 sum += wv[i];
             }
             sum += dpp<0xB1>(sum);
@@ -2185,7 +2197,7 @@ __device__ __forceinline__ void bpass_xs_body(const Geom& g, const State& s, int
             if (sub == 0) {
                 F[sq] = f;
                 FG[sq] = fg;
-                if (cok) s.tshift[(size_t)tile * g.Qp + col0 + sq] = mx;
+                if (cok) s.tshift[(size_t)tile * g.Qp + col0 + sq] = mx * kLn2;
             }
         }
         lds_barrier();
@@ -2199,7 +2211,7 @@ __device__ __forceinline__ void bpass_xs_body(const Geom& g, const State& s, int
     const size_t wgi = (size_t)pg * g.nqc + c;
     store_acc<NCB, NRBW, QC, NW>(acc, s.Vpart + wgi * (size_t)L * QC, L, nrb, w, lane);
     if (qin && sub == 0) {
-        s.mpart[(size_t)pg * g.Qp + col0 + sq] = cok ? mrun : -INFINITY;
+        s.mpart[(size_t)pg * g.Qp + col0 + sq] = cok ? mrun * kLn2 : -INFINITY;
         s.spart[(size_t)pg * g.Qp + col0 + sq] = cok ? (float)srun : 0.f;
     }
 }
