@@ -170,6 +170,34 @@ def time_single_runs(X, p, T, runs, gammas, seeds, out):
     return runs * T / (time.perf_counter() - t0), losses
 
 
+def measured_stream_ceiling(dev, gib=2, reps=5):
+    """Streaming ceilings measured on this GPU, to state beside the 8 TB/s
+    spec: a read-only pass (torch's sum over gib GiB of float32) and a device
+    copy of the same size (read + write), each the best of reps after a
+    warm-up, timed with HIP events on torch's stream."""
+    import torch
+    n = gib * (1 << 30) // 4
+    src = torch.ones(n, device=dev)
+    dst = torch.empty_like(src)
+    best = {}
+    for name, fn in (("read", lambda: src.sum()), ("copy", lambda: dst.copy_(src))):
+        fn()
+        ts = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn()
+            e1.record()
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1) / 1e3)
+        best[name] = min(ts)
+    del src, dst
+    torch.cuda.empty_cache()
+    nb = n * 4
+    return dict(read_gbs=round(nb / best["read"] / 1e9, 1), copy_gbs=round(2 * nb / best["copy"] / 1e9, 1),
+                bytes=nb, method=f"torch sum and copy over {gib} GiB of float32, best of {reps}")
+
+
 def plain_pass_roofline(X, p, T, label, traffic_path=None):
     """Pass durations of one eager single run (HIP events around each launch)
     and the B-pass HBM roofline: algorithmic bytes per launch / its mean
@@ -587,6 +615,15 @@ def main():
     if plain is not None and plain_large is not None:
         plain["roofline"] = plain_large
 
+    stream = measured_stream_ceiling(dev)
+    log(f"measured streaming ceilings: read {stream['read_gbs']} GB/s, copy {stream['copy_gbs']} GB/s")
+    ceiling = max(stream["read_gbs"], stream["copy_gbs"])
+    for rl in ([plain.get("roofline_urban"), plain.get("roofline")] if plain else []) + \
+            ([ragged] if ragged else []):
+        if rl is not None:
+            gbs = rl.get("achieved", rl.get("batched_gbs"))
+            rl["frac_of_measured_stream"] = round(gbs / ceiling, 4)
+
     line = {
         "metric": "EDAA run-iterations/sec + HBM GB/s; batched vs plain at equal loss",
         "value": round(value, 2),
@@ -605,6 +642,7 @@ def main():
                                f"Dirichlet(0.7) abundances, noise sigma 0.02",
                    "L": L, "N": N, "p": p, "M": M, "T": T, "K1": K1, "K2": K2, "launch_shape": plan},
         "hbm_gbs": round(step_bytes / (ms_per_step / 1e3) / 1e9, 1),
+        "hbm_measured": stream,
         "value_eager": round(value_eager, 2),
         "roofline": roofline,
         "error_vs_fp64": headline_err,
