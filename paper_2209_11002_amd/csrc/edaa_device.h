@@ -3104,6 +3104,121 @@ __global__ __launch_bounds__(kRedThreads) void k_reduce_b(Geom g, State s, int n
     __shared__ double scratch[4 * kRedThreads];
     reduce_b_rows<PP, R>(g, s, blockIdx.x, 1, blockIdx.y, need_w, scratch);
 }
+
+// The results of reduce_b_rows, bit for bit (every sum over the partials in
+// the same order), for up to kRedRows rows per workgroup: each thread keeps
+// the partials of its slice (at most kRedHeld of them) in registers, so the
+// column statistics and the factors f = exp(m_pg - M) are formed once for
+// all rows, and the rows' loads are issued together.
+constexpr int kRedRows = 4, kRedHeld = 16;
+template <int PP, int R>
+__device__ __forceinline__ void reduce_b_rows_f(const Geom& g, const State& s, int l0, int nl, int c, int need_w,
+                                                double* scratch) {
+    constexpr int QC = PP * R, KM = kRedHeld, NLM = kRedRows;
+    double* red = scratch;                                       // [NLM][kRedThreads]
+    double* Ss = scratch + NLM * kRedThreads;                    // [QC]
+    double* Ev = Ss + QC;                                        // [NLM][QC]
+    float* Ms = (float*)(Ev + NLM * QC);                         // [QC]
+    const int tid = threadIdx.x;
+    const int col0 = c * QC, L = g.L, npg = g.npg;
+    const int S = red_slices(npg, QC);
+    const bool act = tid < S * QC;
+    const int sl = tid / QC, o = tid % QC;
+    nl = min(nl, L - l0);
+    // this thread's partials pg = sl + k S: maxima, then factors and sums
+    float f[KM], sp[KM];
+    // (the loads are unconditional, from clamped indexes, so that they are
+    // issued together; the values past the partials are then replaced)
+#pragma unroll
+    for (int k = 0; k < KM; ++k) {
+        const int pg = sl + k * S;
+        const size_t at = (size_t)min(pg, npg - 1) * g.Qp + col0 + o;
+        const float mv = s.mpart[at], sv = s.spart[at];
+        const bool ok = act && pg < npg;
+        f[k] = ok ? mv : -INFINITY;
+        sp[k] = ok ? sv : 0.f;
+    }
+    float mx = -INFINITY;
+#pragma unroll
+    for (int k = 0; k < KM; ++k) mx = fmaxf(mx, f[k]);
+    red[tid] = (double)mx;
+    __syncthreads();
+    if (tid < QC) {
+        float t = -INFINITY;
+        for (int k = 0; k < S; ++k) t = fmaxf(t, (float)red[k * QC + tid]);
+        Ms[tid] = t;
+    }
+    __syncthreads();
+    const float mq = act ? Ms[o] : -INFINITY;
+    double sa = 0.0;
+#pragma unroll
+    for (int k = 0; k < KM; ++k) {
+        float fk = -1.f;                                         // -1: no weight
+        if (mq != -INFINITY && f[k] != -INFINITY) {
+            fk = expf(f[k] - mq);
+            sa += (double)sp[k] * (double)fk;
+        }
+        f[k] = fk;
+    }
+    // the rows' partials of X B, all loads issued before the first sum
+    float vv[NLM][KM];
+    const float* vp = s.Vpart + ((size_t)c * L + l0) * QC + o;
+    const size_t vstride = (size_t)g.nqc * L * QC;
+#pragma unroll
+    for (int r = 0; r < NLM; ++r)
+#pragma unroll
+        for (int k = 0; k < KM; ++k)
+            vv[r][k] = vp[(size_t)min(sl + k * S, npg - 1) * vstride + (size_t)min(r, nl - 1) * QC];
+    red[tid] = sa;
+    __syncthreads();
+    if (tid < QC) {
+        double t = 0.0;
+        for (int k = 0; k < S; ++k) t += red[k * QC + tid];
+        Ss[tid] = t;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < NLM; ++r) {
+        double ea = 0.0;
+#pragma unroll
+        for (int k = 0; k < KM; ++k)
+            if (f[k] >= 0.f) ea += (double)vv[r][k] * (double)f[k];
+        red[r * kRedThreads + tid] = ea;
+    }
+    __syncthreads();
+    for (int e = tid; e < nl * QC; e += kRedThreads) {
+        const int r = e / QC, q = e % QC, l = l0 + r, m = c * R + q / PP;
+        double t = 0.0;
+        for (int k = 0; k < S; ++k) t += red[r * kRedThreads + k * QC + q];
+        const double ev = (m < g.M) ? t / Ss[q] : 0.0;
+        Ev[e] = ev;
+        s.E[(size_t)l * g.Qp + col0 + q] = (float)ev;
+        s.Ed[(size_t)l * g.Qp + col0 + q] = ev;
+        if (l == 0 && m < g.M) {
+            s.colm[col0 + q] = Ms[q];
+            s.cols[col0 + q] = (float)Ss[q];
+        }
+    }
+    __syncthreads();
+    if (need_w)
+        for (int e = tid; e < nl * QC; e += kRedThreads) {
+            const int r = e / QC, q = e % QC, l = l0 + r, m = c * R + q / PP, ml = q / PP, j = q % PP;
+            double wv = 0.0;
+            if (m < g.M) {
+                wv = -s.XAtd[(size_t)l * g.Qp + col0 + q];
+                const double* aat = s.AAtd + (size_t)m * PP * PP;
+#pragma unroll
+                for (int k = 0; k < PP; ++k) wv = fma(Ev[r * QC + ml * PP + k], aat[k * PP + j], wv);
+            }
+            s.W[(size_t)l * g.Qp + col0 + q] = (float)wv;
+        }
+}
+
+template <int PP, int R>
+__global__ __launch_bounds__(kRedThreads) void k_reduce_b_f(Geom g, State s, int need_w, int nl) {
+    __shared__ double scratch[kRedRows * kRedThreads + (2 * kRedRows + 2) * 64];
+    reduce_b_rows_f<PP, R>(g, s, blockIdx.x * nl, nl, blockIdx.y, need_w, scratch);
+}
 template <int PP>
 __global__ __launch_bounds__(kRedThreads) void k_reduce_b_multi(const ImageJob* __restrict__ jobs,
                                                              const int2* __restrict__ map, int need_w) {

@@ -4,6 +4,8 @@
 // edaa::ops_p<p>() that returns the table pass_ops(p) hands out.
 #include "edaa_device.h"
 
+#include <algorithm>
+
 #ifndef EDAA_INST_P
 #error "compile with -DEDAA_INST_P=<p>"
 #endif
@@ -90,7 +92,16 @@ struct Kernels {
         return hipGetLastError();
     }
     static hipError_t reduce_b(const Geom& g, const State& s, int need_w, hipStream_t st) {
-        hipLaunchKernelGGL((k_reduce_b<PP, R>), dim3(g.L, g.nqc), dim3(kRedThreads), 0, st, g, s, need_w);
+        // several rows per workgroup (about one workgroup per CU) when each
+        // thread can hold the partials of its slice (red_slices)
+        const int QC = PP * R, S = std::max(1, std::min(kRedThreads / QC, (g.npg + 3) / 4));
+        if ((g.npg + S - 1) / S <= kRedHeld) {
+            const int nl = std::min(kRedRows, std::max(1, g.L * g.nqc / 256));
+            hipLaunchKernelGGL((k_reduce_b_f<PP, R>), dim3((g.L + nl - 1) / nl, g.nqc), dim3(kRedThreads), 0, st, g,
+                               s, need_w, nl);
+        } else {
+            hipLaunchKernelGGL((k_reduce_b<PP, R>), dim3(g.L, g.nqc), dim3(kRedThreads), 0, st, g, s, need_w);
+        }
         return hipGetLastError();
     }
     static hipError_t reduce_aa(const Geom& g, const State& s, int t, hipStream_t st) {
