@@ -2880,9 +2880,11 @@ __device__ __forceinline__ void sliced_sum(const float* __restrict__ src, size_t
     if (r < nr) {
         const float* sr = src + (size_t)r * rstride;
         for (int pg0 = sl; pg0 < npg; pg0 += 4 * S) {     // loads first, sums in the plain order
+            // (unconditional loads from clamped indexes, so that the four
+            // are issued together)
             float v[4];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) v[u] = pg0 + u * S < npg ? sr[(size_t)(pg0 + u * S) * stride + o] : 0.f;
+            for (int u = 0; u < 4; ++u) v[u] = sr[(size_t)min(pg0 + u * S, npg - 1) * stride + o];
 #pragma unroll
             for (int u = 0; u < 4; ++u)
                 if (pg0 + u * S < npg) acc += (double)v[u];
@@ -3022,7 +3024,8 @@ __device__ __forceinline__ void reduce_b_rows(const Geom& g, const State& s, int
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
                     const int pg = pg0 + u * S;
-                    v[u] = pg < g.npg ? s.mpart[(size_t)pg * g.Qp + col0 + o] : -INFINITY;
+                    const float mv = s.mpart[(size_t)min(pg, g.npg - 1) * g.Qp + col0 + o];
+                    v[u] = pg < g.npg ? mv : -INFINITY;
                 }
 #pragma unroll
                 for (int u = 0; u < U; ++u) mx = fmaxf(mx, v[u]);
@@ -3044,11 +3047,13 @@ __device__ __forceinline__ void reduce_b_rows(const Geom& g, const State& s, int
                 float mp[U], sp[U], vp[U];
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
-                    const int pg = pg0 + u * S;
+                    const int pg = pg0 + u * S, pgc = min(pg, g.npg - 1);
                     const bool ok = pg < g.npg;
-                    mp[u] = ok ? s.mpart[(size_t)pg * g.Qp + col0 + o] : -INFINITY;
-                    sp[u] = ok ? s.spart[(size_t)pg * g.Qp + col0 + o] : 0.f;
-                    vp[u] = ok ? s.Vpart[(((size_t)pg * g.nqc + c) * L + l) * QC + o] : 0.f;
+                    const float mv = s.mpart[(size_t)pgc * g.Qp + col0 + o], sv = s.spart[(size_t)pgc * g.Qp + col0 + o];
+                    const float vv = s.Vpart[(((size_t)pgc * g.nqc + c) * L + l) * QC + o];
+                    mp[u] = ok ? mv : -INFINITY;
+                    sp[u] = ok ? sv : 0.f;
+                    vp[u] = ok ? vv : 0.f;
                 }
 #pragma unroll
                 for (int u = 0; u < U; ++u) {

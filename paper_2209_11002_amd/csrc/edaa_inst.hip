@@ -92,11 +92,12 @@ struct Kernels {
         return hipGetLastError();
     }
     static hipError_t reduce_b(const Geom& g, const State& s, int need_w, hipStream_t st) {
-        // several rows per workgroup (about one workgroup per CU) when each
-        // thread can hold the partials of its slice (red_slices)
+        // several rows per workgroup (about one workgroup per CU) when there
+        // are rows enough and each thread can hold the partials of its slice
+        // (red_slices); otherwise one row per workgroup
         const int QC = PP * R, S = std::max(1, std::min(kRedThreads / QC, (g.npg + 3) / 4));
-        if ((g.npg + S - 1) / S <= kRedHeld) {
-            const int nl = std::min(kRedRows, std::max(1, g.L * g.nqc / 256));
+        const int nl = std::min(kRedRows, std::max(1, g.L * g.nqc / 256));
+        if (nl > 1 && (g.npg + S - 1) / S <= kRedHeld) {
             hipLaunchKernelGGL((k_reduce_b_f<PP, R>), dim3((g.L + nl - 1) / nl, g.nqc), dim3(kRedThreads), 0, st, g,
                                s, need_w, nl);
         } else {
