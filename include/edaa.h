@@ -143,6 +143,11 @@ void edaa_destroy(edaa_ctx* ctx);
 /* Message of the last error on the calling thread ("" if none). */
 const char* edaa_last_error(void);
 
+/* Environment: EDAA_TUNE_CACHE (see edaa_autotune); EDAA_REDUCE_ROWS = 1..4
+ * sets the rows of X B each workgroup of the B-step reduction forms (by
+ * default four where a chunk's rows outnumber the CUs, else one; every
+ * choice gives the same bits). */
+
 /* The launch shape edaa_fit (M = 1) or edaa_ensemble (M runs) would use for
  * an L x N image with p endmembers under params (its runs_per_chunk and
  * pixel_groups requests, else a tuned shape, else the default).  Pure host

@@ -5,6 +5,7 @@
 #include "edaa_device.h"
 
 #include <algorithm>
+#include <cstdlib>
 
 #ifndef EDAA_INST_P
 #error "compile with -DEDAA_INST_P=<p>"
@@ -95,8 +96,11 @@ struct Kernels {
         // several rows per workgroup (about one workgroup per CU) when there
         // are rows enough and each thread can hold the partials of its slice
         // (red_slices); otherwise one row per workgroup
+        // EDAA_REDUCE_ROWS (1 .. kRedRows) overrides the rows per workgroup
         const int QC = PP * R, S = std::max(1, std::min(kRedThreads / QC, (g.npg + 3) / 4));
-        const int nl = std::min(kRedRows, std::max(1, g.L * g.nqc / 256));
+        const char* env = std::getenv("EDAA_REDUCE_ROWS");
+        const int want = env ? std::atoi(env) : 0;
+        const int nl = want > 0 ? std::min(kRedRows, want) : std::min(kRedRows, std::max(1, g.L * g.nqc / 256));
         if (nl > 1 && (g.npg + S - 1) / S <= kRedHeld) {
             hipLaunchKernelGGL((k_reduce_b_f<PP, R>), dim3((g.L + nl - 1) / nl, g.nqc), dim3(kRedThreads), 0, st, g,
                                s, need_w, nl);

@@ -151,6 +151,28 @@ def test_ensemble_equals_single_runs(api):
 
 
 @gpu
+@pytest.mark.parametrize("L,N,p,M", [(224, 3000, 6, 24), (162, 5000, 4, 40), (300, 1200, 3, 30)])
+def test_row_shared_reduction_gives_the_same_bits(api, monkeypatch, L, N, p, M):
+    """The B-step reduction with several rows per workgroup (partials held
+    in registers, column statistics formed once) sums in the same order as
+    the one-row form, so the whole ensemble is bit-identical with either
+    (EDAA_REDUCE_ROWS selects the rows per workgroup)."""
+    _say(f"row-shared reduction L={L} N={N} p={p} M={M}")
+    s = synth.small_case(seed=33 + L, L=L, N=N, p=p)
+    Xg, _ = _prep(s.X)
+    seeds = [m // 3 for m in range(M)]
+    gammas = [(0.5, 1.0, 2.0)[m % 3] for m in range(M)]
+    out = {}
+    for rows in ("1", "2", "4"):
+        monkeypatch.setenv("EDAA_REDUCE_ROWS", rows)
+        out[rows] = api.ensemble(Xg, p, seeds, gammas, T=4)
+    for rows in ("2", "4"):
+        assert np.array_equal(out[rows]["loss"], out["1"]["loss"]), rows
+        for k in ("A", "B", "E"):
+            assert torch.equal(out[rows][k], out["1"][k]), (rows, k)
+
+
+@gpu
 def test_ensemble_coherence_modes_and_graph(api):
     _say("ensemble raw coherence + graph replay")
     s = synth.small_case(seed=32, L=30, N=300, p=3)
