@@ -159,7 +159,8 @@ edaa_status edaa_plan(int L, int N, int p, int M, const edaa_params* params, eda
  * of p endmembers on X [L][N] (device, params->x_dtype): every compiled
  * runs-per-chunk size that fits, each with half, the default and twice the
  * default pixel groups (multiples of 8, which keep the workgroups sharing an
- * X tile on one XCD); each candidate runs T = 2 and T = 6 outer iterations
+ * X tile on one XCD) and the count that gives one workgroup per CU; each
+ * candidate runs T = 2 and T = 6 outer iterations
  * (K1, K2 from params, seeds 0..M-1, gamma params->gamma) twice after a
  * warm-up, and scores the difference of the best times.  The fastest shape is recorded for the
  * problem's class (L, p, M, x_dtype and ceil(log2(ceil(N / 64)))): later
