@@ -1307,8 +1307,8 @@ edaa_status edaa_autotune(edaa_ctx* ctx, const void* X, int L, int N, int p, int
     EDAA_REQUIRE(X != nullptr, "X must not be null");
     // candidate shapes: every compiled chunk size that fits (one run per
     // chunk only for single runs), each with half, the default and twice
-    // the default pixel groups, and the count that gives one workgroup per
-    // CU over all chunks (the pass kernels hold one per CU at a time)
+    // the default pixel groups rounded to multiples of 8, and the default
+    // itself (one workgroup per CU over all chunks, not rounded)
     std::vector<std::pair<int, int>> cand;
     int rc[4] = {0, 0, 0, 0};
     const int nr = run_choices(p, rc);
@@ -1322,7 +1322,7 @@ edaa_status edaa_autotune(edaa_ctx* ctx, const void* X, int L, int N, int p, int
         for (int f : {1, 2, 4, 0}) {
             int npg = base * f / 2;
             if (npg >= 8) npg &= ~7;
-            if (f == 0) npg = kTargetWorkgroups / 2 / g0.nqc;     // one workgroup per CU, not rounded
+            if (f == 0) npg = kTargetWorkgroups / g0.nqc;     // one workgroup per CU, not rounded
             npg = std::max(1, std::min(npg, (N + kTile - 1) / kTile));
             bool dup = false;
             for (auto& c : cand) dup |= (c.first == R && c.second == npg);

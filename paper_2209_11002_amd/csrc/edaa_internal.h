@@ -16,7 +16,7 @@ constexpr int kTile = 64;
 constexpr int kThreads = 256;
 constexpr int kMaxL = 448;
 constexpr int kMaxP = 16;
-constexpr int kTargetWorkgroups = 512;   // 2 per CU on 256 CUs
+constexpr int kTargetWorkgroups = 256;   // default pass grid: one workgroup per CU (256 CUs)
 constexpr int kPadRows = 17;             // zero rows after the L rows of E and W
 
 enum PassMode { kModeStep = 0, kModeInitRng = 1, kModeInitB0 = 2 };
