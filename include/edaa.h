@@ -175,7 +175,7 @@ edaa_status edaa_autotune(edaa_ctx* ctx, const void* X, int L, int N, int p, int
                           const edaa_params* params, edaa_launch_plan* best, double* best_us);
 
 /* The same for a ragged batch: tiles per work item of the persistent kernel
- * (1, 2, 4, 8, 16 or 32), timed on the batch itself (the images' outputs are
+ * (1, 2, 4, ..., 128), timed on the batch itself (the images' outputs are
  * overwritten), recorded for the batch's class (image count,
  * ceil(log2(total tiles)), largest p, x_dtype) and used by later
  * edaa_fit_ragged calls of that class with params->tiles_per_item = 0. */

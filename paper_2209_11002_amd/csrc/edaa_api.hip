@@ -1395,7 +1395,7 @@ edaa_status edaa_autotune_ragged(edaa_ctx* ctx, int n_images, edaa_image_desc* i
     P.flags &= ~(EDAA_FLAG_GRAPH | EDAA_FLAG_TIME_PASSES | EDAA_FLAG_RAGGED_GROUPED);
     double bus = -1.0;
     int bt = kDefaultTilesPerItem;
-    for (int tpi : {1, 2, 4, 8, 16, 32}) {
+    for (int tpi : {1, 2, 4, 8, 16, 32, 64, 128}) {
         P.tiles_per_item = tpi;
         double t[2] = {1e30, 1e30};
         for (int rep = 0; rep < 5; ++rep) {
