@@ -1315,8 +1315,6 @@ edaa_status edaa_autotune(edaa_ctx* ctx, const void* X, int L, int N, int p, int
     for (int i = 0; i < nr; ++i) {
         const int R = rc[i];
         if (!runs_fit(p, R, L) || (M == 1) != (R == 1)) continue;
-        // (multiples of 8 keep the chunks of a pixel group on one XCD, see
-        // wg_coords, so their shared X tiles stay in that XCD's L2)
         const Geom g0 = make_geom(L, N, M, p, R, 0);
         const int base = g0.npg;
         for (int f : {1, 2, 4, 0}) {

@@ -172,18 +172,23 @@ __device__ __forceinline__ float uniform_u(uint64_t seed, int i, int j) {
 }
 
 // Workgroup -> (pixel group, chunk).  Blocks are dispatched round-robin over
-// the 8 XCDs (block b runs on XCD b % 8); all chunks of one pixel group are
-// placed on one XCD, at consecutive dispatch slots, so they share the X tiles
-// in that XCD's L2.
+// the 8 XCDs (block b runs on XCD b % 8).  XCD x takes a contiguous range of
+// the (pixel group, chunk) pairs in pixel-group-major order, so the chunks of
+// a pixel group run on one XCD (at most one pixel group per XCD boundary is
+// split over two) and share the X tiles in that XCD's L2, whatever the
+// number of pixel groups.  A single chunk keeps pg = b.
 __device__ __forceinline__ void wg_coords(const Geom& g, int b, int& pg, int& c) {
-    if ((g.npg & 7) == 0) {
-        const int xcd = b & 7, k = b >> 3;
-        c = k % g.nqc;
-        pg = (k / g.nqc) * 8 + xcd;
-    } else {
-        c = b % g.nqc;
-        pg = b / g.nqc;
+    if (g.nqc == 1) {
+        pg = b;
+        c = 0;
+        return;
     }
+    const int total = g.npg * g.nqc, x = b & 7;
+    int off = 0;                                   // pairs of the XCDs before x
+    for (int y = 0; y < x; ++y) off += (total - y + 7) >> 3;
+    const int i = off + (b >> 3);
+    pg = i / g.nqc;
+    c = i - pg * g.nqc;
 }
 
 // X tile staging.  X here is the library's padded copy, [L][ldx] with
