@@ -1280,6 +1280,18 @@ __device__ __forceinline__ void bpass_body(const Geom& g, const State& s, int bi
     for (int jb = 0; jb < NRBW; ++jb)
 #pragma unroll
         for (int cb = 0; cb < NCB; ++cb) acc[jb][cb] = d4{0.0, 0.0, 0.0, 0.0};
+    // single runs up to p = 4: X w^T on the vector ALU instead of 16-column
+    // matrix blocks (p of 16 columns useful; measured faster at p = 3 and 4,
+    // slower at p = 6).  Thread (row vl, pixel half vh) owns bands vl and
+    // vl + 256 and sums its 32 pixels of the tile in float32, folded into
+    // float64 per tile like the matrix-core sums.
+    constexpr bool VACC = (R == 1 && PP <= 4);
+    const int vl = tid & 255, vh = tid >> 8;
+    double vacc[2][VACC ? PP : 1];
+#pragma unroll
+    for (int r = 0; r < 2; ++r)
+#pragma unroll
+        for (int j = 0; j < (VACC ? PP : 1); ++j) vacc[r][j] = 0.0;
 
     // Pipeline: the X tile and this thread's B segment and shift (registers)
     // of tile t + npg are requested while tile t is processed.
@@ -1406,7 +1418,42 @@ __device__ __forceinline__ void bpass_body(const Geom& g, const State& s, int bi
             }
         }
         lds_barrier();
-        mfma_accumulate<NCB, NRBW, WTS, true, 1, true, NW>(acc, gdummy, false, Xs, Wq, F, FG, nrb, w, lane);
+        if constexpr (VACC) {
+            float fq[PP], gq[PP];
+#pragma unroll
+            for (int j = 0; j < PP; ++j) {
+                fq[j] = F[j];
+                gq[j] = FG[j];
+            }
+#pragma unroll
+            for (int r = 0; r < 2; ++r) {
+                const int l = vl + 256 * r;
+                if (l < L) {
+                    float t[PP];
+#pragma unroll
+                    for (int j = 0; j < PP; ++j) t[j] = 0.f;
+                    const float* xr = Xs + l * kXS + 32 * vh;
+                    const float* wr = Wq + 32 * vh;
+#pragma unroll
+                    for (int k = 0; k < 8; ++k) {
+                        const f4 xv = *(const f4*)(xr + 4 * k);
+#pragma unroll
+                        for (int j = 0; j < PP; ++j) {
+                            const f4 wv = *(const f4*)(wr + j * kXS + 4 * k);
+                            t[j] = fmaf(xv[0], wv[0], t[j]);
+                            t[j] = fmaf(xv[1], wv[1], t[j]);
+                            t[j] = fmaf(xv[2], wv[2], t[j]);
+                            t[j] = fmaf(xv[3], wv[3], t[j]);
+                        }
+                    }
+#pragma unroll
+                    for (int j = 0; j < PP; ++j)
+                        vacc[r][j] = fma(vacc[r][j], (double)fq[j], (double)t[j] * (double)gq[j]);
+                }
+            }
+        } else {
+            mfma_accumulate<NCB, NRBW, WTS, true, 1, true, NW>(acc, gdummy, false, Xs, Wq, F, FG, nrb, w, lane);
+        }
         if (nt < g.ntiles && (regx || dma)) {
             if (!g.dbuf) lds_barrier();           // single buffer: overwrite after every reader
             if (regx)
@@ -1417,7 +1464,29 @@ __device__ __forceinline__ void bpass_body(const Geom& g, const State& s, int bi
     }
 
     const size_t wgi = (size_t)pg * g.nqc + c;
-    store_acc<NCB, NRBW, QC, NW>(acc, s.Vpart + wgi * (size_t)L * QC, L, nrb, w, lane);
+    if constexpr (VACC) {
+        // the two pixel halves of a band, added in a fixed order
+        __syncthreads();                           // every wave is done with the X tiles
+        double* hx = (double*)(smem + xo[0]);      // [L][PP]: L * PP * 8 <= L * kXS * 4 bytes
+        float* Vp = s.Vpart + wgi * (size_t)L * QC;
+        if (vh == 1)
+#pragma unroll
+            for (int r = 0; r < 2; ++r)
+                if (vl + 256 * r < L)
+#pragma unroll
+                    for (int j = 0; j < PP; ++j) hx[(vl + 256 * r) * PP + j] = vacc[r][j];
+        __syncthreads();
+        if (vh == 0)
+#pragma unroll
+            for (int r = 0; r < 2; ++r) {
+                const int l = vl + 256 * r;
+                if (l < L)
+#pragma unroll
+                    for (int j = 0; j < PP; ++j) Vp[(size_t)l * QC + j] = (float)(vacc[r][j] + hx[l * PP + j]);
+            }
+    } else {
+        store_acc<NCB, NRBW, QC, NW>(acc, s.Vpart + wgi * (size_t)L * QC, L, nrb, w, lane);
+    }
     if (qin && sub == 0) {
         s.mpart[(size_t)pg * g.Qp + col0 + sq] = cok ? mrun : -INFINITY;
         s.spart[(size_t)pg * g.Qp + col0 + sq] = cok ? (float)srun : 0.f;
