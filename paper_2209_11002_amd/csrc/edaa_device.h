@@ -2025,17 +2025,20 @@ __device__ __forceinline__ void xs_accumulate(d4 (&acc)[NRBW][NCB], const float*
     for (int j = 0; j < NRBW; ++j)
 #pragma unroll
         for (int cb = 0; cb < NCB; ++cb) t[j][cb] = f4{0.f, 0.f, 0.f, 0.f};
+    // Row blocks in groups of JG (the split X operands of a group are live
+    // together: 20 registers per row block), column blocks in groups of CG.
+    // A group's JN valid row blocks take both pixel halves in one branch-free
+    // stretch of code, so the split of one half can be scheduled between the
+    // other half's matrix products.
+    auto group = [&](auto jn, int j0) {
+        constexpr int JN = decltype(jn)::value;
 #pragma unroll
-    for (int pk = 0; pk < 2; ++pk) {
-        u32x4 xa[JG][3];
-        // row blocks in groups of JG (the split X operands of a group are live
-        // together: 20 registers per row block), column blocks in groups of CG
+        for (int pk = 0; pk < 2; ++pk) {
+            u32x4 xa[JN][3];
+            float xv[JN][8];
 #pragma unroll
-        for (int j0 = 0; j0 < NRBW; j0 += JG) {
-            float xv[JG][8];
-#pragma unroll
-            for (int jj = 0; jj < JG; ++jj) {
-                const float* xp = Xf + (16 * min(w + NW * (j0 + jj), nrb - 1) + m) * kXS + 32 * pk + 8 * kg;
+            for (int jj = 0; jj < JN; ++jj) {
+                const float* xp = Xf + (16 * (w + NW * (j0 + jj)) + m) * kXS + 32 * pk + 8 * kg;
                 const f4 a = *(const f4*)xp, b = *(const f4*)(xp + 4);
 #pragma unroll
                 for (int e = 0; e < 4; ++e) {
@@ -2044,7 +2047,7 @@ __device__ __forceinline__ void xs_accumulate(d4 (&acc)[NRBW][NCB], const float*
                 }
             }
 #pragma unroll
-            for (int jj = 0; jj < JG; ++jj) split8_bf16x3(xv[jj], xa[jj]);
+            for (int jj = 0; jj < JN; ++jj) split8_bf16x3(xv[jj], xa[jj]);
 #pragma unroll
             for (int c0 = 0; c0 < NCB; c0 += CG) {
                 u32x4 bop[CG][3];
@@ -2056,16 +2059,19 @@ __device__ __forceinline__ void xs_accumulate(d4 (&acc)[NRBW][NCB], const float*
 #pragma unroll
                 for (int u = 0; u < 6; ++u)
 #pragma unroll
-                    for (int jj = 0; jj < JG; ++jj) {
-                        if (w + NW * (j0 + jj) < nrb) {
+                    for (int jj = 0; jj < JN; ++jj)
 #pragma unroll
-                            for (int cc = 0; cc < CG; ++cc)
-                                t[j0 + jj][c0 + cc] =
-                                    mfma16_bf16(xa[jj][x6a(u)], bop[cc][x6b(u)], t[j0 + jj][c0 + cc]);
-                        }
-                    }
+                        for (int cc = 0; cc < CG; ++cc)
+                            t[j0 + jj][c0 + cc] = mfma16_bf16(xa[jj][x6a(u)], bop[cc][x6b(u)], t[j0 + jj][c0 + cc]);
             }
         }
+    };
+#pragma unroll
+    for (int j0 = 0; j0 < NRBW; j0 += JG) {
+        if (JG == 2 && w + NW * (j0 + 1) < nrb)
+            group(std::integral_constant<int, JG>{}, j0);
+        else if (w + NW * j0 < nrb)
+            group(std::integral_constant<int, 1>{}, j0);
     }
     float fs[NCB], gs[NCB];
     if (SCALE) {
