@@ -3196,10 +3196,11 @@ __global__ __launch_bounds__(kRedThreads) void k_reduce_b(Geom g, State s, int n
 // column statistics and the factors f = exp(m_pg - M) are formed once for
 // all rows, and the rows' loads are issued together.
 constexpr int kRedRows = 4, kRedHeld = 16;
-template <int PP, int R>
+template <int PP, int R, int KM>
 __device__ __forceinline__ void reduce_b_rows_f(const Geom& g, const State& s, int l0, int nl, int c, int need_w,
                                                 double* scratch) {
-    constexpr int QC = PP * R, KM = kRedHeld, NLM = kRedRows;
+    constexpr int QC = PP * R, NLM = kRedRows;
+    static_assert(KM <= kRedHeld, "partials held per thread");
     double* red = scratch;                                       // [NLM][kRedThreads]
     double* Ss = scratch + NLM * kRedThreads;                    // [QC]
     double* Ev = Ss + QC;                                        // [NLM][QC]
@@ -3299,10 +3300,11 @@ __device__ __forceinline__ void reduce_b_rows_f(const Geom& g, const State& s, i
         }
 }
 
-template <int PP, int R>
+// KM: partials held per thread, at least ceil(npg / red_slices(npg, QC))
+template <int PP, int R, int KM>
 __global__ __launch_bounds__(kRedThreads) void k_reduce_b_f(Geom g, State s, int need_w, int nl) {
     __shared__ double scratch[kRedRows * kRedThreads + (2 * kRedRows + 2) * 64];
-    reduce_b_rows_f<PP, R>(g, s, blockIdx.x * nl, nl, blockIdx.y, need_w, scratch);
+    reduce_b_rows_f<PP, R, KM>(g, s, blockIdx.x * nl, nl, blockIdx.y, need_w, scratch);
 }
 template <int PP>
 __global__ __launch_bounds__(kRedThreads) void k_reduce_b_multi(const ImageJob* __restrict__ jobs,

@@ -101,9 +101,14 @@ struct Kernels {
         const char* env = std::getenv("EDAA_REDUCE_ROWS");
         const int want = env ? std::atoi(env) : 0;
         const int nl = want > 0 ? std::min(kRedRows, want) : std::min(kRedRows, std::max(1, g.L * g.nqc / 256));
-        if (nl > 1 && (g.npg + S - 1) / S <= kRedHeld) {
-            hipLaunchKernelGGL((k_reduce_b_f<PP, R>), dim3((g.L + nl - 1) / nl, g.nqc), dim3(kRedThreads), 0, st, g,
-                               s, need_w, nl);
+        const int held = (g.npg + S - 1) / S;   // partials per thread
+        const dim3 grid((g.L + nl - 1) / nl, g.nqc);
+        if (nl > 1 && held <= 4) {
+            hipLaunchKernelGGL((k_reduce_b_f<PP, R, 4>), grid, dim3(kRedThreads), 0, st, g, s, need_w, nl);
+        } else if (nl > 1 && held <= 8) {
+            hipLaunchKernelGGL((k_reduce_b_f<PP, R, 8>), grid, dim3(kRedThreads), 0, st, g, s, need_w, nl);
+        } else if (nl > 1 && held <= kRedHeld) {
+            hipLaunchKernelGGL((k_reduce_b_f<PP, R, kRedHeld>), grid, dim3(kRedThreads), 0, st, g, s, need_w, nl);
         } else {
             hipLaunchKernelGGL((k_reduce_b<PP, R>), dim3(g.L, g.nqc), dim3(kRedThreads), 0, st, g, s, need_w);
         }
